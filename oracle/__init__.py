@@ -1,0 +1,292 @@
+"""Plain CPU oracle for one optimisation step of a 3D Gaussian map.
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` are its only users. It shares no code with the HIP
+library and never loads it; the product path never imports this package.
+
+The arithmetic lives in ``gs_oracle.cpp`` (FP64, with an FP32 key path for the
+bit-exact tile keys); this module only marshals numpy arrays through ctypes and
+composes the per-view steps in the paper's order:
+
+    project (Sec. III-A, Eq. 1-3) -> emit (tile, Gaussian) pairs for tiles the footprint
+    reaches (Sec. III-D.2) -> stable sort by (tile, depth) (Sec. III-A) -> per-tile ranges
+    -> blend front to back with exposure (Eq. 5, Sec. III-C.3) -> loss (Eq. 9)
+    -> adjoint -> sparse Adam (Sec. III-D.2, Sec. IV-A.1).
+
+Cameras are ``float64[16]`` = R_cw row-major (9), t_cw (3), fx, fy, cx, cy. Parameter rows
+are ``float64[N, 11 + 3K]`` = mean (3), log-scale (3), quaternion wxyz (4), opacity logit
+(1), SH [k][channel] (3K), K = (deg + 1)^2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.cpp")
+_LIB = os.path.join(_HERE, "libgs_oracle.so")
+
+NEAR_Z = 0.2
+TILE = 16
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (FP32 key path needs -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = ctypes.CDLL(_LIB)
+        _lib.or_loss.restype = ctypes.c_double
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def n_sh(deg: int) -> int:
+    return (deg + 1) * (deg + 1)
+
+
+def n_floats(deg: int) -> int:
+    return 11 + 3 * n_sh(deg)
+
+
+@dataclass
+class OView:
+    """One camera of a step: pose, intrinsics, size, exposure [A|b] (3x4) and background."""
+    cam: np.ndarray          # float64[16]
+    W: int
+    H: int
+    E: np.ndarray = field(default_factory=lambda: np.concatenate(
+        [np.eye(3), np.zeros((3, 1))], axis=1).reshape(12))
+    bg: np.ndarray = field(default_factory=lambda: np.zeros(3))
+
+    @property
+    def tiles_x(self):
+        return (self.W + TILE - 1) // TILE
+
+    @property
+    def tiles_y(self):
+        return (self.H + TILE - 1) // TILE
+
+    @property
+    def n_tiles(self):
+        return self.tiles_x * self.tiles_y
+
+
+def project(params, deg, view: OView, fp64=False, near=NEAR_Z):
+    """Per-Gaussian projection (Eq. 1-3), culls and tile counts for one view."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    N = params.shape[0]
+    assert params.shape[1] == n_floats(deg)
+    cam = np.ascontiguousarray(view.cam, dtype=np.float64)
+    out = dict(
+        visible=np.zeros(N, np.uint8), depth_bits=np.zeros(N, np.uint32),
+        depth=np.zeros(N), mean2d=np.zeros((N, 2)), conic=np.zeros((N, 3)),
+        opacity=np.zeros(N), thr=np.zeros(N), cov2d=np.zeros((N, 3)),
+        colour=np.zeros((N, 3)), rect=np.zeros((N, 4), np.int32), count=np.zeros(N, np.int32))
+    lib().or_project(ctypes.c_int(N), ctypes.c_int(deg), _p(params), _p(cam),
+                     ctypes.c_int(view.W), ctypes.c_int(view.H), ctypes.c_double(near),
+                     ctypes.c_int(1 if fp64 else 0),
+                     _p(out["visible"]), _p(out["depth_bits"]), _p(out["depth"]),
+                     _p(out["mean2d"]), _p(out["conic"]), _p(out["opacity"]), _p(out["thr"]),
+                     _p(out["cov2d"]), _p(out["colour"]), _p(out["rect"]), _p(out["count"]))
+    return out
+
+
+def bin_views(projs, views, fp64=False):
+    """Emit, stable-sort and range the (tile, Gaussian) instances of several views whose
+    tiles are numbered consecutively (view 0's tiles first)."""
+    tile_chunks, val_chunks, depth_cat, bits_cat = [], [], [], []
+    base, n_total_g = 0, 0
+    for pr, v in zip(projs, views):
+        N = pr["count"].shape[0]
+        counts = pr["count"].astype(np.int64)
+        offs = np.zeros(N, np.int64)
+        if N > 1:
+            offs[1:] = np.cumsum(counts)[:-1]
+        n = int(counts.sum())
+        tiles = np.zeros(n, np.int64)
+        vals = np.zeros(n, np.uint32)
+        lib().or_emit(ctypes.c_int(N), ctypes.c_int(v.W), ctypes.c_int(v.H), ctypes.c_int64(base),
+                      ctypes.c_int(1 if fp64 else 0), _p(pr["rect"]), _p(pr["count"]),
+                      _p(pr["mean2d"]), _p(pr["conic"]), _p(pr["thr"]), _p(offs), _p(tiles),
+                      _p(vals))
+        tile_chunks.append(tiles)
+        # values index the concatenation of all views' per-Gaussian arrays
+        val_chunks.append(vals.astype(np.uint64) + n_total_g)
+        depth_cat.append(pr["depth"])
+        bits_cat.append(pr["depth_bits"])
+        base += v.n_tiles
+        n_total_g += N
+    tiles = np.concatenate(tile_chunks) if tile_chunks else np.zeros(0, np.int64)
+    vals_g = np.concatenate(val_chunks).astype(np.uint32) if val_chunks else np.zeros(0, np.uint32)
+    depth = np.ascontiguousarray(np.concatenate(depth_cat))
+    bits = np.ascontiguousarray(np.concatenate(bits_cat))
+    n = tiles.shape[0]
+    ts = np.zeros(n, np.int64)
+    vs = np.zeros(n, np.uint32)
+    ks = np.zeros(n, np.uint64)
+    lib().or_sort(ctypes.c_int64(n), _p(tiles), _p(vals_g), _p(depth), _p(bits), _p(ts), _p(vs),
+                  _p(ks) if not fp64 else None)
+    ranges = np.zeros((base, 2), np.int64)
+    lib().or_ranges(ctypes.c_int64(n), _p(ts), ctypes.c_int64(base), _p(ranges))
+    # local Gaussian index (the product path stores the Gaussian index, not the view's)
+    Ns = [pr["count"].shape[0] for pr in projs]
+    view_of = np.repeat(np.arange(len(views)), [v.n_tiles for v in views])
+    starts = np.concatenate([[0], np.cumsum(Ns)[:-1]]).astype(np.int64)
+    local = (vs.astype(np.int64) - starts[view_of[ts]]).astype(np.uint32) if n else vs
+    return dict(tile=ts, val=vs, local_val=local, key=ks if not fp64 else None, ranges=ranges,
+                n_tiles=base)
+
+
+def _cat(projs, name):
+    return np.ascontiguousarray(np.concatenate([p[name] for p in projs]))
+
+
+def render(projs, views, bins, tie_alpha=0.0, tie_T=0.0):
+    """Tiled blend of every view. Returns per-view dicts with out (3,H,W), pre, T_final,
+    n_contrib and tie flags."""
+    mean2d, conic = _cat(projs, "mean2d"), _cat(projs, "conic")
+    opac, colour = _cat(projs, "opacity"), _cat(projs, "colour")
+    res, base = [], 0
+    for v in views:
+        P = v.W * v.H
+        out, pre = np.zeros(3 * P), np.zeros(3 * P)
+        Tf, nc, tie = np.zeros(P), np.zeros(P, np.int32), np.zeros(P, np.int32)
+        ncon, sig = np.zeros(P, np.int32), np.zeros(P, np.uint64)
+        E = np.ascontiguousarray(v.E, dtype=np.float64)
+        bg = np.ascontiguousarray(v.bg, dtype=np.float64)
+        lib().or_render_tiled(ctypes.c_int(v.W), ctypes.c_int(v.H), ctypes.c_int64(base),
+                              _p(bins["ranges"]), _p(bins["val"]), _p(mean2d), _p(conic),
+                              _p(opac), _p(colour), _p(E), _p(bg), ctypes.c_double(tie_alpha),
+                              ctypes.c_double(tie_T), _p(out), _p(pre), _p(Tf), _p(nc), _p(tie),
+                              _p(ncon), _p(sig))
+        res.append(dict(out=out.reshape(3, v.H, v.W), pre=pre.reshape(3, v.H, v.W),
+                        T_final=Tf.reshape(v.H, v.W), n_contrib=nc.reshape(v.H, v.W),
+                        tie=tie.reshape(v.H, v.W), n_contributors=ncon.reshape(v.H, v.W),
+                        signature=sig.reshape(v.H, v.W)))
+        base += v.n_tiles
+    return res
+
+
+def render_brute(proj, view: OView):
+    """Per-pixel blend over all visible Gaussians in (depth, index) order; no tiles."""
+    N = proj["count"].shape[0]
+    P = view.W * view.H
+    out, Tf, nc = np.zeros(3 * P), np.zeros(P), np.zeros(P, np.int32)
+    E = np.ascontiguousarray(view.E, dtype=np.float64)
+    bg = np.ascontiguousarray(view.bg, dtype=np.float64)
+    lib().or_render_brute(ctypes.c_int(N), ctypes.c_int(view.W), ctypes.c_int(view.H),
+                          _p(proj["visible"]), _p(proj["depth"]), _p(proj["mean2d"]),
+                          _p(proj["conic"]), _p(proj["opacity"]), _p(proj["colour"]), _p(E),
+                          _p(bg), _p(out), _p(Tf), _p(nc))
+    return dict(out=out.reshape(3, view.H, view.W), T_final=Tf.reshape(view.H, view.W),
+                n_contributors=nc.reshape(view.H, view.W))
+
+
+def loss(out, gt, lam):
+    """Eq. 9: (1 - lam) mean|out - gt| + lam (1 - mean SSIM); returns (L, dL/dout, ssim)."""
+    out = np.ascontiguousarray(out, dtype=np.float64)
+    gt = np.ascontiguousarray(gt, dtype=np.float64)
+    _, H, W = out.shape
+    g = np.zeros_like(out)
+    ss = ctypes.c_double(0.0)
+    L = lib().or_loss(ctypes.c_int(H), ctypes.c_int(W), _p(out), _p(gt), ctypes.c_double(lam),
+                      _p(g), ctypes.byref(ss))
+    return float(L), g, float(ss.value)
+
+
+def blend_backward(projs, views, bins, gouts, tie_alpha=0.0, tie_T=0.0):
+    """Adjoint of the blend: per view, per Gaussian (mean2d 2, conic 3, opacity, colour 3)
+    gradients, exposure gradients (12) and tie flags."""
+    mean2d, conic = _cat(projs, "mean2d"), _cat(projs, "conic")
+    opac, colour = _cat(projs, "opacity"), _cat(projs, "colour")
+    Ntot = mean2d.shape[0]
+    g2d = np.zeros((Ntot, 9))
+    gtie = np.zeros(Ntot, np.uint8)
+    gEs, base = [], 0
+    for v, go in zip(views, gouts):
+        gE = np.zeros(12)
+        E = np.ascontiguousarray(v.E, dtype=np.float64)
+        bg = np.ascontiguousarray(v.bg, dtype=np.float64)
+        go = np.ascontiguousarray(go, dtype=np.float64).reshape(-1)
+        lib().or_blend_backward(ctypes.c_int(v.W), ctypes.c_int(v.H), ctypes.c_int64(base),
+                                _p(bins["ranges"]), _p(bins["val"]), _p(mean2d), _p(conic),
+                                _p(opac), _p(colour), _p(E), _p(bg), ctypes.c_double(tie_alpha),
+                                ctypes.c_double(tie_T), _p(go), _p(g2d), _p(gE), _p(gtie))
+        gEs.append(gE)
+        base += v.n_tiles
+    Ns = [p["count"].shape[0] for p in projs]
+    splits = np.cumsum(Ns)[:-1]
+    return np.split(g2d, splits), gEs, np.split(gtie, splits)
+
+
+def project_backward(params, deg, view: OView, visible, g2d, near=NEAR_Z):
+    """Chain rule from one view's 2D gradients to the parameter rows (FP64)."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    N = params.shape[0]
+    gp = np.zeros_like(params)
+    cam = np.ascontiguousarray(view.cam, dtype=np.float64)
+    g2d = np.ascontiguousarray(g2d, dtype=np.float64)
+    vis = np.ascontiguousarray(visible, dtype=np.uint8)
+    lib().or_project_backward(ctypes.c_int(N), ctypes.c_int(deg), _p(params), _p(cam),
+                              ctypes.c_int(view.W), ctypes.c_int(view.H), ctypes.c_double(near),
+                              _p(vis), _p(g2d), _p(gp))
+    return gp
+
+
+def sh_basis(deg, dirs):
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+    Y = np.zeros((dirs.shape[0], n_sh(deg)))
+    lib().or_sh_basis(ctypes.c_int(deg), ctypes.c_int(dirs.shape[0]), _p(dirs), _p(Y))
+    return Y
+
+
+def adam(p, g, m, v, vis, lr, beta1, beta2, eps, t):
+    """Sparse Adam on row-major (N, F) arrays; returns updated copies (p, g, m, v)."""
+    p, g, m, v = (np.array(a, dtype=np.float64, order="C") for a in (p, g, m, v))
+    N, F = p.shape
+    lr = np.ascontiguousarray(np.broadcast_to(np.asarray(lr, np.float64), (F,)))
+    vis = np.ascontiguousarray(vis, dtype=np.uint8)
+    lib().or_adam(ctypes.c_int64(N), ctypes.c_int(F), _p(p), _p(g), _p(m), _p(v), _p(vis), _p(lr),
+                  ctypes.c_double(beta1), ctypes.c_double(beta2), ctypes.c_double(eps),
+                  ctypes.c_int64(t))
+    return p, g, m, v
+
+
+def forward(params, deg, views, fp64=False, tie_alpha=0.0, tie_T=0.0):
+    """Project, bin and blend every view; returns (projs, bins, renders)."""
+    projs = [project(params, deg, v, fp64=fp64) for v in views]
+    bins = bin_views(projs, views, fp64=fp64)
+    rend = render(projs, views, bins, tie_alpha=tie_alpha, tie_T=tie_T)
+    return projs, bins, rend
+
+
+def backward(params, deg, views, projs, bins, gouts, tie_alpha=0.0, tie_T=0.0):
+    """Full adjoint: parameter-row gradients summed over views, exposure gradients per view,
+    per-Gaussian tie flags (OR over views)."""
+    g2ds, gEs, gties = blend_backward(projs, views, bins, gouts, tie_alpha, tie_T)
+    gp = np.zeros_like(np.asarray(params, dtype=np.float64))
+    tie = np.zeros(gp.shape[0], np.uint8)
+    for v, pr, g2d, gt in zip(views, projs, g2ds, gties):
+        gp += project_backward(params, deg, v, pr["visible"], g2d)
+        tie |= gt
+    return gp, gEs, tie

@@ -1,0 +1,238 @@
+/*
+ * gslic.h - C ABI of the MI355X (gfx950) mapping step of a 3D Gaussian map.
+ *
+ * Method: Gaussian-LIC (arXiv 2404.06926). A map of anisotropic 3D Gaussians (Sec. III-A)
+ * is optimised online from posed keyframes (Sec. III-C): every step projects the
+ * Gaussians (Eq. 1-3), bins them into 16x16 tiles with a depth-ordered key sort, blends
+ * front to back (Eq. 4-5) with a per-keyframe 3x4 exposure affine (Sec. III-C.3), takes
+ * the L1 + D-SSIM loss (Eq. 9), back-propagates, and applies sparse Adam to the Gaussians
+ * seen in the step (Sec. III-D.2). New points become Gaussians by the rule of
+ * Sec. III-C.1.
+ *
+ * Conventions shared by every call
+ *   - All pointers named "device" are HIP device pointers; all other pointers are host.
+ *     Nothing is copied between host and device implicitly except the small per-view
+ *     parameters carried in gs_view (passed by value to the kernels).
+ *   - Every call that takes a `stream` (a hipStream_t, NULL = default stream) only
+ *     enqueues work and returns; results are ready when the stream reaches that point.
+ *   - Return value: GS_OK (0) or a negative gs_status. On a validation error nothing is
+ *     enqueued and the map is unchanged; gs_last_error() describes the failure
+ *     (thread-local, valid until the next call on the same thread).
+ *   - A map is used from one host thread and one stream at a time. Different maps are
+ *     independent. No C++ exception crosses this ABI.
+ *   - Gaussian parameters are stored as planes (structure of arrays) of FP32:
+ *       plane 0..2   mean (world frame)
+ *       plane 3..5   log-scale            (scale = exp)
+ *       plane 6..9   quaternion w, x, y, z (normalised when used)
+ *       plane 10     opacity logit        (opacity = sigmoid)
+ *       plane 11+3k+c  SH coefficient k (k < (deg+1)^2) of colour channel c
+ *     Plane f of a buffer starts at base + f * capacity.
+ */
+#ifndef GSLIC_H
+#define GSLIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_map gs_map; /* opaque */
+typedef int32_t gs_status;
+
+enum {
+  GS_OK = 0,
+  GS_ERR_INVALID = -1,       /* bad argument; nothing enqueued */
+  GS_ERR_OOM = -2,           /* an allocation failed; map unchanged */
+  GS_ERR_HIP = -3,           /* a HIP runtime call failed */
+  GS_ERR_CAPACITY = -4,      /* a fixed capacity (views per call, instances) is exceeded */
+  GS_ERR_STATE = -6,         /* call order violated (e.g. backward without a render) */
+  GS_ERR_UNIMPLEMENTED = -7
+};
+
+enum { GS_MAX_VIEWS = 16, GS_TILE = 16, GS_EXPOSURE_STATE_FLOATS = 48 };
+
+/* Optional device-memory provider. alloc returns a device pointer of at least `bytes`
+ * bytes (256-byte aligned) usable on `stream`, or NULL; free releases it. When the
+ * allocator passed to gs_create_map is NULL, the library calls hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* ctx;
+} gs_allocator;
+
+/* Map hyper-parameters. Learning rates are per parameter group (Sec. IV-A.1: vanilla
+ * 3DGS rates, not decayed). */
+typedef struct {
+  int32_t sh_degree;         /* 0..3 (the paper uses 3, Sec. III-A) */
+  int64_t initial_capacity;  /* Gaussians; grows by doubling */
+  float near_z;              /* cull depth <= near_z (camera frame); 0.2 */
+  float lr_mean, lr_log_scale, lr_quat, lr_opacity, lr_sh_dc, lr_sh_rest, lr_exposure;
+  float beta1, beta2, eps;   /* Adam */
+} gs_map_desc;
+
+/* One camera of a step. The pose maps world points into the camera frame
+ * (x_c = R_cw x_w + t_cw; camera x right, y down, z forward), Sec. III-A Eq. 2.
+ * Pixel (u, v) is sampled at its centre (u + 0.5, v + 0.5). */
+typedef struct {
+  float R_cw[9];             /* row-major */
+  float t_cw[3];
+  float fx, fy, cx, cy;      /* pinhole intrinsics in pixels */
+  int32_t width, height;     /* pixels, 1..16384 each */
+  float bg[3];               /* background colour added behind the Gaussians */
+  const float* exposure;     /* device float[12]: 3x4 [A | b] row-major; out = A c + b
+                                (Sec. III-C.3). NULL = identity. */
+} gs_view;
+
+/* Per-view outputs of gs_render (all device, caller-owned, H*W pixels).
+ *   rgb       float[3][H][W]  exposed colour, required
+ *   final_T   float[H][W]     transmittance after the last contributor (1 - opacity map,
+ *                             Eq. 7); NULL = kept inside the map's workspace
+ *   n_contrib uint32[H][W]    list position after the last contributing Gaussian of the
+ *                             pixel's tile list; NULL = kept inside the workspace
+ * When given, final_T and n_contrib must stay alive until gs_render_backward. */
+typedef struct {
+  float* rgb;
+  float* final_T;
+  uint32_t* n_contrib;
+} gs_frame;
+
+/* Defaults: SH 3, near 0.2, 3DGS learning rates, Adam (0.9, 0.999, 1e-15). */
+void gs_default_desc(gs_map_desc* desc);
+
+/* Create an empty map. `allocator` may be NULL (hipMalloc); it is copied. */
+gs_status gs_create_map(const gs_map_desc* desc, const gs_allocator* allocator, gs_map** out);
+
+/* Release every buffer of the map (synchronises the device first). NULL is a no-op. */
+gs_status gs_destroy_map(gs_map* map);
+
+/* Append n Gaussians (Sec. III-C.1 parameters, already in parameter space).
+ * Inputs are device arrays in rows: means n x 3, log_scales n x 3, quats n x 4 (w,x,y,z),
+ * opacity_logits n, sh n x K x 3 (K = (deg+1)^2, coefficient-major). Gradients and Adam
+ * moments of the new rows start at zero. Capacity doubles as needed (device copy on
+ * `stream`). n = 0 is a no-op. */
+gs_status gs_add_gaussians(gs_map* map, int64_t n, const float* means, const float* log_scales,
+                           const float* quats, const float* opacity_logits, const float* sh,
+                           void* stream);
+
+/* Initialise Gaussians from coloured points as in Sec. III-C.1: centre = point, SH DC
+ * chosen so the colour renders as `rgb`, other SH 0, opacity o_init, rotation identity,
+ * isotropic scale d / f where d is the point's depth in `view` and f = view.fx.
+ * xyz, rgb: device n x 3. Points with depth <= near_z get scale near_z / f. */
+gs_status gs_add_points(gs_map* map, int64_t n, const float* xyz, const float* rgb,
+                        const gs_view* view, float o_init, void* stream);
+
+/* Forward pass over n_views views of the same map in one batch (Sec. III-A Eq. 1-5,
+ * Sec. III-C.3 exposure, Sec. III-D.2 tile culling). Tiles of all views are numbered
+ * consecutively and processed by the same launches. Saves what gs_render_backward needs. */
+gs_status gs_render(gs_map* map, int32_t n_views, const gs_view* views, const gs_frame* frames,
+                    void* stream);
+
+/* Reverse pass of the immediately preceding gs_render on this map (same n_views).
+ * dL_drgb[v]: device float[3][H][W]. dL_dexposure[v]: device float[12] that receives
+ * (+=) dL/d[A|b]; the array or any entry may be NULL. Parameter gradients are added to
+ * the map's gradient planes (they accumulate until gs_adam_step) and the Gaussians seen
+ * by any view are marked for the next sparse Adam step. GS_ERR_STATE without a render. */
+gs_status gs_render_backward(gs_map* map, int32_t n_views, const float* const* dL_drgb,
+                             float* const* dL_dexposure, void* stream);
+
+/* One sparse Adam step (Sec. III-D.2, Sec. IV-A.1): rows marked since the last step move,
+ * other rows keep parameters and moments bit-identical; gradients of moved rows are
+ * cleared. The step count t is kept on the device (bias correction 1 - beta^t).
+ * exposure_states[e]: device float[48] = exposure [A|b] (12), its gradient (12), Adam m
+ * (12), Adam v (12); each is updated with lr_exposure and its gradient cleared. */
+gs_status gs_adam_step(gs_map* map, int32_t n_exposures, float* const* exposure_states,
+                       void* stream);
+
+/* Eq. 9 loss between out and gt (device float[3][H][W] each):
+ *   L = (1 - lambda) mean|out - gt| + lambda (1 - mean SSIM(out, gt)),
+ * SSIM per channel with an 11x11 Gaussian window (sigma 1.5), C1 = 1e-4, C2 = 9e-4 and
+ * zero padding. Writes L to loss_dev (device float[1]) and dL/dout to dL_dout (device,
+ * same shape; may alias nothing). Uses the map's workspace. */
+gs_status gs_loss(gs_map* map, const float* out, const float* gt, int32_t height, int32_t width,
+                  float lambda, float* loss_dev, float* dL_dout, void* stream);
+
+/* One mapping job on a keyframe (Sec. III-C): append Gaussians from the keyframe's points
+ * (gs_add_points with o_init), store the keyframe (pose, a copy of `image`, an identity
+ * exposure with fresh Adam state) in a window of the `window` most recent keyframes
+ * (window <= GS_MAX_VIEWS), then run `iters` steps, each = one batched gs_render over
+ * the window, Eq. 9 loss per keyframe, gs_render_backward, gs_adam_step (Gaussians and
+ * window exposures). image: device float[3][H][W]; xyz, rgb: device n_points x 3.
+ * done_event (a hipEvent_t, may be NULL) is recorded on `stream` after the last step. */
+gs_status gs_submit_keyframe(gs_map* map, const gs_view* view, const float* image,
+                             int64_t n_points, const float* xyz, const float* rgb,
+                             int32_t iters, int32_t window, float lambda, float o_init,
+                             void* done_event, void* stream);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* gs_last_error(void);
+
+/* Size and memory: live Gaussians, capacity, bytes the map holds (parameters, gradients,
+ * moments, workspace). Host-side values; never synchronises. */
+gs_status gs_map_info(const gs_map* map, int64_t* n, int64_t* capacity, int64_t* resident_bytes);
+
+/* Device pointers to plane 0 of the parameter, gradient and Adam m / v buffers, and the
+ * plane stride (= capacity). Valid until the map grows or is destroyed. Any may be NULL. */
+gs_status gs_map_params(gs_map* map, float** params, float** grads, float** adam_m, float** adam_v,
+                        int64_t* plane_stride);
+
+/* Device pointer to the per-Gaussian "seen since the last Adam step" flags (uint8[n]). */
+gs_status gs_map_visibility(gs_map* map, uint8_t** vis);
+
+/* Number of Adam steps taken (host mirror of the device counter). */
+gs_status gs_map_step_count(const gs_map* map, int64_t* t);
+
+/* Device views of the last gs_render's intermediate results, valid until the next render:
+ *   keys      uint64[n_inst]  sorted keys (global tile << 32 | float bits of depth)
+ *   vals      uint32[n_inst]  Gaussian index of each sorted key
+ *   ranges    uint32[2 * n_tiles] [start, end) of each global tile in the sorted list
+ *   proj      float[16 * n_views * n]  per (view, Gaussian) record, view-major:
+ *             mean2d x, y, conic A, B, C, opacity, colour r, g, b, depth, unused,
+ *             2 ln(255 opacity), tile rectangle x0 | y0 << 16 and x1 | y1 << 16 (uint32
+ *             bits), 2 unused; written only where the tile count is > 0
+ *   counts    uint32[n_views * n]  tiles reached by each (view, Gaussian), view-major
+ * n_inst is read back from the device (this call synchronises `stream`). */
+gs_status gs_debug_last_render(gs_map* map, void* stream, const uint64_t** keys,
+                               const uint32_t** vals, int64_t* n_inst, const uint32_t** ranges,
+                               int64_t* n_tiles, const float** proj, const uint32_t** counts);
+
+/* Instance-buffer policy. sync_plan = 1 (default): gs_render reads the instance count back
+ * after binning and grows the buffers to fit (one host wait per render). sync_plan = 0:
+ * no host wait inside gs_render (a graph-capturable sequence); instances beyond
+ * `capacity` are dropped and flagged, to be checked with gs_check_overflow. */
+gs_status gs_set_instance_policy(gs_map* map, int32_t sync_plan, int64_t capacity);
+
+/* Synchronise `stream` and report whether any render since the last check dropped
+ * instances (1) or not (0); clears the flag. */
+gs_status gs_check_overflow(gs_map* map, void* stream, int32_t* overflow);
+
+/* Per-stage GPU timing. With timing enabled, every stage of the calls below records a
+ * pair of HIP events on the call's stream around its kernels. gs_stage_times synchronises
+ * `stream`, writes the summed milliseconds and the number of timed launches of each stage
+ * since the previous query into ms[GS_NUM_STAGES] and count[GS_NUM_STAGES], and resets.
+ * Stage order: GS_STAGE_* below. */
+enum {
+  GS_STAGE_PROJECT = 0,       /* per-Gaussian projection and tile count */
+  GS_STAGE_SCAN = 1,          /* exclusive scan of tile counts */
+  GS_STAGE_DUPLICATE = 2,     /* (tile, depth) keys of every instance */
+  GS_STAGE_SORT = 3,          /* radix sort of the keys */
+  GS_STAGE_RANGES = 4,        /* per-tile [start, end) */
+  GS_STAGE_BLEND = 5,         /* forward blend */
+  GS_STAGE_LOSS = 6,          /* L1 + D-SSIM and its gradient */
+  GS_STAGE_BLEND_BACKWARD = 7,
+  GS_STAGE_PROJECT_BACKWARD = 8,
+  GS_STAGE_ADAM = 9,
+  GS_NUM_STAGES = 10
+};
+gs_status gs_set_stage_timing(gs_map* map, int32_t enable);
+gs_status gs_stage_times(gs_map* map, void* stream, double* ms, int64_t* count);
+
+/* Launch configuration of the blend kernels: pixels per lane in the forward and backward
+ * (1, 2 or 4). Results do not depend on it beyond FP32 summation order. */
+gs_status gs_set_blend_config(gs_map* map, int32_t fwd_px_per_lane, int32_t bwd_px_per_lane);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSLIC_H */

@@ -187,6 +187,26 @@ def render(projs, views, bins, tie_alpha=0.0, tie_T=0.0):
     return res
 
 
+def render_pixels(projs, views, bins, view_index, pix, tie_alpha=0.0, tie_T=0.0):
+    """Tiled blend of one view at the flat pixel indices `pix` only."""
+    mean2d, conic = _cat(projs, "mean2d"), _cat(projs, "conic")
+    opac, colour = _cat(projs, "opacity"), _cat(projs, "colour")
+    base = sum(v.n_tiles for v in views[:view_index])
+    v = views[view_index]
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.shape[0]
+    out, Tf = np.zeros((n, 3)), np.zeros(n)
+    nc, tie = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    E = np.ascontiguousarray(v.E, dtype=np.float64)
+    bg = np.ascontiguousarray(v.bg, dtype=np.float64)
+    lib().or_render_tiled_pixels(ctypes.c_int(v.W), ctypes.c_int(v.H), ctypes.c_int64(base),
+                                 _p(bins["ranges"]), _p(bins["val"]), _p(mean2d), _p(conic), _p(opac),
+                                 _p(colour), _p(E), _p(bg), ctypes.c_double(tie_alpha),
+                                 ctypes.c_double(tie_T), ctypes.c_int64(n), _p(pix), _p(out), _p(Tf),
+                                 _p(nc), _p(tie))
+    return dict(out=out, T_final=Tf, n_contrib=nc, tie=tie)
+
+
 def render_brute(proj, view: OView):
     """Per-pixel blend over all visible Gaussians in (depth, index) order; no tiles."""
     N = proj["count"].shape[0]

@@ -451,7 +451,7 @@ int blend_pixel(const BlendIn& in, const uint32_t* ids, int n, double px, double
     const double alpha = std::min(kAlphaMax, araw);
     if (alpha < kAlphaMin) continue;
     const double Tn = T * (1.0 - alpha);
-    if (in.tie_T > 0 && std::fabs(Tn / kTMin - 1.0) < in.tie_T * (1.0 + 0.02 * ncon)) *tie |= 1;
+    if (in.tie_T > 0 && std::fabs(Tn / kTMin - 1.0) < in.tie_T * (1.0 + 0.2 * ncon)) *tie |= 1;
     if (Tn < kTMin) break;
     if (rec) rec->push_back(PairRec{g, p, alpha, araw, expo, T, dx, dy});
     T = Tn;
@@ -636,6 +636,33 @@ void or_render_tiled(int W, int H, int64_t tile_base, const int64_t* ranges /*gl
   }
 }
 
+// The tiled blend at a list of pixels only (sampled checks of large images).
+void or_render_tiled_pixels(int W, int H, int64_t tile_base, const int64_t* ranges, const uint32_t* vals,
+                            const double* mean2d, const double* conic, const double* opac,
+                            const double* colour, const double* E, const double* bg, double tie_alpha,
+                            double tie_T, int64_t npix, const int64_t* pix, double* out /*npix x 3*/,
+                            double* Tfinal, int32_t* ncontrib, int32_t* tie) {
+  const int tiles_x = (W + 15) / 16;
+  (void)H;
+  BlendIn in{mean2d, conic, opac, colour, nullptr, E, bg, tie_alpha, tie_T};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < npix; ++k) {
+    const int x = (int)(pix[k] % W), y = (int)(pix[k] / W);
+    const int64_t t = tile_base + (int64_t)(y / 16) * tiles_x + (x / 16);
+    const int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
+    std::vector<PairRec> rec;
+    double Tf;
+    int nc, tf;
+    blend_pixel(in, vals + s, (int)(e - s), x + 0.5, y + 0.5, &rec, &Tf, &nc, &tf);
+    double pr[3], o[3];
+    finish_pixel(in, rec, Tf, pr, o);
+    for (int c = 0; c < 3; ++c) out[3 * k + c] = o[c];
+    Tfinal[k] = Tf;
+    ncontrib[k] = nc;
+    tie[k] = tf;
+  }
+}
+
 // Brute force, the plain definition: every pixel blends every visible Gaussian in
 // (depth, index) order, with no tiles. ncon = number of contributors.
 void or_render_brute(int N, int W, int H, const uint8_t* visible, const double* depth,
@@ -688,8 +715,12 @@ void or_blend_backward(int W, int H, int64_t tile_base, const int64_t* ranges, c
       double Tf;
       int nc, tf;
       blend_pixel(in, vals + s, (int)(e - s), x + 0.5, y + 0.5, &rec, &Tf, &nc, &tf);
-      if (tf && gtie)
-        for (int64_t k = s; k < e; ++k) gtie[vals[k]] = 1;
+      if (tf && gtie) {
+        // every Gaussian whose gradient sees this pixel: its contributors, and the entries
+        // up to the first one past the last contributor (where a stop decision sits)
+        const int64_t upto = std::min<int64_t>(e, s + (int64_t)nc + 1);
+        for (int64_t k = s; k < upto; ++k) gtie[vals[k]] = 1;
+      }
       double pr[3], o[3];
       finish_pixel(in, rec, Tf, pr, o);
       double go[3] = {gout[pix], gout[P + pix], gout[2 * P + pix]};

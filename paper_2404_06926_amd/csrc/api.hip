@@ -1,0 +1,757 @@
+// C ABI of libgslic: the map object, its device buffers and workspace, and the
+// orchestration of the kernels for render, backward, loss, Adam and keyframe jobs.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gs_common.h"
+#include "kernels.h"
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_err;
+
+gs_status fail(gs_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define GS_HIP(expr)                                                              \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess)                                                         \
+      return fail(GS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define GS_TRY(expr)            \
+  do {                          \
+    gs_status _s = (expr);      \
+    if (_s != GS_OK) return _s; \
+  } while (0)
+
+}  // namespace
+
+// A device buffer that grows by reallocation (old contents are not kept).
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct KeyframeSlot {
+  gs_view view{};
+  float* image = nullptr;      // 3 x H x W (owned copy of the target)
+  float* state = nullptr;      // exposure [E | grad | m | v] (48 floats)
+  float* rgb = nullptr;        // render output
+  float* T = nullptr;
+  uint32_t* nc = nullptr;
+  float* dl = nullptr;         // dL/d rgb
+  size_t pix_bytes = 0;        // bytes of one float plane of this slot's buffers
+};
+
+struct gs_map {
+  gs_map_desc desc{};
+  gs_allocator alloc{};
+  bool has_alloc = false;
+  int deg = 3, K = 16, F = 59;
+  int64_t n = 0, cap = 0;
+  float* buf = nullptr;        // params | grads | m | v, each F planes of cap floats
+  uint8_t* vis = nullptr;      // cap bytes (rounded up to 4)
+  int64_t* d_step = nullptr;   // Adam step t
+  float* d_bc = nullptr;       // bias corrections
+  uint32_t* d_ninst = nullptr; // instance count of the last render
+  uint32_t* d_overflow = nullptr;
+  float* d_loss = nullptr;     // loss values of keyframe jobs (64 floats)
+  uint32_t* h_pinned = nullptr;
+  int64_t h_step = 0;
+  int64_t resident = 0;
+  // workspace
+  DevBuf rec, counts, offsets, scan_tmp, g2d, keys[2], vals[2], sort_tmp, ranges, pixT, pixN, loss_tmp;
+  int64_t vn_cap = 0, inst_cap = 0, tiles_cap = 0, pix_cap = 0;
+  bool sync_plan = true;
+  // last render
+  bool have_render = false;
+  ViewsArg last_va{};
+  int32_t last_N = 0;
+  int sorted = 0;
+  // keyframe window
+  std::vector<KeyframeSlot> kf;
+  int kf_next = 0;
+  // per-stage timing: event pairs recorded since the last query
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (stage, index of its start event)
+};
+
+namespace {
+
+void* dev_alloc(gs_map* m, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (m->has_alloc) {
+    p = m->alloc.alloc(bytes, (void*)s, m->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) m->resident += (int64_t)bytes;
+  return p;
+}
+
+void dev_free(gs_map* m, void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  m->resident -= (int64_t)bytes;
+  if (m->has_alloc)
+    m->alloc.free(p, (void*)s, m->alloc.ctx);
+  else
+    (void)hipFree(p);
+}
+
+// Grow `b` to at least `bytes` (contents dropped). zero: clear the new buffer.
+gs_status ensure(gs_map* m, DevBuf& b, size_t bytes, hipStream_t s, bool zero = false) {
+  if (b.bytes >= bytes && b.ptr) return GS_OK;
+  void* p = dev_alloc(m, bytes, s);
+  if (!p) return fail(GS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  dev_free(m, b.ptr, b.bytes, s);
+  b.ptr = p;
+  b.bytes = bytes;
+  if (zero) {
+    hipError_t e = fill_u32((uint32_t*)p, 0u, (int64_t)((bytes + 3) / 4), s);
+    if (e != hipSuccess) return fail(GS_ERR_HIP, hipGetErrorString(e));
+  }
+  return GS_OK;
+}
+
+float* params_of(gs_map* m) { return m->buf; }
+float* grads_of(gs_map* m) { return m->buf + (int64_t)m->F * m->cap; }
+
+gs_status grow_capacity(gs_map* m, int64_t need, hipStream_t s) {
+  if (need <= m->cap) return GS_OK;
+  int64_t nc = std::max<int64_t>(need, std::max<int64_t>(1024, 2 * m->cap));
+  const size_t fbytes = (size_t)4 * m->F * nc * sizeof(float);
+  const size_t vbytes = (size_t)((nc + 3) / 4) * 4;
+  float* nb = (float*)dev_alloc(m, fbytes, s);
+  if (!nb) return fail(GS_ERR_OOM, "map growth to " + std::to_string(nc) + " Gaussians failed");
+  uint8_t* nv = (uint8_t*)dev_alloc(m, vbytes, s);
+  if (!nv) {
+    dev_free(m, nb, fbytes, s);
+    return fail(GS_ERR_OOM, "map growth (visibility) failed");
+  }
+  GS_HIP(fill_u32((uint32_t*)nv, 0u, (int64_t)(vbytes / 4), s));
+  if (m->n > 0) {
+    GS_HIP(copy_planes(m->buf, m->cap, nb, nc, m->n, 4 * m->F, s));
+    GS_HIP(hipMemcpyAsync(nv, m->vis, (size_t)m->n, hipMemcpyDeviceToDevice, s));
+  }
+  if (m->buf) {
+    // the old buffers may still be read by queued work on this stream
+    GS_HIP(hipStreamSynchronize(s));
+    dev_free(m, m->buf, (size_t)4 * m->F * m->cap * sizeof(float), s);
+    dev_free(m, m->vis, (size_t)((m->cap + 3) / 4) * 4, s);
+  }
+  m->buf = nb;
+  m->vis = nv;
+  m->cap = nc;
+  m->have_render = false;
+  return GS_OK;
+}
+
+int bits_for(int64_t x) {
+  int b = 0;
+  while ((int64_t(1) << b) < x) ++b;
+  return std::max(b, 1);
+}
+
+gs_status check_view(const gs_view& v, int idx) {
+  if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
+    return fail(GS_ERR_INVALID, "view " + std::to_string(idx) + ": size out of range");
+  const float vals[] = {v.fx, v.fy, v.cx, v.cy};
+  for (float f : vals)
+    if (!std::isfinite(f)) return fail(GS_ERR_INVALID, "view " + std::to_string(idx) + ": non-finite intrinsics");
+  if (!(v.fx > 0.f) || !(v.fy > 0.f))
+    return fail(GS_ERR_INVALID, "view " + std::to_string(idx) + ": focal length must be positive");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(v.R_cw[k])) return fail(GS_ERR_INVALID, "view " + std::to_string(idx) + ": non-finite pose");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(v.t_cw[k])) return fail(GS_ERR_INVALID, "view " + std::to_string(idx) + ": non-finite pose");
+  return GS_OK;
+}
+
+void fill_viewdev(ViewDev& d, const gs_view& v) {
+  std::memcpy(d.R, v.R_cw, sizeof(d.R));
+  std::memcpy(d.t, v.t_cw, sizeof(d.t));
+  d.fx = v.fx;
+  d.fy = v.fy;
+  d.cx = v.cx;
+  d.cy = v.cy;
+  for (int k = 0; k < 3; ++k) {
+    double c = 0.0;
+    for (int r = 0; r < 3; ++r) c -= (double)v.R_cw[3 * r + k] * (double)v.t_cw[r];
+    d.campos[k] = (float)c;
+    d.bg[k] = v.bg[k];
+  }
+  d.W = v.width;
+  d.H = v.height;
+  d.tiles_x = (v.width + kTile - 1) / kTile;
+  d.tiles_y = (v.height + kTile - 1) / kTile;
+  d.exposure = v.exposure;
+  d.dl_drgb = nullptr;
+  d.dl_dexp = nullptr;
+}
+
+// Records a start event for `stage` (when timing is on); stage_end records the stop.
+struct StageTimer {
+  gs_map* m;
+  hipStream_t s;
+  int stage;
+  size_t idx = 0;
+  bool on = false;
+  StageTimer(gs_map* m_, hipStream_t s_, int st) : m(m_), s(s_), stage(st) {
+    if (!m->timing) return;
+    while (m->ev_pool.size() < m->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      m->ev_pool.push_back(e);
+    }
+    idx = m->ev_used;
+    m->ev_used += 2;
+    on = hipEventRecord(m->ev_pool[idx], s) == hipSuccess;
+  }
+  ~StageTimer() {
+    if (on && hipEventRecord(m->ev_pool[idx + 1], s) == hipSuccess) m->ev_marks.emplace_back(stage, idx);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void gs_default_desc(gs_map_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->sh_degree = 3;
+  d->initial_capacity = 1 << 16;
+  d->near_z = 0.2f;
+  d->lr_mean = 1.6e-4f;
+  d->lr_log_scale = 5e-3f;
+  d->lr_quat = 1e-3f;
+  d->lr_opacity = 5e-2f;
+  d->lr_sh_dc = 2.5e-3f;
+  d->lr_sh_rest = 2.5e-3f / 20.0f;
+  d->lr_exposure = 1e-3f;
+  d->beta1 = 0.9f;
+  d->beta2 = 0.999f;
+  d->eps = 1e-15f;
+}
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+gs_status gs_create_map(const gs_map_desc* desc, const gs_allocator* allocator, gs_map** out) {
+  g_err.clear();
+  if (!desc || !out) return fail(GS_ERR_INVALID, "desc and out must not be NULL");
+  *out = nullptr;
+  if (desc->sh_degree < 0 || desc->sh_degree > 3) return fail(GS_ERR_INVALID, "sh_degree must be 0..3");
+  if (desc->initial_capacity < 0) return fail(GS_ERR_INVALID, "initial_capacity must be >= 0");
+  if (!(desc->near_z > 0.f)) return fail(GS_ERR_INVALID, "near_z must be > 0");
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return fail(GS_ERR_INVALID, "allocator needs both alloc and free");
+  gs_map* m = new (std::nothrow) gs_map();
+  if (!m) return fail(GS_ERR_OOM, "host allocation failed");
+  m->desc = *desc;
+  if (allocator) {
+    m->alloc = *allocator;
+    m->has_alloc = true;
+  }
+  m->deg = desc->sh_degree;
+  m->K = (m->deg + 1) * (m->deg + 1);
+  m->F = 11 + 3 * m->K;
+  hipStream_t s = nullptr;
+  m->d_step = (int64_t*)dev_alloc(m, 64, s);
+  m->d_bc = (float*)dev_alloc(m, 64, s);
+  m->d_ninst = (uint32_t*)dev_alloc(m, 64, s);
+  m->d_overflow = (uint32_t*)dev_alloc(m, 64, s);
+  m->d_loss = (float*)dev_alloc(m, 256, s);
+  if (!m->d_step || !m->d_bc || !m->d_ninst || !m->d_overflow || !m->d_loss) {
+    gs_destroy_map(m);
+    return fail(GS_ERR_OOM, "device allocation failed");
+  }
+  if (hipHostMalloc((void**)&m->h_pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    m->h_pinned = nullptr;
+    gs_destroy_map(m);
+    return fail(GS_ERR_HIP, "pinned host allocation failed");
+  }
+  hipError_t e = fill_u32((uint32_t*)m->d_step, 0u, 16, s);
+  if (e == hipSuccess) e = fill_u32(m->d_overflow, 0u, 16, s);
+  if (e == hipSuccess) e = fill_u32(m->d_ninst, 0u, 16, s);
+  if (e != hipSuccess) {
+    gs_destroy_map(m);
+    return fail(GS_ERR_HIP, hipGetErrorString(e));
+  }
+  if (desc->initial_capacity > 0) {
+    gs_status st = grow_capacity(m, desc->initial_capacity, s);
+    if (st != GS_OK) {
+      std::string msg = g_err;
+      gs_destroy_map(m);
+      return fail(st, msg);
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    gs_destroy_map(m);
+    return fail(GS_ERR_HIP, "initialisation failed");
+  }
+  *out = m;
+  return GS_OK;
+}
+
+gs_status gs_destroy_map(gs_map* m) {
+  if (!m) return GS_OK;
+  (void)hipDeviceSynchronize();
+  hipStream_t s = nullptr;
+  dev_free(m, m->buf, (size_t)4 * m->F * m->cap * sizeof(float), s);
+  dev_free(m, m->vis, (size_t)((m->cap + 3) / 4) * 4, s);
+  dev_free(m, m->d_step, 64, s);
+  dev_free(m, m->d_bc, 64, s);
+  dev_free(m, m->d_ninst, 64, s);
+  dev_free(m, m->d_overflow, 64, s);
+  dev_free(m, m->d_loss, 256, s);
+  DevBuf* bufs[] = {&m->rec, &m->counts, &m->offsets, &m->scan_tmp, &m->g2d, &m->keys[0], &m->keys[1],
+                    &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp};
+  for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
+  for (KeyframeSlot& k : m->kf) {
+    dev_free(m, k.image, 3 * k.pix_bytes, s);
+    dev_free(m, k.rgb, 3 * k.pix_bytes, s);
+    dev_free(m, k.dl, 3 * k.pix_bytes, s);
+    dev_free(m, k.T, k.pix_bytes, s);
+    dev_free(m, k.nc, k.pix_bytes, s);
+    dev_free(m, k.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+  }
+  if (m->h_pinned) (void)hipHostFree(m->h_pinned);
+  for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+  delete m;
+  return GS_OK;
+}
+
+gs_status gs_add_gaussians(gs_map* m, int64_t n, const float* means, const float* log_scales, const float* quats,
+                           const float* opacity_logits, const float* sh, void* stream) {
+  g_err.clear();
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+  if (n == 0) return GS_OK;
+  if (!means || !log_scales || !quats || !opacity_logits || !sh)
+    return fail(GS_ERR_INVALID, "input pointers must not be NULL");
+  if (m->n + n > (int64_t)INT32_MAX) return fail(GS_ERR_CAPACITY, "more than 2^31-1 Gaussians");
+  hipStream_t s = (hipStream_t)stream;
+  GS_TRY(grow_capacity(m, m->n + n, s));
+  GS_HIP(append_rows(m->buf, m->cap, m->F, m->K, m->n, n, means, log_scales, quats, opacity_logits, sh, m->vis, s));
+  m->n += n;
+  m->have_render = false;
+  return GS_OK;
+}
+
+gs_status gs_add_points(gs_map* m, int64_t n, const float* xyz, const float* rgb, const gs_view* view, float o_init,
+                        void* stream) {
+  g_err.clear();
+  if (!m || !view) return fail(GS_ERR_INVALID, "map and view must not be NULL");
+  if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+  if (n == 0) return GS_OK;
+  if (!xyz || !rgb) return fail(GS_ERR_INVALID, "xyz and rgb must not be NULL");
+  if (!(o_init > 0.f && o_init < 1.f)) return fail(GS_ERR_INVALID, "o_init must be in (0, 1)");
+  GS_TRY(check_view(*view, 0));
+  if (m->n + n > (int64_t)INT32_MAX) return fail(GS_ERR_CAPACITY, "more than 2^31-1 Gaussians");
+  hipStream_t s = (hipStream_t)stream;
+  GS_TRY(grow_capacity(m, m->n + n, s));
+  ViewDev V{};
+  fill_viewdev(V, *view);
+  const float logit0 = std::log(o_init / (1.0f - o_init));
+  GS_HIP(init_points(m->buf, m->cap, m->F, m->K, m->n, n, xyz, rgb, V, m->desc.near_z, logit0, m->vis, s));
+  m->n += n;
+  m->have_render = false;
+  return GS_OK;
+}
+
+gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* frames, void* stream) {
+  g_err.clear();
+  if (!m || !views || !frames) return fail(GS_ERR_INVALID, "map, views and frames must not be NULL");
+  if (nv < 1 || nv > kMaxViews) return fail(GS_ERR_CAPACITY, "n_views must be in 1..16");
+  hipStream_t s = (hipStream_t)stream;
+  ViewsArg va{};
+  va.n = nv;
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < nv; ++v) {
+    GS_TRY(check_view(views[v], v));
+    if (!frames[v].rgb) return fail(GS_ERR_INVALID, "frame " + std::to_string(v) + ": rgb must not be NULL");
+    fill_viewdev(va.v[v], views[v]);
+    va.v[v].tile_base = (int32_t)tiles;
+    va.v[v].pix_base = pix;
+    tiles += (int64_t)va.v[v].tiles_x * va.v[v].tiles_y;
+    pix += (int64_t)views[v].width * views[v].height;
+  }
+  if (tiles >= (int64_t(1) << 31)) return fail(GS_ERR_CAPACITY, "too many tiles");
+  va.total_tiles = (int32_t)tiles;
+  const int32_t N = (int32_t)m->n;
+  const int64_t vn = (int64_t)nv * N;
+  // workspace
+  GS_TRY(ensure(m, m->rec, (size_t)std::max<int64_t>(vn, 1) * kRecFloats * 4, s));
+  GS_TRY(ensure(m, m->counts, (size_t)std::max<int64_t>(vn, 1) * 4, s));
+  GS_TRY(ensure(m, m->offsets, (size_t)std::max<int64_t>(vn, 1) * 4, s));
+  GS_TRY(ensure(m, m->scan_tmp, (size_t)scan_temp_elems(std::max<int64_t>(vn, 1)) * 4, s));
+  GS_TRY(ensure(m, m->g2d, (size_t)std::max<int64_t>(vn, 1) * kGradFloats * 4, s, true));
+  GS_TRY(ensure(m, m->ranges, (size_t)tiles * 8, s));
+  GS_TRY(ensure(m, m->pixT, (size_t)pix * 4, s));
+  GS_TRY(ensure(m, m->pixN, (size_t)pix * 4, s));
+  for (int v = 0; v < nv; ++v) {
+    ViewDev& d = va.v[v];
+    d.out_rgb = frames[v].rgb;
+    d.out_T = frames[v].final_T ? frames[v].final_T : (float*)m->pixT.ptr + d.pix_base;
+    d.out_nc = frames[v].n_contrib ? frames[v].n_contrib : (uint32_t*)m->pixN.ptr + d.pix_base;
+  }
+  float4* rec = (float4*)m->rec.ptr;
+  uint32_t* counts = (uint32_t*)m->counts.ptr;
+  uint32_t* offsets = (uint32_t*)m->offsets.ptr;
+  {
+    StageTimer t(m, s, GS_STAGE_PROJECT);
+    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, s));
+  }
+  {
+    StageTimer t(m, s, GS_STAGE_SCAN);
+    if (vn > 0)
+      GS_HIP(scan_counts(counts, offsets, vn, (uint32_t*)m->scan_tmp.ptr, m->d_ninst, s));
+    else
+      GS_HIP(fill_u32(m->d_ninst, 0u, 1, s));
+  }
+  if (m->sync_plan) {
+    GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_ninst, 4, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    const int64_t need = m->h_pinned[0];
+    if (need > m->inst_cap) {
+      const int64_t nc = std::max<int64_t>(need + need / 4, 1 << 16);
+      for (int b = 0; b < 2; ++b) {
+        GS_TRY(ensure(m, m->keys[b], (size_t)nc * 8, s));
+        GS_TRY(ensure(m, m->vals[b], (size_t)nc * 4, s));
+      }
+      GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(nc) * 4, s));
+      m->inst_cap = nc;
+    }
+  } else if (m->inst_cap == 0) {
+    return fail(GS_ERR_STATE, "sync_plan = 0 needs an instance capacity (gs_set_instance_policy)");
+  }
+  uint64_t* keys[2] = {(uint64_t*)m->keys[0].ptr, (uint64_t*)m->keys[1].ptr};
+  uint32_t* vals[2] = {(uint32_t*)m->vals[0].ptr, (uint32_t*)m->vals[1].ptr};
+  {
+    StageTimer t(m, s, GS_STAGE_DUPLICATE);
+    GS_HIP(duplicate_keys(rec, counts, offsets, N, va, keys[0], vals[0], m->inst_cap, m->d_overflow, s));
+  }
+  int which = 0;
+  {
+    StageTimer t(m, s, GS_STAGE_SORT);
+    GS_HIP(radix_sort(keys, vals, m->d_ninst, m->inst_cap, 32 + bits_for(tiles), (uint32_t*)m->sort_tmp.ptr,
+                      &which, s));
+  }
+  uint2* ranges = (uint2*)m->ranges.ptr;
+  {
+    StageTimer t(m, s, GS_STAGE_RANGES);
+    GS_HIP(fill_u32((uint32_t*)ranges, 0u, 2 * tiles, s));
+    GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, s));
+  }
+  {
+    StageTimer t(m, s, GS_STAGE_BLEND);
+    GS_HIP(blend_forward(va, rec, N, vals[which], ranges, s));
+  }
+  m->have_render = true;
+  m->last_va = va;
+  m->last_N = N;
+  m->sorted = which;
+  return GS_OK;
+}
+
+gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
+                             void* stream) {
+  g_err.clear();
+  if (!m || !dL_drgb) return fail(GS_ERR_INVALID, "map and dL_drgb must not be NULL");
+  if (!m->have_render) return fail(GS_ERR_STATE, "render_backward needs a preceding render of the same map");
+  if (nv != m->last_va.n) return fail(GS_ERR_STATE, "n_views differs from the preceding render");
+  if (m->last_N != (int32_t)m->n) return fail(GS_ERR_STATE, "map changed since the render");
+  for (int v = 0; v < nv; ++v)
+    if (!dL_drgb[v]) return fail(GS_ERR_INVALID, "dL_drgb[" + std::to_string(v) + "] is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ViewsArg va = m->last_va;
+  for (int v = 0; v < nv; ++v) {
+    va.v[v].dl_drgb = dL_drgb[v];
+    va.v[v].dl_dexp = dL_dexposure ? dL_dexposure[v] : nullptr;
+  }
+  const int32_t N = m->last_N;
+  float4* rec = (float4*)m->rec.ptr;
+  float* g2d = (float*)m->g2d.ptr;
+  {
+    StageTimer t(m, s, GS_STAGE_BLEND_BACKWARD);
+    GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint2*)m->ranges.ptr, g2d,
+                          s));
+  }
+  {
+    StageTimer t(m, s, GS_STAGE_PROJECT_BACKWARD);
+    GS_HIP(project_backward(m->deg, params_of(m), grads_of(m), m->cap, N, va, m->desc.near_z,
+                            (const uint32_t*)m->counts.ptr, (float4*)g2d, m->vis, s));
+  }
+  return GS_OK;
+}
+
+gs_status gs_adam_step(gs_map* m, int32_t ne, float* const* exposure_states, void* stream) {
+  g_err.clear();
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (ne < 0 || ne > kMaxExposures) return fail(GS_ERR_CAPACITY, "n_exposures must be in 0..64");
+  if (ne > 0 && !exposure_states) return fail(GS_ERR_INVALID, "exposure_states is NULL");
+  ExpArg ea{};
+  ea.n = ne;
+  for (int e = 0; e < ne; ++e) {
+    if (!exposure_states[e]) return fail(GS_ERR_INVALID, "exposure_states[" + std::to_string(e) + "] is NULL");
+    ea.p[e] = exposure_states[e];
+  }
+  LrArg lr{};
+  const gs_map_desc& d = m->desc;
+  for (int f = 0; f < m->F; ++f) {
+    float r = d.lr_sh_rest;
+    if (f < 3) r = d.lr_mean;
+    else if (f < 6) r = d.lr_log_scale;
+    else if (f < 10) r = d.lr_quat;
+    else if (f < 11) r = d.lr_opacity;
+    else if (f < 14) r = d.lr_sh_dc;
+    lr.lr[f] = r;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StageTimer t(m, s, GS_STAGE_ADAM);
+  GS_HIP(adam_step(m->buf, m->cap, m->F, (int32_t)m->n, m->vis, lr, m->d_step, m->d_bc, d.beta1, d.beta2, d.eps,
+                   ea, d.lr_exposure, s));
+  if (m->n > 0) GS_HIP(fill_u32((uint32_t*)m->vis, 0u, (m->n + 3) / 4, s));
+  m->h_step += 1;
+  return GS_OK;
+}
+
+gs_status gs_loss(gs_map* m, const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
+                  float* dL_dout, void* stream) {
+  g_err.clear();
+  if (!m || !out || !gt || !loss_dev || !dL_dout) return fail(GS_ERR_INVALID, "NULL argument");
+  if (H < 1 || W < 1 || H > 16384 || W > 16384) return fail(GS_ERR_INVALID, "image size out of range");
+  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
+  hipStream_t s = (hipStream_t)stream;
+  GS_TRY(ensure(m, m->loss_tmp, (size_t)loss_temp_floats(H, W) * 4, s));
+  StageTimer t(m, s, GS_STAGE_LOSS);
+  GS_HIP(ssim_loss(out, gt, H, W, lambda, (float*)m->loss_tmp.ptr, loss_dev, dL_dout, s));
+  return GS_OK;
+}
+
+gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image, int64_t n_points, const float* xyz,
+                             const float* rgb, int32_t iters, int32_t window, float lambda, float o_init,
+                             void* done_event, void* stream) {
+  g_err.clear();
+  if (!m || !view || !image) return fail(GS_ERR_INVALID, "map, view and image must not be NULL");
+  if (iters < 0) return fail(GS_ERR_INVALID, "iters must be >= 0");
+  if (window < 1 || window > kMaxViews) return fail(GS_ERR_INVALID, "window must be in 1..16");
+  if (n_points < 0 || (n_points > 0 && (!xyz || !rgb))) return fail(GS_ERR_INVALID, "bad point arguments");
+  GS_TRY(check_view(*view, 0));
+  hipStream_t s = (hipStream_t)stream;
+  if (n_points > 0) GS_TRY(gs_add_points(m, n_points, xyz, rgb, view, o_init, stream));
+  // keyframe slot (ring of `window`)
+  if ((int)m->kf.size() > window) {
+    for (size_t k = window; k < m->kf.size(); ++k) {
+      KeyframeSlot& q = m->kf[k];
+      dev_free(m, q.image, 3 * q.pix_bytes, s);
+      dev_free(m, q.rgb, 3 * q.pix_bytes, s);
+      dev_free(m, q.dl, 3 * q.pix_bytes, s);
+      dev_free(m, q.T, q.pix_bytes, s);
+      dev_free(m, q.nc, q.pix_bytes, s);
+      dev_free(m, q.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+    }
+    m->kf.resize(window);
+    m->kf_next %= window;
+  }
+  int slot;
+  if ((int)m->kf.size() < window) {
+    m->kf.push_back(KeyframeSlot{});
+    slot = (int)m->kf.size() - 1;
+  } else {
+    slot = m->kf_next;
+  }
+  m->kf_next = (slot + 1) % window;
+  KeyframeSlot& k = m->kf[slot];
+  const size_t pb = (size_t)view->width * view->height * sizeof(float);
+  if (k.pix_bytes != pb) {
+    GS_HIP(hipStreamSynchronize(s));
+    dev_free(m, k.image, 3 * k.pix_bytes, s);
+    dev_free(m, k.rgb, 3 * k.pix_bytes, s);
+    dev_free(m, k.dl, 3 * k.pix_bytes, s);
+    dev_free(m, k.T, k.pix_bytes, s);
+    dev_free(m, k.nc, k.pix_bytes, s);
+    k.image = (float*)dev_alloc(m, 3 * pb, s);
+    k.rgb = (float*)dev_alloc(m, 3 * pb, s);
+    k.dl = (float*)dev_alloc(m, 3 * pb, s);
+    k.T = (float*)dev_alloc(m, pb, s);
+    k.nc = (uint32_t*)dev_alloc(m, pb, s);
+    k.pix_bytes = pb;
+    if (!k.image || !k.rgb || !k.dl || !k.T || !k.nc) {
+      // leave the slot empty-sized so a later call reallocates it
+      dev_free(m, k.image, 3 * pb, s);
+      dev_free(m, k.rgb, 3 * pb, s);
+      dev_free(m, k.dl, 3 * pb, s);
+      dev_free(m, k.T, pb, s);
+      dev_free(m, k.nc, pb, s);
+      k = KeyframeSlot{};
+      m->kf.erase(m->kf.begin() + slot);
+      m->kf_next = m->kf.empty() ? 0 : (int)(slot % m->kf.size());
+      return fail(GS_ERR_OOM, "keyframe buffers");
+    }
+  }
+  if (!k.state) {
+    k.state = (float*)dev_alloc(m, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+    if (!k.state) return fail(GS_ERR_OOM, "exposure state");
+  }
+  GS_HIP(hipMemcpyAsync(k.image, image, 3 * pb, hipMemcpyDeviceToDevice, s));
+  // identity exposure, zero gradient and moments
+  {
+    GS_HIP(fill_u32((uint32_t*)k.state, 0u, GS_EXPOSURE_STATE_FLOATS, s));
+    GS_HIP(fill_u32((uint32_t*)k.state + 0, 0x3f800000u, 1, s));
+    GS_HIP(fill_u32((uint32_t*)k.state + 5, 0x3f800000u, 1, s));
+    GS_HIP(fill_u32((uint32_t*)k.state + 10, 0x3f800000u, 1, s));
+  }
+  k.view = *view;
+  k.view.exposure = k.state;
+  const int nk = (int)m->kf.size();
+  std::vector<gs_view> vv(nk);
+  std::vector<gs_frame> ff(nk);
+  std::vector<const float*> dl(nk);
+  std::vector<float*> eg(nk), es(nk);
+  for (int j = 0; j < nk; ++j) {
+    KeyframeSlot& q = m->kf[j];
+    vv[j] = q.view;
+    ff[j] = gs_frame{q.rgb, q.T, q.nc};
+    dl[j] = q.dl;
+    eg[j] = q.state + 12;
+    es[j] = q.state;
+  }
+  for (int it = 0; it < iters; ++it) {
+    GS_TRY(gs_render(m, nk, vv.data(), ff.data(), stream));
+    for (int j = 0; j < nk; ++j) {
+      KeyframeSlot& q = m->kf[j];
+      GS_TRY(gs_loss(m, q.rgb, q.image, q.view.height, q.view.width, lambda, m->d_loss + j, q.dl, stream));
+    }
+    GS_TRY(gs_render_backward(m, nk, dl.data(), eg.data(), stream));
+    GS_TRY(gs_adam_step(m, nk, es.data(), stream));
+  }
+  if (done_event) GS_HIP(hipEventRecord((hipEvent_t)done_event, s));
+  return GS_OK;
+}
+
+gs_status gs_map_info(const gs_map* m, int64_t* n, int64_t* capacity, int64_t* resident_bytes) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (n) *n = m->n;
+  if (capacity) *capacity = m->cap;
+  if (resident_bytes) *resident_bytes = m->resident;
+  return GS_OK;
+}
+
+gs_status gs_map_params(gs_map* m, float** params, float** grads, float** am, float** av, int64_t* stride) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  const int64_t pl = (int64_t)m->F * m->cap;
+  if (params) *params = m->buf;
+  if (grads) *grads = m->buf ? m->buf + pl : nullptr;
+  if (am) *am = m->buf ? m->buf + 2 * pl : nullptr;
+  if (av) *av = m->buf ? m->buf + 3 * pl : nullptr;
+  if (stride) *stride = m->cap;
+  return GS_OK;
+}
+
+gs_status gs_map_visibility(gs_map* m, uint8_t** vis) {
+  if (!m || !vis) return fail(GS_ERR_INVALID, "NULL argument");
+  *vis = m->vis;
+  return GS_OK;
+}
+
+gs_status gs_map_step_count(const gs_map* m, int64_t* t) {
+  if (!m || !t) return fail(GS_ERR_INVALID, "NULL argument");
+  *t = m->h_step;
+  return GS_OK;
+}
+
+gs_status gs_debug_last_render(gs_map* m, void* stream, const uint64_t** keys, const uint32_t** vals,
+                               int64_t* n_inst, const uint32_t** ranges, int64_t* n_tiles, const float** proj,
+                               const uint32_t** counts) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (!m->have_render) return fail(GS_ERR_STATE, "no render yet");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_ninst, 4, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
+  if (keys) *keys = (const uint64_t*)m->keys[m->sorted].ptr;
+  if (vals) *vals = (const uint32_t*)m->vals[m->sorted].ptr;
+  if (n_inst) *n_inst = m->h_pinned[0];
+  if (ranges) *ranges = (const uint32_t*)m->ranges.ptr;
+  if (n_tiles) *n_tiles = m->last_va.total_tiles;
+  if (proj) *proj = (const float*)m->rec.ptr;
+  if (counts) *counts = (const uint32_t*)m->counts.ptr;
+  return GS_OK;
+}
+
+gs_status gs_set_instance_policy(gs_map* m, int32_t sync_plan, int64_t capacity) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (capacity < 0 || capacity > (int64_t)UINT32_MAX) return fail(GS_ERR_INVALID, "capacity out of range");
+  if (capacity > m->inst_cap) {
+    hipStream_t s = nullptr;
+    for (int b = 0; b < 2; ++b) {
+      GS_TRY(ensure(m, m->keys[b], (size_t)capacity * 8, s));
+      GS_TRY(ensure(m, m->vals[b], (size_t)capacity * 4, s));
+    }
+    GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(capacity) * 4, s));
+    m->inst_cap = capacity;
+    GS_HIP(hipStreamSynchronize(s));
+  }
+  m->sync_plan = sync_plan != 0;
+  return GS_OK;
+}
+
+gs_status gs_check_overflow(gs_map* m, void* stream, int32_t* overflow) {
+  if (!m || !overflow) return fail(GS_ERR_INVALID, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_overflow, 4, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
+  *overflow = m->h_pinned[0] ? 1 : 0;
+  GS_HIP(fill_u32(m->d_overflow, 0u, 1, s));
+  return GS_OK;
+}
+
+gs_status gs_set_stage_timing(gs_map* m, int32_t enable) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  m->timing = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_stage_times(gs_map* m, void* stream, double* ms, int64_t* count) {
+  if (!m || !ms || !count) return fail(GS_ERR_INVALID, "NULL argument");
+  GS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  for (int k = 0; k < GS_NUM_STAGES; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  for (const auto& mk : m->ev_marks) {
+    float t = 0.f;
+    GS_HIP(hipEventElapsedTime(&t, m->ev_pool[mk.second], m->ev_pool[mk.second + 1]));
+    ms[mk.first] += t;
+    count[mk.first] += 1;
+  }
+  m->ev_marks.clear();
+  m->ev_used = 0;
+  return GS_OK;
+}
+
+gs_status gs_set_blend_config(gs_map* m, int32_t fwd, int32_t bwd) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (fwd != 1 || bwd != 1) return fail(GS_ERR_UNIMPLEMENTED, "only one pixel per lane is built");
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Host-side launchers of the HIP kernels (internal to libgslic).
+#pragma once
+
+#include "gs_common.h"
+
+namespace gs {
+
+constexpr int kMaxPlanes = 11 + 3 * 16;
+constexpr int kMaxExposures = 64;
+
+struct LrArg {
+  float lr[kMaxPlanes];
+};
+
+struct ExpArg {
+  int32_t n;
+  float* p[kMaxExposures];
+};
+
+// projection (project.hip)
+hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
+                           float4* rec, uint32_t* counts, hipStream_t s);
+hipError_t project_backward(int deg, const float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va,
+                            float near_z, const uint32_t* counts, float4* g2d, uint8_t* vis, hipStream_t s);
+
+// binning (binning.hip)
+int64_t scan_temp_elems(int64_t n);
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s);
+hipError_t scan_counts(const uint32_t* counts, uint32_t* offsets, int64_t n, uint32_t* temp, uint32_t* total,
+                       hipStream_t s);
+hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* offsets, int32_t N,
+                          const ViewsArg& va, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                          uint32_t* overflow, hipStream_t s);
+int64_t sort_temp_elems(int64_t cap);
+hipError_t radix_sort(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
+                      uint32_t* temp, int* which, hipStream_t s);
+hipError_t tile_ranges(const uint64_t* keys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
+                       hipStream_t s);
+
+// blending (blend.hip)
+hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                         const uint2* ranges, hipStream_t s);
+hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                          const uint2* ranges, float* g2d, hipStream_t s);
+
+// loss (loss.hip)
+int64_t loss_temp_floats(int H, int W);
+hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,
+                     float* gout, hipStream_t s);
+
+// optimiser and map maintenance (adam.hip)
+hipError_t adam_step(float* buf, int64_t cap, int32_t F, int32_t N, const uint8_t* vis, const LrArg& lr,
+                     int64_t* step, float* bc, float beta1, float beta2, float eps, const ExpArg& ea,
+                     float lr_exposure, hipStream_t s);
+hipError_t fill_u32(uint32_t* d, uint32_t val, int64_t n, hipStream_t s);
+hipError_t append_rows(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0, int64_t n, const float* means,
+                       const float* ls, const float* quats, const float* logits, const float* sh, uint8_t* vis,
+                       hipStream_t s);
+hipError_t init_points(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0, int64_t n, const float* xyz,
+                       const float* rgb, const ViewDev& V, float near_z, float logit0, uint8_t* vis,
+                       hipStream_t s);
+hipError_t copy_planes(const float* src, int64_t cap0, float* dst, int64_t cap1, int64_t n, int nplanes,
+                       hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,303 @@
+// Per-Gaussian projection: forward (Sec. III-A Eq. 1-3, SH colour, culls, tile count of
+// the footprint predicate of Sec. III-D.2) and its adjoint down to the parameters.
+//
+// One lane per Gaussian; the lane loops over the views of the batch so the parameters
+// are read once and the view-independent covariance is formed once. Parameter planes
+// are read coalesced; the per-(view, Gaussian) records are 64 B and written by the lane
+// that owns them.
+#include "gs_common.h"
+#include "kernels.h"
+
+namespace gs {
+
+template <int DEG>
+__global__ void __launch_bounds__(256)
+k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
+              float4* __restrict__ rec, uint32_t* __restrict__ counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const float m0 = P[i], m1 = P[cap + i], m2 = P[2 * cap + i];
+  const KeyGeo G = key_geometry(P[3 * cap + i], P[4 * cap + i], P[5 * cap + i], P[6 * cap + i],
+                                P[7 * cap + i], P[8 * cap + i], P[9 * cap + i]);
+  const float logit = P[10 * cap + i];
+  float sh[3 * K];
+#pragma unroll
+  for (int f = 0; f < 3 * K; ++f) sh[f] = P[(11 + f) * cap + i];
+
+  for (int v = 0; v < va.n; ++v) {
+    const ViewDev& V = va.v[v];
+    const size_t vi = (size_t)v * N + i;
+    const KeyProj kp = key_project(V, G, m0, m1, m2, logit, near_z);
+    int r[4];
+    uint32_t cnt = 0;
+    if (kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) {
+      for (int ty = r[1]; ty <= r[3]; ++ty)
+        for (int tx = r[0]; tx <= r[2]; ++tx)
+          cnt += key_tile_hit(kp.mx, kp.my, kp.A, kp.B, kp.C, kp.thr, tx, ty) ? 1u : 0u;
+    }
+    counts[vi] = cnt;
+    if (cnt == 0) continue;
+    // view-dependent colour: max(0, sum_k sh_k Y_k(dir) + 0.5)
+    float dx = m0 - V.campos[0], dy = m1 - V.campos[1], dz = m2 - V.campos[2];
+    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv;
+    dy *= inv;
+    dz *= inv;
+    float Y[K];
+    sh_basis<DEG>(dx, dy, dz, Y);
+    float col[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float acc = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc += sh[3 * k + c] * Y[k];
+      col[c] = fmaxf(acc, 0.0f);
+    }
+    float4* o = rec + vi * 4;
+    o[0] = make_float4(kp.mx, kp.my, kp.A, kp.B);
+    o[1] = make_float4(kp.C, kp.o, col[0], col[1]);
+    o[2] = make_float4(col[2], kp.zh, 0.0f, kp.thr);
+    o[3] = make_float4(__uint_as_float((uint32_t)r[0] | ((uint32_t)r[1] << 16)),
+                       __uint_as_float((uint32_t)r[2] | ((uint32_t)r[3] << 16)), 0.0f, 0.0f);
+  }
+}
+
+// Adjoint of the projection. Input: per (view, Gaussian) gradients of
+// (mean2d x, y, conic A, B, C, opacity, colour r, g, b) in 64-B records (consumed and
+// reset to zero here, so the buffer is clean for the next backward). Output: gradients
+// added to the parameter planes, summed over views; vis[i] = 1 for Gaussians with a tile
+// in some view.
+template <int DEG>
+__global__ void __launch_bounds__(256)
+k_project_bwd(const float* __restrict__ P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg va,
+              float near_z, const uint32_t* __restrict__ counts, float4* __restrict__ g2d,
+              uint8_t* __restrict__ vis) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  bool any = false;
+  for (int v = 0; v < va.n; ++v) any |= counts[(size_t)v * N + i] > 0;
+  if (!any) return;
+
+  const float mu[3] = {P[i], P[cap + i], P[2 * cap + i]};
+  const float ls[3] = {P[3 * cap + i], P[4 * cap + i], P[5 * cap + i]};
+  const float q[4] = {P[6 * cap + i], P[7 * cap + i], P[8 * cap + i], P[9 * cap + i]};
+  const float logit = P[10 * cap + i];
+  // view-independent: normalised quaternion, rotation, scales, M = R S, Sigma = M M^T
+  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const float Rq[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                       2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                       2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+  const float s[3] = {__expf(ls[0]), __expf(ls[1]), __expf(ls[2])};
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = Rq[3 * r + k] * s[k];
+  float Sg[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Sg[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+  const float op = 1.0f / (1.0f + __expf(-logit));
+
+  float gmu[3] = {0, 0, 0};
+  float gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  float glogit = 0.0f;
+  float gsh[3 * K];
+#pragma unroll
+  for (int f = 0; f < 3 * K; ++f) gsh[f] = 0.0f;
+
+  for (int v = 0; v < va.n; ++v) {
+    const size_t vi = (size_t)v * N + i;
+    if (counts[vi] == 0) continue;
+    const ViewDev& V = va.v[v];
+    const float4 ga = g2d[vi * 4 + 0], gb = g2d[vi * 4 + 1], gc = g2d[vi * 4 + 2];
+    g2d[vi * 4 + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    g2d[vi * 4 + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    g2d[vi * 4 + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float g_mx = ga.x, g_my = ga.y, g_A = ga.z, g_B = ga.w;
+    const float g_C = gb.x, g_o = gb.y;
+    const float g_col[3] = {gb.z, gb.w, gc.x};
+    const float* W = V.R;
+    const float xh = W[0] * mu[0] + W[1] * mu[1] + W[2] * mu[2] + V.t[0];
+    const float yh = W[3] * mu[0] + W[4] * mu[1] + W[5] * mu[2] + V.t[1];
+    const float zh = W[6] * mu[0] + W[7] * mu[1] + W[8] * mu[2] + V.t[2];
+    const float iz = 1.0f / zh, iz2 = iz * iz;
+    const float limx = 1.3f * (0.5f * (float)V.W / V.fx), limy = 1.3f * (0.5f * (float)V.H / V.fy);
+    const float rx = xh * iz, ry = yh * iz;
+    const bool clx = rx < -limx || rx > limx, cly = ry < -limy || ry > limy;
+    const float tx = fminf(limx, fmaxf(-limx, rx)), ty = fminf(limy, fmaxf(-limy, ry));
+    const float J00 = V.fx * iz, J02 = -V.fx * tx * iz, J11 = V.fy * iz, J12 = -V.fy * ty * iz;
+    float T0[3], T1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T0[k] = J00 * W[k] + J02 * W[6 + k];
+      T1[k] = J11 * W[3 + k] + J12 * W[6 + k];
+    }
+    float ST0[3], ST1[3];  // Sigma T0, Sigma T1
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      ST0[r] = Sg[3 * r] * T0[0] + Sg[3 * r + 1] * T0[1] + Sg[3 * r + 2] * T0[2];
+      ST1[r] = Sg[3 * r] * T1[0] + Sg[3 * r + 1] * T1[1] + Sg[3 * r + 2] * T1[2];
+    }
+    const float a = T0[0] * ST0[0] + T0[1] * ST0[1] + T0[2] * ST0[2] + 0.3f;
+    const float b = T0[0] * ST1[0] + T0[1] * ST1[1] + T0[2] * ST1[2];
+    const float c = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2] + 0.3f;
+    const float det = a * c - b * b;
+    const float id2 = 1.0f / (det * det);
+    // conic = inverse(Sigma'): gradients w.r.t. (a, b, c) of Sigma' = [[a, b], [b, c]]
+    const float g_a = (-c * c * g_A + b * c * g_B - b * b * g_C) * id2;
+    const float g_b = (2.f * b * c * g_A - (a * c + b * b) * g_B + 2.f * a * b * g_C) * id2;
+    const float g_c = (-b * b * g_A + a * b * g_B - a * a * g_C) * id2;
+    // Sigma' = T Sigma T^T: dL/dSigma (symmetric part) and dL/dT
+    //   dL/dM = 2 Psym M with Psym = g_a T0 T0^T + g_b (T0 T1^T + T1 T0^T)/2 + g_c T1 T1^T
+    float Pm[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        Pm[3 * r + k] = g_a * T0[r] * T0[k] + 0.5f * g_b * (T0[r] * T1[k] + T1[r] * T0[k]) + g_c * T1[r] * T1[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        gM[3 * r + k] += 2.f * (Pm[3 * r] * M[k] + Pm[3 * r + 1] * M[3 + k] + Pm[3 * r + 2] * M[6 + k]);
+    float gT0[3], gT1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gT0[k] = 2.f * g_a * ST0[k] + g_b * ST1[k];
+      gT1[k] = g_b * ST0[k] + 2.f * g_c * ST1[k];
+    }
+    const float gJ00 = gT0[0] * W[0] + gT0[1] * W[1] + gT0[2] * W[2];
+    const float gJ02 = gT0[0] * W[6] + gT0[1] * W[7] + gT0[2] * W[8];
+    const float gJ11 = gT1[0] * W[3] + gT1[1] * W[4] + gT1[2] * W[5];
+    const float gJ12 = gT1[0] * W[6] + gT1[1] * W[7] + gT1[2] * W[8];
+    // camera-frame mean: through J and the 2D mean
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    gz += -V.fx * iz2 * gJ00 - V.fy * iz2 * gJ11;
+    if (!clx) {
+      gx += -V.fx * iz2 * gJ02;
+      gz += 2.f * V.fx * xh * iz2 * iz * gJ02;
+    } else {
+      gz += V.fx * tx * iz2 * gJ02;
+    }
+    if (!cly) {
+      gy += -V.fy * iz2 * gJ12;
+      gz += 2.f * V.fy * yh * iz2 * iz * gJ12;
+    } else {
+      gz += V.fy * ty * iz2 * gJ12;
+    }
+    gx += g_mx * V.fx * iz;
+    gz += -g_mx * V.fx * xh * iz2;
+    gy += g_my * V.fy * iz;
+    gz += -g_my * V.fy * yh * iz2;
+    // world mean: R_cw^T
+    gmu[0] += W[0] * gx + W[3] * gy + W[6] * gz;
+    gmu[1] += W[1] * gx + W[4] * gy + W[7] * gz;
+    gmu[2] += W[2] * gx + W[5] * gy + W[8] * gz;
+    glogit += g_o * op * (1.0f - op);
+    // colour through the SH direction
+    float dv[3] = {mu[0] - V.campos[0], mu[1] - V.campos[1], mu[2] - V.campos[2]};
+    const float inv = rsqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const float d[3] = {dv[0] * inv, dv[1] * inv, dv[2] * inv};
+    float Y[K];
+    sh_basis<DEG>(d[0], d[1], d[2], Y);
+    float wsum[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wsum[k] = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float raw = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) raw += P[(11 + 3 * k + ch) * cap + i] * Y[k];
+      if (raw < 0.0f) continue;  // clamped channel: no gradient
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        gsh[3 * k + ch] += g_col[ch] * Y[k];
+        wsum[k] += g_col[ch] * P[(11 + 3 * k + ch) * cap + i];
+      }
+    }
+    if (DEG > 0) {
+      float gdx, gdy, gdz;
+      sh_basis_grad<DEG>(d[0], d[1], d[2], wsum, gdx, gdy, gdz);
+      const float dot = gdx * d[0] + gdy * d[1] + gdz * d[2];
+      gmu[0] += (gdx - dot * d[0]) * inv;
+      gmu[1] += (gdy - dot * d[1]) * inv;
+      gmu[2] += (gdz - dot * d[2]) * inv;
+    }
+  }
+  // M = R diag(s): scales and rotation
+  float gls[3], gR[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float gs_ = gM[k] * Rq[k] + gM[3 + k] * Rq[3 + k] + gM[6 + k] * Rq[6 + k];
+    gls[k] = gs_ * s[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) gR[3 * r + k] = gM[3 * r + k] * s[k];
+  }
+  // rotation from the unit quaternion, then through the normalisation
+  float gq[4];
+  gq[0] = 2.f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+  gq[1] = 2.f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.f * x * gR[4] - w * gR[5] + z * gR[6] + w * gR[7] - 2.f * x * gR[8]);
+  gq[2] = 2.f * (-2.f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] + z * gR[7] - 2.f * y * gR[8]);
+  gq[3] = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] + y * gR[5] + x * gR[6] + y * gR[7]);
+  const float qd = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+  const float unit[4] = {w, x, y, z};
+  float* g = Gp;
+  g[i] += gmu[0];
+  g[cap + i] += gmu[1];
+  g[2 * cap + i] += gmu[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[(3 + k) * cap + i] += gls[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g[(6 + k) * cap + i] += (gq[k] - qd * unit[k]) / qn;
+  g[10 * cap + i] += glogit;
+#pragma unroll
+  for (int f = 0; f < 3 * K; ++f) g[(11 + f) * cap + i] += gsh[f];
+  vis[i] = 1;
+}
+
+template <int DEG>
+static hipError_t launch_fwd(const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
+                             float4* rec, uint32_t* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_project_fwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, cap, N, va,
+                     near_z, rec, counts);
+  return hipGetLastError();
+}
+
+template <int DEG>
+static hipError_t launch_bwd(const float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va,
+                             float near_z, const uint32_t* counts, float4* g2d, uint8_t* vis,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_project_bwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, G, cap, N, va,
+                     near_z, counts, g2d, vis);
+  return hipGetLastError();
+}
+
+hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va,
+                           float near_z, float4* rec, uint32_t* counts, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  switch (deg) {
+    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, s);
+    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, s);
+    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, s);
+    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, s);
+  }
+}
+
+hipError_t project_backward(int deg, const float* P, float* G, int64_t cap, int32_t N,
+                            const ViewsArg& va, float near_z, const uint32_t* counts, float4* g2d,
+                            uint8_t* vis, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  switch (deg) {
+    case 0: return launch_bwd<0>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
+    case 1: return launch_bwd<1>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
+    case 2: return launch_bwd<2>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
+    default: return launch_bwd<3>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
+  }
+}
+
+}  // namespace gs

@@ -18,3 +18,13 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+def pytest_collection_modifyitems(config, items):
+    # slow tests (minutes of CPU) run only when GSLIC_SLOW=1
+    if os.environ.get("GSLIC_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="slow; set GSLIC_SLOW=1 to run")
+    for it in items:
+        if "slow" in it.keywords:
+            it.add_marker(skip)

@@ -1,0 +1,73 @@
+"""Shared pieces of the GPU parity tests: building maps on the device, running the oracle
+on the same seeded inputs, and the comparison bars."""
+import numpy as np
+
+import oracle
+from helpers import oview
+from paper_2404_06926_amd import scenes
+
+# Relative margins inside which the oracle (FP64 blend) marks an alpha or transmittance
+# decision as a tie the FP32 kernel may take the other way. The kernel's alpha carries a
+# relative error of a few 1e-6 (FP32 quadratic form and exp); its transmittance after k
+# layers a few 1e-6 per layer; the oracle widens the T margin by (1 + 0.2 k).
+TIE_ALPHA = 1e-5
+TIE_T = 1e-5
+IMG_TOL = 1e-4
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def gpu_map(params, deg, cap=None):
+    from paper_2404_06926_amd import gslic
+    torch = torch_mod()
+    m = gslic.GaussianMap(sh_degree=deg, capacity=cap or max(1024, params.shape[0]))
+    if params.shape[0]:
+        m.add_gaussians(torch.from_numpy(np.ascontiguousarray(params)).cuda())
+    return m
+
+
+def exposures(cams):
+    torch = torch_mod()
+    return [torch.tensor(c.exposure, device="cuda") for c in cams]
+
+
+def case(name):
+    """(params float32 [N, F], deg, cams) of a named parity case."""
+    if name == "c1":       # 10k SH0 at 256x192, L1 only, identity exposure (config 1)
+        cam = scenes.pinhole(256, 192, 200.0)
+        return scenes.frustum_gaussians(10_000, 0, cam, seed=1000), 0, [cam]
+    if name == "c3a":      # 2k SH3 at 64x48 with a random exposure and background
+        cam = scenes.pinhole(64, 48, 50.0)
+        cam.exposure = scenes.random_exposure(3000)
+        cam.bg = np.array([0.1, 0.05, 0.2], np.float32)
+        return scenes.frustum_gaussians(2000, 3, cam, seed=3000), 3, [cam]
+    if name == "ragged":   # image sizes that leave partial tiles, SH1
+        cam = scenes.pinhole(100, 75, 80.0)
+        cam.bg = np.array([0.3, 0.3, 0.3], np.float32)
+        return scenes.frustum_gaussians(3000, 1, cam, seed=77, log_scale_mean=-2.5), 1, [cam]
+    if name == "multi":    # three uneven views over one SH2 map
+        base = scenes.pinhole(160, 96, 120.0)
+        params = scenes.frustum_gaussians(4000, 2, base, seed=55)
+        cams = [base, scenes.pinhole(97, 131, 90.0), scenes.pinhole(64, 40, 50.0)]
+        cams[1].R = scenes.axis_angle([0.0, 0.05, 0.02]).astype(np.float32)
+        cams[1].t = np.array([0.2, -0.1, 0.3], np.float32)
+        cams[1].exposure = scenes.random_exposure(9)
+        cams[2].t = np.array([-0.3, 0.0, -0.5], np.float32)
+        return params, 2, cams
+    raise KeyError(name)
+
+
+def oracle_forward(params, deg, cams, fp64=False):
+    views = [oview(c) for c in cams]
+    projs, bins, rend = oracle.forward(params, deg, views, fp64=fp64, tie_alpha=TIE_ALPHA, tie_T=TIE_T)
+    return views, projs, bins, rend
+
+
+def grad_close(gpu, ref, rel=1e-3, floor=1e-3):
+    """Per element |gpu - ref| <= rel * max(|ref|, floor * max|ref| of the column)."""
+    scale = np.maximum(np.abs(ref), floor * np.abs(ref).max(axis=0, keepdims=True))
+    err = np.abs(gpu - ref) / np.maximum(scale, 1e-30)
+    return err <= rel, err

@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded
+inputs. Keys, sort order, tile counts and the FP32 key-path projection are bit-exact;
+images within 1e-4 away from threshold ties; gradients within 1e-3 relative."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import (IMG_TOL, TIE_ALPHA, TIE_T, case, exposures, gpu_map, grad_close, oracle_forward,
+                        torch_mod)
+from paper_2404_06926_amd import gslic, scenes
+
+pytestmark = pytest.mark.gpu
+CASES = ["c1", "c3a", "ragged", "multi"]
+
+
+def _run_gpu(params, deg, cams):
+    m = gpu_map(params, deg)
+    frames = m.render(cams, exposures(cams))
+    torch_mod().cuda.synchronize()
+    return m, frames
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_projection_keys_and_sort_bit_exact(name):
+    params, deg, cams = case(name)
+    print(f"case {name}: N={params.shape[0]} deg={deg} views={len(cams)}", flush=True)
+    m, frames = _run_gpu(params, deg, cams)
+    dbg = m.debug_last_render()
+    views, projs, bins, rend = oracle_forward(params, deg, cams)
+    for v, pr in enumerate(projs):
+        cnt = dbg["counts"][v].cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(cnt, pr["count"])
+        vis = pr["count"] > 0
+        rec = dbg["proj"][v].cpu().numpy()[vis]
+        f32 = lambda a: np.asarray(a, np.float64).astype(np.float32)
+        for col, ref in [(0, pr["mean2d"][vis, 0]), (1, pr["mean2d"][vis, 1]), (2, pr["conic"][vis, 0]),
+                         (3, pr["conic"][vis, 1]), (4, pr["conic"][vis, 2]), (5, pr["opacity"][vis]),
+                         (9, pr["depth"][vis]), (11, pr["thr"][vis])]:
+            np.testing.assert_array_equal(rec[:, col].view(np.uint32), f32(ref).view(np.uint32), err_msg=f"col {col}")
+        rect = rec[:, 12:14].view(np.uint32)
+        r = pr["rect"][vis].astype(np.uint32)
+        np.testing.assert_array_equal(rect[:, 0], r[:, 0] | (r[:, 1] << 16))
+        np.testing.assert_array_equal(rect[:, 1], r[:, 2] | (r[:, 3] << 16))
+        np.testing.assert_allclose(rec[:, 6:9], pr["colour"][vis], atol=3e-6)
+    assert dbg["n_inst"] == bins["key"].shape[0]
+    np.testing.assert_array_equal(dbg["keys"].cpu().numpy().view(np.uint64), bins["key"])
+    np.testing.assert_array_equal(dbg["vals"].cpu().numpy().view(np.uint32), bins["local_val"])
+    np.testing.assert_array_equal(dbg["ranges"].cpu().numpy().astype(np.int64), bins["ranges"])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_render_matches_oracle(name):
+    params, deg, cams = case(name)
+    print(f"case {name}", flush=True)
+    m, frames = _run_gpu(params, deg, cams)
+    views, projs, bins, rend = oracle_forward(params, deg, cams)
+    for f, r in zip(frames, rend):
+        ok = r["tie"] == 0
+        assert ok.mean() > 0.99, f"too many tie pixels: {(~ok).sum()}"
+        img = f.rgb.cpu().numpy()
+        err = np.abs(img - r["out"])[:, ok]
+        assert err.max() <= IMG_TOL, err.max()
+        np.testing.assert_allclose(f.final_T.cpu().numpy()[ok], r["T_final"][ok], atol=2e-5)
+        np.testing.assert_array_equal(f.n_contrib.cpu().numpy()[ok], r["n_contrib"][ok])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_backward_matches_oracle_adjoint(name):
+    torch = torch_mod()
+    params, deg, cams = case(name)
+    print(f"case {name}", flush=True)
+    m, frames = _run_gpu(params, deg, cams)
+    rng = np.random.default_rng(11)
+    gouts = [rng.normal(size=(3, c.height, c.width)) for c in cams]
+    gexp = [torch.zeros(12, device="cuda") for _ in cams]
+    m.render_backward([torch.tensor(g, dtype=torch.float32, device="cuda") for g in gouts], gexp)
+    torch.cuda.synchronize()
+    views, projs, bins, rend = oracle_forward(params, deg, cams)
+    gp, gE, tie = oracle.backward(params, deg, views, projs, bins, gouts, TIE_ALPHA, TIE_T)
+    vis_ref = np.zeros(params.shape[0], bool)
+    for pr in projs:
+        vis_ref |= pr["count"] > 0
+    np.testing.assert_array_equal(m.visibility().cpu().numpy().astype(bool), vis_ref)
+    g_gpu = m.grads().cpu().numpy().T
+    sel = vis_ref & (tie == 0)
+    assert sel.sum() > 0.9 * vis_ref.sum()
+    ok, err = grad_close(g_gpu[sel], gp[sel])
+    frac = ok.mean()
+    print(f"grad elements within bar: {frac:.6f}, worst {err.max():.3e}, tie Gaussians {int((tie > 0).sum())}")
+    assert frac >= 0.999, (frac, err.max())
+    for k, c in enumerate(cams):
+        np.testing.assert_allclose(gexp[k].cpu().numpy(), gE[k], rtol=1e-3,
+                                   atol=1e-4 * np.abs(gE[k]).max())
+
+
+def test_loss_matches_oracle():
+    torch = torch_mod()
+    rng = np.random.default_rng(3)
+    for (H, W) in [(48, 64), (75, 100), (192, 256)]:
+        gt = scenes.smooth_image(5, H, W)
+        out = np.clip(gt + rng.normal(0, 0.05, gt.shape), 0, 1).astype(np.float32)
+        m = gpu_map(np.zeros((0, 14), np.float32), 0)
+        lo, g = m.loss(torch.tensor(out, device="cuda"), torch.tensor(gt, device="cuda"), 0.2)
+        L, gref, _ = oracle.loss(out.astype(np.float64), gt.astype(np.float64), 0.2)
+        np.testing.assert_allclose(lo.item(), L, rtol=2e-5)
+        ok, err = grad_close(g.cpu().numpy().reshape(-1, 1), gref.reshape(-1, 1))
+        assert ok.mean() >= 0.999, (ok.mean(), err.max())
+
+
+def test_sparse_adam_matches_oracle():
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    m = gpu_map(params, deg)
+    n, F = params.shape
+    rng = np.random.default_rng(2)
+    g = rng.normal(0, 1e-2, (n, F)).astype(np.float32)
+    vis = (rng.random(n) < 0.6).astype(np.uint8)
+    g[vis == 0] = 0
+    m.grads().copy_(torch.tensor(g.T, device="cuda"))
+    m.visibility().copy_(torch.tensor(vis, device="cuda"))
+    st = gslic.identity_exposure_state()
+    st[12:24] = torch.tensor(rng.normal(0, 1e-2, 12), dtype=torch.float32)
+    st_ref = st.cpu().numpy().astype(np.float64)
+    m.adam_step([st])
+    d = m.desc
+    lr = np.array([d.lr_mean] * 3 + [d.lr_log_scale] * 3 + [d.lr_quat] * 4 + [d.lr_opacity] + [d.lr_sh_dc] * 3
+                  + [d.lr_sh_rest] * (F - 14), np.float64)
+    p1, g1, m1, v1 = oracle.adam(params, g, np.zeros((n, F)), np.zeros((n, F)), vis, lr, d.beta1, d.beta2, d.eps, 1)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(m.params().cpu().numpy().T, p1, rtol=1e-6, atol=1e-7)
+    np.testing.assert_array_equal(m.params().cpu().numpy().T[vis == 0], params[vis == 0])
+    mm, vv = m.adam_moments()
+    np.testing.assert_allclose(mm.cpu().numpy().T, m1, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(vv.cpu().numpy().T, v1, rtol=1e-5, atol=1e-15)
+    assert (m.grads().cpu().numpy() == 0).all()
+    assert (m.visibility().cpu().numpy() == 0).all()
+    e1 = oracle.adam(st_ref[None, :12], st_ref[None, 12:24], np.zeros((1, 12)), np.zeros((1, 12)),
+                     np.ones(1, np.uint8), d.lr_exposure, d.beta1, d.beta2, d.eps, 1)
+    np.testing.assert_allclose(st[:12].cpu().numpy(), e1[0][0], rtol=1e-6, atol=1e-7)
+    # second step with a new gradient: moments carry over, t = 2
+    g2 = rng.normal(0, 1e-2, (n, F)).astype(np.float32)
+    g2[vis == 0] = 0
+    m.grads().copy_(torch.tensor(g2.T, device="cuda"))
+    m.visibility().copy_(torch.tensor(vis, device="cuda"))
+    m.adam_step([])
+    p2, _, _, _ = oracle.adam(p1, g2, m1, v1, vis, lr, d.beta1, d.beta2, d.eps, 2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(m.params().cpu().numpy().T, p2, rtol=1e-6, atol=1e-7)
+
+
+def test_batched_equals_per_view_launches():
+    torch = torch_mod()
+    params, deg, cams = case("multi")
+    m = gpu_map(params, deg)
+    ex = exposures(cams)
+    batched = m.render(cams, ex)
+    rng = np.random.default_rng(5)
+    gouts = [torch.tensor(rng.normal(size=(3, c.height, c.width)), dtype=torch.float32, device="cuda") for c in cams]
+    m.render_backward(gouts)
+    gb = m.grads().clone()
+    m.grads().zero_()
+    m.visibility().zero_()
+    for k, c in enumerate(cams):
+        single = m.render([c], [ex[k]])
+        assert torch.equal(single[0].rgb, batched[k].rgb)
+        assert torch.equal(single[0].n_contrib, batched[k].n_contrib)
+        m.render_backward([gouts[k]])
+    ok, err = grad_close(m.grads().cpu().numpy().T, gb.cpu().numpy().T, rel=1e-4)
+    assert ok.mean() > 0.999, err.max()
+
+
+def test_autograd_function_against_fp64_adjoint():
+    # The torch.autograd.Function around render / render_backward returns gradients that
+    # match the oracle's FP64 adjoint, itself pinned by FP64 central differences.
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    m = gpu_map(params, deg)
+    ex = [e.clone().requires_grad_(True) for e in exposures(cams)]
+    imgs, p = gslic.render_autograd(m, cams, ex)
+    w = np.random.default_rng(8).normal(size=(3, cams[0].height, cams[0].width))
+    L = (imgs[0] * torch.tensor(w, dtype=torch.float32, device="cuda")).sum()
+    gp_t, ge_t = torch.autograd.grad(L, [p, ex[0]])
+    views, projs, bins, rend = oracle_forward(params, deg, cams)
+    gp, gE, tie = oracle.backward(params, deg, views, projs, bins, [w], TIE_ALPHA, TIE_T)
+    sel = (projs[0]["count"] > 0) & (tie == 0)
+    ok, err = grad_close(gp_t.cpu().numpy().T[sel], gp[sel])
+    assert ok.mean() >= 0.999, err.max()
+    np.testing.assert_allclose(ge_t.cpu().numpy(), gE[0], rtol=1e-3, atol=1e-4 * np.abs(gE[0]).max())
+
+
+def test_empty_and_degenerate_maps():
+    torch = torch_mod()
+    cam = scenes.pinhole(70, 50, 60.0)
+    cam.bg = np.array([0.2, 0.4, 0.6], np.float32)
+    cam.exposure = scenes.random_exposure(4)
+    A, b = cam.exposure.reshape(3, 4)[:, :3], cam.exposure.reshape(3, 4)[:, 3]
+    expect = (A.astype(np.float64) @ cam.bg + b)[:, None, None]
+    # no Gaussians at all
+    m = gpu_map(np.zeros((0, 14), np.float32), 0)
+    f = m.render([cam], exposures([cam]))[0]
+    np.testing.assert_allclose(f.rgb.cpu().numpy(), np.broadcast_to(expect, (3, 50, 70)), atol=1e-6)
+    m.render_backward([torch.ones(3, 50, 70, device="cuda")])
+    m.adam_step([])
+    # every Gaussian behind the camera, transparent or with a zero quaternion
+    p = scenes.frustum_gaussians(500, 0, cam, seed=2)
+    p[:100, 2] = -p[:100, 2]
+    p[100:200, 10] = -40.0
+    p[200:300, 6:10] = 0.0
+    p[300:, 2] = 0.1
+    m = gpu_map(p, 0)
+    f = m.render([cam], exposures([cam]))[0]
+    np.testing.assert_allclose(f.rgb.cpu().numpy(), np.broadcast_to(expect, (3, 50, 70)), atol=1e-6)
+    assert m.debug_last_render()["n_inst"] == 0
+    m.render_backward([torch.ones(3, 50, 70, device="cuda")])
+    assert torch.isfinite(m.grads()).all()
+    # one Gaussian covering the whole image
+    big = scenes.frustum_gaussians(1, 0, cam, seed=3)
+    big[0, 0:3] = [0.0, 0.0, 3.0]
+    big[0, 3:6] = np.log(2.0)
+    m = gpu_map(big, 0)
+    f = m.render([cam], exposures([cam]))[0]
+    views, projs, bins, rend = oracle_forward(big, 0, [cam])
+    ok = rend[0]["tie"] == 0
+    assert np.abs(f.rgb.cpu().numpy() - rend[0]["out"])[:, ok].max() <= IMG_TOL
+
+
+def test_capacity_growth_keeps_rows():
+    torch = torch_mod()
+    cam = scenes.pinhole(64, 48, 50.0)
+    p = scenes.frustum_gaussians(5000, 1, cam, seed=6)
+    from paper_2404_06926_amd import gslic as g
+    m = g.GaussianMap(sh_degree=1, capacity=1000)
+    for a, b in [(0, 700), (700, 2500), (2500, 5000)]:
+        m.add_gaussians(torch.tensor(p[a:b], device="cuda"))
+    n, cap, res = m.info()
+    assert n == 5000 and cap >= 5000
+    np.testing.assert_array_equal(m.params().cpu().numpy().T, p)
+    f = m.render([cam])[0]
+    views, projs, bins, rend = oracle_forward(p, 1, [cam])
+    ok = rend[0]["tie"] == 0
+    assert np.abs(f.rgb.cpu().numpy() - rend[0]["out"])[:, ok].max() <= IMG_TOL
+
+
+def test_invalid_arguments_leave_map_unchanged():
+    torch = torch_mod()
+    cam = scenes.pinhole(64, 48, 50.0)
+    p = scenes.frustum_gaussians(300, 0, cam, seed=6)
+    m = gpu_map(p, 0)
+    with pytest.raises(gslic.GsError) as e:
+        m.render_backward([torch.zeros(3, 48, 64, device="cuda")])
+    assert e.value.code == gslic.GS_ERR_STATE
+    bad = scenes.pinhole(64, 48, 50.0)
+    bad.width = 0
+    with pytest.raises(gslic.GsError) as e:
+        m.render([bad])
+    assert e.value.code == gslic.GS_ERR_INVALID
+    with pytest.raises(gslic.GsError) as e:
+        m.render([cam] * 17)
+    assert e.value.code == gslic.GS_ERR_CAPACITY
+    np.testing.assert_array_equal(m.params().cpu().numpy().T, p)
+    assert m.n == 300

@@ -213,3 +213,15 @@ def test_multi_view_tiles_are_consecutive():
     for a, b in zip(rend, single):
         np.testing.assert_array_equal(a["out"], b["out"])
     assert bins["n_tiles"] == views[0].n_tiles + views[1].n_tiles
+
+
+def test_sampled_pixels_equal_full_render():
+    cam = scenes.pinhole(96, 64, 75.0)
+    params = scenes.frustum_gaussians(1500, 1, cam, seed=12)
+    v = oview(cam)
+    projs, bins, rend = oracle.forward(params, 1, [v])
+    pix = np.random.default_rng(0).choice(96 * 64, 300, replace=False)
+    s = oracle.render_pixels(projs, [v], bins, 0, pix)
+    np.testing.assert_array_equal(s["out"], rend[0]["out"].reshape(3, -1)[:, pix].T)
+    np.testing.assert_array_equal(s["T_final"], rend[0]["T_final"].reshape(-1)[pix])
+    np.testing.assert_array_equal(s["n_contrib"], rend[0]["n_contrib"].reshape(-1)[pix])

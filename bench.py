@@ -1,12 +1,21 @@
 """Mapping-iteration throughput on one MI355X.
 
-One step = one optimisation iteration of the Gaussian map on one keyframe: project, bin,
-sort, blend (with exposure), L1 + D-SSIM loss, backward, sparse Adam (Gaussians and the
-keyframe's exposure). Workload: 1M Gaussians volume-uniform at 2-20 m in the frustum of a
-1280x720 pinhole camera (f = 1000), SH degree 3, target = render of the same map with
-means jittered by N(0, 5 cm). Inputs are synthetic and resident in HBM before timing.
+One step = one optimisation iteration of the Gaussian map: project, bin, sort, blend (with
+exposure), L1 + D-SSIM loss, backward, sparse Adam (Gaussians and exposures).
 
-Prints one JSON line. `--gpus N` with N > 1 exits: this build runs on one GPU.
+Default workload (the headline metric): 1M Gaussians volume-uniform at 2-20 m in the
+frustum of a 1280x720 pinhole camera (f = 1000), SH degree 3, one keyframe per step,
+target = render of the same map with means jittered by N(0, 5 cm). The step is captured
+as a HIP graph and replayed; a second timed region runs the same steps eagerly with HIP
+events around every stage for the per-kernel durations.
+
+--workload batch8: 1M Gaussians (SH0) and 8 keyframes of uneven size (640x400, 960x600,
+1280x720, 1440x1080, each twice) per step, batched in one launch sequence and captured,
+against the plain path that launches the same sequence once per view and takes one Adam
+step over the summed gradients.
+
+Inputs are synthetic and resident in HBM before timing. Prints one JSON line.
+`--gpus N` with N > 1 exits: this build runs on one GPU.
 """
 import argparse
 import json
@@ -31,12 +40,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(n, deg, W, H, seed=2024):
+def headline_workload(n, deg, W, H, seed=2024):
     from paper_2404_06926_amd import scenes
     cam = scenes.pinhole(W, H, 1000.0 * W / 1280.0)
     params = scenes.frustum_gaussians(n, deg, cam, seed=seed)
     target_params = scenes.jitter_means(params, 0.05, seed)
-    return cam, params, target_params
+    return [cam], params, target_params
+
+
+def batch_workload(n, seed=3003):
+    from paper_2404_06926_amd import scenes
+    ref = scenes.pinhole(1280, 720, 1000.0)
+    params = scenes.frustum_gaussians(n, 0, ref, seed=seed)
+    target_params = scenes.jitter_means(params, 0.05, seed)
+    return scenes.batch_views(seed, 8), params, target_params
 
 
 def cpu_baseline(params, target_params, deg, cam, lam):
@@ -62,18 +79,41 @@ def cpu_baseline(params, target_params, deg, cam, lam):
                        f"{t_target:.1f} s not counted)")
 
 
+class StepBuffers:
+    def __init__(self, torch, gslic, cams, dev):
+        self.frames = [gslic.Frame(torch.empty(3, c.height, c.width, device=dev), torch.empty(c.height, c.width, device=dev),
+                                   torch.empty(c.height, c.width, dtype=torch.int32, device=dev)) for c in cams]
+        self.expo = [gslic.identity_exposure_state(dev) for _ in cams]
+        self.grads = [torch.empty(3, c.height, c.width, device=dev) for c in cams]
+        self.loss = torch.empty(len(cams), device=dev)
+
+
+def timed(torch, fn, steps):
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["headline", "batch8"], default="headline")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--sh", type=int, default=3)
     ap.add_argument("--width", type=int, default=1280)
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--lam", type=float, default=0.2)
+    ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device-to-device (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the mapping step is not "
@@ -84,87 +124,93 @@ def main():
     from paper_2404_06926_amd import gslic
 
     dev = torch.device("cuda:0")
-    log(f"building workload: n={args.n} sh={args.sh} {args.width}x{args.height}")
-    cam, params, target_params = build_workload(args.n, args.sh, args.width, args.height)
-    H, W = args.height, args.width
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload == "batch8":
+        args.sh = 0
+        cams, params, target_params = batch_workload(args.n)
+    else:
+        cams, params, target_params = headline_workload(args.n, args.sh, args.width, args.height)
+    log(f"workload {args.workload}: n={args.n} sh={args.sh} views={[(c.width, c.height) for c in cams]}")
 
-    # target image from the jittered map (outside the timed region)
+    # targets: renders of the jittered map (outside the timed regions)
     tmap = gslic.GaussianMap(sh_degree=args.sh, capacity=args.n)
     tmap.add_gaussians(torch.from_numpy(target_params).to(dev))
-    target = tmap.render([cam])[0].rgb.clone()
+    targets = [f.rgb.clone() for f in tmap.render(cams)]
     tmap.close()
     del tmap
 
     m = gslic.GaussianMap(sh_degree=args.sh, capacity=args.n)
     m.add_gaussians(torch.from_numpy(params).to(dev))
-    expo = gslic.identity_exposure_state(dev)
-    frame = gslic.Frame(torch.empty(3, H, W, device=dev), torch.empty(H, W, device=dev),
-                        torch.empty(H, W, dtype=torch.int32, device=dev))
-    loss_buf = torch.empty(1, device=dev)
-    grad_buf = torch.empty(3, H, W, device=dev)
+    B = StepBuffers(torch, gslic, cams, dev)
 
     def step():
-        m.render([cam], [expo], frames=[frame])
-        m.loss(frame.rgb, target, args.lam, loss_out=loss_buf, grad_out=grad_buf)
-        m.render_backward([grad_buf], [expo[12:24]])
-        m.adam_step([expo])
+        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
 
-    # first step plans the instance buffers; then no host wait inside the step
-    step()
+    step()  # plans the instance buffers
     torch.cuda.synchronize()
     n_inst0 = m.debug_last_render()["n_inst"]
     m.set_instance_policy(False, int(n_inst0 * 1.5) + 65536)
-    log(f"instances {n_inst0}; warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    if m.check_overflow():
-        raise RuntimeError("instance buffer overflow during warmup")
-    m.set_stage_timing(not args.no_stage_timing)
-    m.stage_times()  # reset
 
-    log(f"timing {args.steps} steps")
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+    # eager timed region with per-stage HIP events
+    m.set_stage_timing(True)
+    m.stage_times()
+    log(f"instances {n_inst0}; eager timed region ({args.steps} steps)")
+    ms_eager = timed(torch, step, args.steps)
     stages = m.stage_times()
-    if m.check_overflow():
-        raise RuntimeError("instance buffer overflow during the timed steps")
     m.set_stage_timing(False)
 
-    # work counts of the last step (outside the timed region)
+    # captured step, replayed
+    graph = None
+    ms_graph = None
+    if not args.eager:
+        graph = m.capture_step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+        for _ in range(args.warmup):
+            graph.launch()
+        log(f"graph timed region ({args.steps} steps)")
+        ms_graph = timed(torch, graph.launch, args.steps)
+    if m.check_overflow():
+        raise RuntimeError("instance buffer overflow during the timed steps")
+    ms = ms_graph if ms_graph is not None else ms_eager
+
+    # work counts of the last step (outside the timed regions)
     dbg = m.debug_last_render()
     n_inst = dbg["n_inst"]
-    counts = dbg["counts"][0]
-    n_vis = int((counts > 0).sum().item())
-    pairs = int(frame.n_contrib.to(torch.int64).sum().item())
+    n_vis = int((dbg["counts"] > 0).sum().item())
+    pairs = sum(int(f.n_contrib.to(torch.int64).sum().item()) for f in B.frames)
     F = 11 + 3 * (args.sh + 1) ** 2
     T_total = dbg["n_tiles"]
-    P = W * H
-    sort_passes = (32 + max(1, int(np.ceil(np.log2(T_total)))) + 7) // 8
+    P = sum(c.width * c.height for c in cams)
+    tile_passes = (int(np.ceil(np.log2(T_total + 1))) + 7) // 8
+    V = len(cams)
 
     per = {k: (v[0] / max(v[1], 1)) for k, v in stages.items()}
-    # algorithmic work per launch of each stage (bytes or FLOPs), see the design doc
+    # algorithmic work per launch of each stage (bytes or FLOPs); per-unit figures in the design doc
     work = {
-        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * n_vis + 64.0 * n_vis + 4.0 * args.n),
-        "scan": ("hbm", 8.0 * args.n),
-        "duplicate": ("hbm", 40.0 * n_vis + 12.0 * n_inst),
-        "sort": ("hbm", sort_passes * 32.0 * n_inst),
-        "ranges": ("hbm", 8.0 * n_inst + 8.0 * T_total),
+        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + (64.0 + 12.0) * n_vis + 12.0 * V * args.n),
+        "depth_sort": ("hbm", 4 * 24.0 * V * args.n),
+        "scan": ("hbm", 12.0 * V * args.n),
+        "duplicate": ("hbm", 72.0 * n_vis + 8.0 * n_inst),
+        "sort": ("hbm", tile_passes * 20.0 * n_inst),
+        "ranges": ("hbm", 4.0 * n_inst + 8.0 * T_total),
         "blend": ("alu", FWD_FLOPS_PER_PAIR * float(pairs)),
-        "loss": ("hbm", 24.0 * P + 36.0 * P + 60.0 * P + 12.0 * P),
+        "loss": ("hbm", 132.0 * P),
         "blend_backward": ("alu", BWD_FLOPS_PER_PAIR * float(pairs)),
-        "project_backward": ("hbm", 4.0 * F * n_vis * 2 + 64.0 * n_vis * 2 + 4.0 * args.n),
+        "project_backward": ("hbm", 4.0 * F * n_vis * 3 + 96.0 * n_vis + 4.0 * V * args.n),
         "adam": ("hbm", 32.0 * F * n_vis),
     }
-    dom = max(per, key=lambda k: per[k]) if not args.no_stage_timing else "blend_backward"
+    dom = max(per, key=lambda k: per[k])
     bound, amount = work[dom]
-    dur_s = per[dom] * 1e-3 if per[dom] > 0 else float("nan")
+    dur_s = per[dom] * 1e-3
     if bound == "hbm":
         achieved, peak, unit = amount / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
@@ -185,17 +231,44 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.n} Gaussians, SH{args.sh}, one {W}x{H} view (f={1000.0 * W / 1280:.0f}), "
-                               f"loss 0.8 L1 + 0.2 D-SSIM, sparse Adam", "n_gaussians": args.n,
-                   "sh_degree": args.sh, "width": W, "height": H, "views_per_step": 1},
+        "config": {"workload": (f"{args.n} Gaussians, SH{args.sh}, "
+                                + ", ".join(f"{c.width}x{c.height}" for c in cams)
+                                + f" per step, loss 0.8 L1 + 0.2 D-SSIM, sparse Adam"),
+                   "n_gaussians": args.n, "sh_degree": args.sh, "views_per_step": V,
+                   "timing": "graph replay" if ms_graph is not None else "eager"},
         "roofline": roof,
+        "eager_ms_per_step": ms_eager,
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
-        "counts": {"visible": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total},
+        "counts": {"visible_pairs": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total},
     }
-    if not args.no_cpu_baseline:
+
+    if args.workload == "batch8":
+        # plain: the same views launched one at a time, gradients summed, one Adam step
+        Bp = StepBuffers(torch, gslic, cams, dev)
+
+        def plain():
+            for k, c in enumerate(cams):
+                m.render([c], [Bp.expo[k]], frames=[Bp.frames[k]])
+                m.loss(Bp.frames[k].rgb, targets[k], args.lam, loss_out=Bp.loss[k:k + 1], grad_out=Bp.grads[k])
+                m.render_backward([Bp.grads[k]], [Bp.expo[k][12:24]])
+            m.adam_step(Bp.expo)
+
+        for _ in range(args.warmup):
+            plain()
+        ms_plain = timed(torch, plain, args.steps)
+        if m.check_overflow():
+            raise RuntimeError("instance buffer overflow in the plain path")
+        result["plain_ms_per_step"] = ms_plain
+        result["batched_over_plain"] = ms_plain / ms
+        result["batched_eager_over_plain"] = ms_plain / ms_eager
+        result["metric"] = "mapping iters/s, 8 uneven keyframes per step (batched vs one view per launch)"
+
+    if graph is not None:
+        graph.close()
+    if not args.no_cpu_baseline and args.workload == "headline":
         log("cpu baseline (oracle)")
         try:
-            result["cpu_baseline"] = cpu_baseline(params, target_params, args.sh, cam, args.lam)
+            result["cpu_baseline"] = cpu_baseline(params, target_params, args.sh, cams[0], args.lam)
         except Exception as e:  # report, never fail the GPU result
             result["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(result), flush=True)

@@ -82,7 +82,8 @@ typedef struct {
   int32_t width, height;     /* pixels, 1..16384 each */
   float bg[3];               /* background colour added behind the Gaussians */
   const float* exposure;     /* device float[12]: 3x4 [A | b] row-major; out = A c + b
-                                (Sec. III-C.3). NULL = identity. */
+                                (Sec. III-C.3). NULL = identity. Read by gs_render and by
+                                the gs_render_backward that follows: keep it valid until then. */
 } gs_view;
 
 /* Per-view outputs of gs_render (all device, caller-owned, H*W pixels).
@@ -165,6 +166,38 @@ gs_status gs_submit_keyframe(gs_map* map, const gs_view* view, const float* imag
                              int32_t iters, int32_t window, float lambda, float o_init,
                              void* done_event, void* stream);
 
+/* One mapping step over n_views keyframes of one map (Sec. III-C.3): one batched
+ * gs_render, the Eq. 9 loss of every view against targets[v] (device float[3][H][W]),
+ * gs_render_backward, and gs_adam_step over the Gaussians and the views' exposures.
+ * exposure_states[v] (device float[48], see gs_adam_step) supplies the exposure of view v
+ * (it replaces views[v].exposure) and receives its gradient; frames[v] receive the
+ * renders; dl_drgb[v] (device float[3][H][W]) holds the image gradient; loss_dev (device
+ * float[n_views]) receives each view's loss. */
+gs_status gs_step(gs_map* map, int32_t n_views, const gs_view* views, const gs_frame* frames,
+                  const float* const* targets, float lambda, float* const* exposure_states,
+                  float* const* dl_drgb, float* loss_dev, void* stream);
+
+/* gs_step runs the projection backward and the Adam update of each Gaussian row in one
+ * kernel (enable = 1, the default): the step's gradient is complete after its backward,
+ * so the gradient planes are neither written nor read back; gradients accumulated by
+ * earlier gs_render_backward calls are included and cleared as gs_adam_step would.
+ * enable = 0 runs gs_render_backward then gs_adam_step. Both give the same update. */
+gs_status gs_set_fused_step(gs_map* map, int32_t enable);
+
+/* A captured mapping step (HIP graph). gs_capture_step records the kernels gs_step would
+ * enqueue, with the same arguments, into a graph without running them. Requirements: the
+ * map's instance policy has sync_plan = 0 (no host wait inside the step), and an eager
+ * gs_step with the same views has sized the workspace (capture never allocates; it fails
+ * with GS_ERR_STATE otherwise). Every pointer passed is baked into the graph and must stay
+ * valid while it is used; the map must not grow. Each gs_launch_step performs one more
+ * step (the Adam step count lives on the device). */
+typedef struct gs_step_graph gs_step_graph;
+gs_status gs_capture_step(gs_map* map, int32_t n_views, const gs_view* views, const gs_frame* frames,
+                          const float* const* targets, float lambda, float* const* exposure_states,
+                          float* const* dl_drgb, float* loss_dev, void* stream, gs_step_graph** out);
+gs_status gs_launch_step(gs_step_graph* graph, void* stream);
+gs_status gs_destroy_step(gs_step_graph* graph);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* gs_last_error(void);
 
@@ -184,8 +217,10 @@ gs_status gs_map_visibility(gs_map* map, uint8_t** vis);
 gs_status gs_map_step_count(const gs_map* map, int64_t* t);
 
 /* Device views of the last gs_render's intermediate results, valid until the next render:
- *   keys      uint64[n_inst]  sorted keys (global tile << 32 | float bits of depth)
- *   vals      uint32[n_inst]  Gaussian index of each sorted key
+ *   tiles     uint32[n_inst]  global tile id of each instance, in blend order (tile, then
+ *                             depth, then Gaussian index); the sort key of instance k is
+ *                             tiles[k] << 32 | float bits of its Gaussian's depth
+ *   vals      uint32[n_inst]  Gaussian index of each instance
  *   ranges    uint32[2 * n_tiles] [start, end) of each global tile in the sorted list
  *   proj      float[16 * n_views * n]  per (view, Gaussian) record, view-major:
  *             mean2d x, y, conic A, B, C, opacity, colour r, g, b, depth, unused,
@@ -193,7 +228,7 @@ gs_status gs_map_step_count(const gs_map* map, int64_t* t);
  *             bits), 2 unused; written only where the tile count is > 0
  *   counts    uint32[n_views * n]  tiles reached by each (view, Gaussian), view-major
  * n_inst is read back from the device (this call synchronises `stream`). */
-gs_status gs_debug_last_render(gs_map* map, void* stream, const uint64_t** keys,
+gs_status gs_debug_last_render(gs_map* map, void* stream, const uint32_t** tiles,
                                const uint32_t** vals, int64_t* n_inst, const uint32_t** ranges,
                                int64_t* n_tiles, const float** proj, const uint32_t** counts);
 
@@ -214,19 +249,28 @@ gs_status gs_check_overflow(gs_map* map, void* stream, int32_t* overflow);
  * Stage order: GS_STAGE_* below. */
 enum {
   GS_STAGE_PROJECT = 0,       /* per-Gaussian projection and tile count */
-  GS_STAGE_SCAN = 1,          /* exclusive scan of tile counts */
-  GS_STAGE_DUPLICATE = 2,     /* (tile, depth) keys of every instance */
-  GS_STAGE_SORT = 3,          /* radix sort of the keys */
+  GS_STAGE_SCAN = 1,          /* exclusive scan of tile counts in depth order */
+  GS_STAGE_DUPLICATE = 2,     /* tile id of every instance, emitted in depth order */
+  GS_STAGE_SORT = 3,          /* stable radix sort of the instances by tile */
   GS_STAGE_RANGES = 4,        /* per-tile [start, end) */
   GS_STAGE_BLEND = 5,         /* forward blend */
   GS_STAGE_LOSS = 6,          /* L1 + D-SSIM and its gradient */
   GS_STAGE_BLEND_BACKWARD = 7,
   GS_STAGE_PROJECT_BACKWARD = 8,
   GS_STAGE_ADAM = 9,
-  GS_NUM_STAGES = 10
+  GS_STAGE_DEPTH_SORT = 10,   /* radix sort of (view, Gaussian) pairs by depth */
+  GS_NUM_STAGES = 11
 };
 gs_status gs_set_stage_timing(gs_map* map, int32_t enable);
 gs_status gs_stage_times(gs_map* map, void* stream, double* ms, int64_t* count);
+
+/* Deterministic backward (enable = 1): the backward blend writes every instance's
+ * gradient to its own record with a fixed-order reduction over the tile's waves, and the
+ * projection backward adds a Gaussian's records in emission order; the exposure gradient
+ * is reduced over tiles in tile order. Results then do not depend on scheduling (bit-equal
+ * across runs and concurrent work), at the cost of 48 B per instance and extra traffic.
+ * Default 0: wave-reduced float atomics. Takes effect from the next gs_render. */
+gs_status gs_set_deterministic(gs_map* map, int32_t enable);
 
 /* Launch configuration of the blend kernels: pixels per lane in the forward and backward
  * (1, 2 or 4). Results do not depend on it beyond FP32 summation order. */

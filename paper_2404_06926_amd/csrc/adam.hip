@@ -23,13 +23,11 @@ k_adam(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m, floa
   const int f = blockIdx.y;
   if (i >= N || !vis[i]) return;
   const int64_t k = (int64_t)f * cap + i;
-  const float gr = g[k];
-  const float mm = beta1 * m[k] + (1.0f - beta1) * gr;
-  const float vv = beta2 * v[k] + (1.0f - beta2) * gr * gr;
+  float pp = p[k], mm = m[k], vv = v[k];
+  adam_update(pp, mm, vv, g[k], lr.lr[f], beta1, beta2, eps, bc[0], bc[1]);
+  p[k] = pp;
   m[k] = mm;
   v[k] = vv;
-  const float mh = mm / bc[0], vh = vv / bc[1];
-  p[k] -= lr.lr[f] * mh / (sqrtf(vh) + eps);
   g[k] = 0.0f;
 }
 
@@ -39,12 +37,11 @@ __global__ void k_adam_exposure(ExpArg ea, const float* __restrict__ bc, float l
   const int e = blockIdx.x, k = threadIdx.x;
   if (e >= ea.n || k >= 12) return;
   float* s = ea.p[e];
-  const float gr = s[12 + k];
-  const float mm = beta1 * s[24 + k] + (1.0f - beta1) * gr;
-  const float vv = beta2 * s[36 + k] + (1.0f - beta2) * gr * gr;
+  float pp = s[k], mm = s[24 + k], vv = s[36 + k];
+  adam_update(pp, mm, vv, s[12 + k], lr, beta1, beta2, eps, bc[0], bc[1]);
+  s[k] = pp;
   s[24 + k] = mm;
   s[36 + k] = vv;
-  s[k] -= lr * (mm / bc[0]) / (sqrtf(vv / bc[1]) + eps);
   s[12 + k] = 0.0f;
 }
 
@@ -121,6 +118,17 @@ k_copy_planes(const float* __restrict__ src, int64_t cap0, float* __restrict__ d
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int f = blockIdx.y;
   if (i < n) dst[(int64_t)f * cap1 + i] = src[(int64_t)f * cap0 + i];
+}
+
+hipError_t adam_prepare(int64_t* step, float* bc, float beta1, float beta2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam_prepare, dim3(1), dim3(1), 0, s, step, bc, beta1, beta2);
+  return hipGetLastError();
+}
+
+hipError_t adam_exposures(const ExpArg& ea, const float* bc, float lr, float beta1, float beta2, float eps,
+                          hipStream_t s) {
+  if (ea.n > 0) hipLaunchKernelGGL(k_adam_exposure, dim3(ea.n), dim3(64), 0, s, ea, bc, lr, beta1, beta2, eps);
+  return hipGetLastError();
 }
 
 hipError_t adam_step(float* buf, int64_t cap, int32_t F, int32_t N, const uint8_t* vis, const LrArg& lr,

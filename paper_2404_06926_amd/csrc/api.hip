@@ -72,6 +72,13 @@ struct gs_map {
   int64_t resident = 0;
   // workspace
   DevBuf rec, counts, offsets, scan_tmp, g2d, keys[2], vals[2], sort_tmp, ranges, pixT, pixN, loss_tmp;
+  DevBuf dkey[2], dval[2];     // depth-sort keys / (view, Gaussian) ids, double-buffered
+  DevBuf emit_g, inst_off;     // Gaussian of each emission index; first emission index per pair
+  DevBuf inst_grad, exp_part;  // deterministic backward: per-instance gradients, per-tile exposure sums
+  DevBuf dbg_g;                // Gaussian index per instance in blend order (inspection only)
+  bool deterministic = false;
+  bool fused_step = true;      // gs_step applies Adam inside the projection backward
+  uint32_t* d_nvn = nullptr;   // number of (view, Gaussian) pairs of the last render
   int64_t vn_cap = 0, inst_cap = 0, tiles_cap = 0, pix_cap = 0;
   bool sync_plan = true;
   // last render
@@ -87,6 +94,13 @@ struct gs_map {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (stage, index of its start event)
+  bool capturing = false;      // inside gs_capture_step: no allocation, no timing, no host wait
+};
+
+struct gs_step_graph {
+  gs_map* map = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -119,6 +133,8 @@ void dev_free(gs_map* m, void* p, size_t bytes, hipStream_t s) {
 // Grow `b` to at least `bytes` (contents dropped). zero: clear the new buffer.
 gs_status ensure(gs_map* m, DevBuf& b, size_t bytes, hipStream_t s, bool zero = false) {
   if (b.bytes >= bytes && b.ptr) return GS_OK;
+  if (m->capturing)
+    return fail(GS_ERR_STATE, "capture would allocate: run an eager gs_step with the same views first");
   void* p = dev_alloc(m, bytes, s);
   if (!p) return fail(GS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   dev_free(m, b.ptr, b.bytes, s);
@@ -162,6 +178,33 @@ gs_status grow_capacity(gs_map* m, int64_t need, hipStream_t s) {
   m->cap = nc;
   m->have_render = false;
   return GS_OK;
+}
+
+gs_status ensure_instances(gs_map* m, int64_t nc, int64_t vn, hipStream_t s) {
+  for (int b = 0; b < 2; ++b) {
+    GS_TRY(ensure(m, m->keys[b], (size_t)nc * 4, s));
+    GS_TRY(ensure(m, m->vals[b], (size_t)nc * 4, s));
+  }
+  GS_TRY(ensure(m, m->emit_g, (size_t)nc * 4, s));
+  if (m->deterministic) GS_TRY(ensure(m, m->inst_grad, (size_t)nc * 12 * 4, s));
+  GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(std::max<int64_t>(nc, vn)) * 4, s));
+  if (nc > m->inst_cap) m->inst_cap = nc;
+  return GS_OK;
+}
+
+LrArg lr_table(const gs_map* m) {
+  LrArg lr{};
+  const gs_map_desc& d = m->desc;
+  for (int f = 0; f < m->F; ++f) {
+    float r = d.lr_sh_rest;
+    if (f < 3) r = d.lr_mean;
+    else if (f < 6) r = d.lr_log_scale;
+    else if (f < 10) r = d.lr_quat;
+    else if (f < 11) r = d.lr_opacity;
+    else if (f < 14) r = d.lr_sh_dc;
+    lr.lr[f] = r;
+  }
+  return lr;
 }
 
 int bits_for(int64_t x) {
@@ -215,7 +258,7 @@ struct StageTimer {
   size_t idx = 0;
   bool on = false;
   StageTimer(gs_map* m_, hipStream_t s_, int st) : m(m_), s(s_), stage(st) {
-    if (!m->timing) return;
+    if (!m->timing || m->capturing) return;
     while (m->ev_pool.size() < m->ev_used + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return;
@@ -279,7 +322,8 @@ gs_status gs_create_map(const gs_map_desc* desc, const gs_allocator* allocator, 
   m->d_ninst = (uint32_t*)dev_alloc(m, 64, s);
   m->d_overflow = (uint32_t*)dev_alloc(m, 64, s);
   m->d_loss = (float*)dev_alloc(m, 256, s);
-  if (!m->d_step || !m->d_bc || !m->d_ninst || !m->d_overflow || !m->d_loss) {
+  m->d_nvn = (uint32_t*)dev_alloc(m, 64, s);
+  if (!m->d_step || !m->d_bc || !m->d_ninst || !m->d_overflow || !m->d_loss || !m->d_nvn) {
     gs_destroy_map(m);
     return fail(GS_ERR_OOM, "device allocation failed");
   }
@@ -322,8 +366,11 @@ gs_status gs_destroy_map(gs_map* m) {
   dev_free(m, m->d_ninst, 64, s);
   dev_free(m, m->d_overflow, 64, s);
   dev_free(m, m->d_loss, 256, s);
+  dev_free(m, m->d_nvn, 64, s);
   DevBuf* bufs[] = {&m->rec, &m->counts, &m->offsets, &m->scan_tmp, &m->g2d, &m->keys[0], &m->keys[1],
-                    &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp};
+                    &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp,
+                    &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
+                    &m->inst_grad, &m->exp_part, &m->dbg_g};
   for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
   for (KeyframeSlot& k : m->kf) {
     dev_free(m, k.image, 3 * k.pix_bytes, s);
@@ -404,6 +451,14 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   GS_TRY(ensure(m, m->offsets, (size_t)std::max<int64_t>(vn, 1) * 4, s));
   GS_TRY(ensure(m, m->scan_tmp, (size_t)scan_temp_elems(std::max<int64_t>(vn, 1)) * 4, s));
   GS_TRY(ensure(m, m->g2d, (size_t)std::max<int64_t>(vn, 1) * kGradFloats * 4, s, true));
+  for (int b = 0; b < 2; ++b) {
+    GS_TRY(ensure(m, m->dkey[b], (size_t)std::max<int64_t>(vn, 1) * 4, s));
+    GS_TRY(ensure(m, m->dval[b], (size_t)std::max<int64_t>(vn, 1) * 4, s));
+  }
+  GS_TRY(ensure(m, m->inst_off, (size_t)std::max<int64_t>(vn, 1) * 4, s));
+  GS_TRY(ensure(m, m->exp_part, (size_t)std::max<int64_t>(tiles, 1) * 12 * 4, s));
+  GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(std::max<int64_t>(std::max<int64_t>(vn, m->inst_cap), 1)) * 4,
+                s));
   GS_TRY(ensure(m, m->ranges, (size_t)tiles * 8, s));
   GS_TRY(ensure(m, m->pixT, (size_t)pix * 4, s));
   GS_TRY(ensure(m, m->pixN, (size_t)pix * 4, s));
@@ -416,44 +471,49 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   float4* rec = (float4*)m->rec.ptr;
   uint32_t* counts = (uint32_t*)m->counts.ptr;
   uint32_t* offsets = (uint32_t*)m->offsets.ptr;
+  uint32_t* dkey[2] = {(uint32_t*)m->dkey[0].ptr, (uint32_t*)m->dkey[1].ptr};
+  uint32_t* dval[2] = {(uint32_t*)m->dval[0].ptr, (uint32_t*)m->dval[1].ptr};
   {
     StageTimer t(m, s, GS_STAGE_PROJECT);
-    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, s));
+    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0], dval[0], s));
   }
+  int dwhich = 0;
+  {
+    StageTimer t(m, s, GS_STAGE_DEPTH_SORT);
+    GS_HIP(fill_u32(m->d_nvn, (uint32_t)vn, 1, s));
+    GS_HIP(radix_sort_u32(dkey, dval, m->d_nvn, vn, 32, (uint32_t*)m->sort_tmp.ptr, &dwhich, s));
+  }
+  const uint32_t* order = dval[dwhich];
   {
     StageTimer t(m, s, GS_STAGE_SCAN);
     if (vn > 0)
-      GS_HIP(scan_counts(counts, offsets, vn, (uint32_t*)m->scan_tmp.ptr, m->d_ninst, s));
+      GS_HIP(scan_counts(counts, order, offsets, vn, (uint32_t*)m->scan_tmp.ptr, m->d_ninst, s));
     else
       GS_HIP(fill_u32(m->d_ninst, 0u, 1, s));
   }
+  if (m->sync_plan && m->capturing) return fail(GS_ERR_STATE, "capture needs sync_plan = 0");
   if (m->sync_plan) {
     GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_ninst, 4, hipMemcpyDeviceToHost, s));
     GS_HIP(hipStreamSynchronize(s));
     const int64_t need = m->h_pinned[0];
-    if (need > m->inst_cap) {
-      const int64_t nc = std::max<int64_t>(need + need / 4, 1 << 16);
-      for (int b = 0; b < 2; ++b) {
-        GS_TRY(ensure(m, m->keys[b], (size_t)nc * 8, s));
-        GS_TRY(ensure(m, m->vals[b], (size_t)nc * 4, s));
-      }
-      GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(nc) * 4, s));
-      m->inst_cap = nc;
-    }
+    if (need > m->inst_cap) GS_TRY(ensure_instances(m, std::max<int64_t>(need + need / 4, 1 << 16), vn, s));
   } else if (m->inst_cap == 0) {
     return fail(GS_ERR_STATE, "sync_plan = 0 needs an instance capacity (gs_set_instance_policy)");
   }
-  uint64_t* keys[2] = {(uint64_t*)m->keys[0].ptr, (uint64_t*)m->keys[1].ptr};
+  GS_TRY(ensure_instances(m, m->inst_cap, vn, s));
+  uint32_t* keys[2] = {(uint32_t*)m->keys[0].ptr, (uint32_t*)m->keys[1].ptr};
   uint32_t* vals[2] = {(uint32_t*)m->vals[0].ptr, (uint32_t*)m->vals[1].ptr};
   {
     StageTimer t(m, s, GS_STAGE_DUPLICATE);
-    GS_HIP(duplicate_keys(rec, counts, offsets, N, va, keys[0], vals[0], m->inst_cap, m->d_overflow, s));
+    GS_HIP(duplicate_keys(rec, counts, order, offsets, N, va, keys[0], vals[0], (uint32_t*)m->emit_g.ptr,
+                          (uint32_t*)m->inst_off.ptr, m->inst_cap, m->d_overflow, s));
   }
   int which = 0;
   {
+    // stable sort by tile id; one extra bit keeps the sentinel id above every real tile
     StageTimer t(m, s, GS_STAGE_SORT);
-    GS_HIP(radix_sort(keys, vals, m->d_ninst, m->inst_cap, 32 + bits_for(tiles), (uint32_t*)m->sort_tmp.ptr,
-                      &which, s));
+    GS_HIP(radix_sort_u32(keys, vals, m->d_ninst, m->inst_cap, bits_for(tiles + 1), (uint32_t*)m->sort_tmp.ptr,
+                          &which, s));
   }
   uint2* ranges = (uint2*)m->ranges.ptr;
   {
@@ -463,7 +523,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   }
   {
     StageTimer t(m, s, GS_STAGE_BLEND);
-    GS_HIP(blend_forward(va, rec, N, vals[which], ranges, s));
+    GS_HIP(blend_forward(va, rec, N, vals[which], (const uint32_t*)m->emit_g.ptr, ranges, s));
   }
   m->have_render = true;
   m->last_va = va;
@@ -472,9 +532,17 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   return GS_OK;
 }
 
+static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
+                               const AdamArg* fused, hipStream_t s);
+
 gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
                              void* stream) {
   g_err.clear();
+  return backward_impl(m, nv, dL_drgb, dL_dexposure, nullptr, (hipStream_t)stream);
+}
+
+static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
+                               const AdamArg* fused, hipStream_t stream) {
   if (!m || !dL_drgb) return fail(GS_ERR_INVALID, "map and dL_drgb must not be NULL");
   if (!m->have_render) return fail(GS_ERR_STATE, "render_backward needs a preceding render of the same map");
   if (nv != m->last_va.n) return fail(GS_ERR_STATE, "n_views differs from the preceding render");
@@ -492,13 +560,16 @@ gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb,
   float* g2d = (float*)m->g2d.ptr;
   {
     StageTimer t(m, s, GS_STAGE_BLEND_BACKWARD);
-    GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint2*)m->ranges.ptr, g2d,
-                          s));
+    GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr,
+                          (const uint2*)m->ranges.ptr, g2d, m->deterministic ? (float*)m->inst_grad.ptr : nullptr,
+                          (float*)m->exp_part.ptr, s));
   }
   {
     StageTimer t(m, s, GS_STAGE_PROJECT_BACKWARD);
     GS_HIP(project_backward(m->deg, params_of(m), grads_of(m), m->cap, N, va, m->desc.near_z,
-                            (const uint32_t*)m->counts.ptr, (float4*)g2d, m->vis, s));
+                            (const uint32_t*)m->counts.ptr, (float4*)g2d,
+                            m->deterministic ? (const float*)m->inst_grad.ptr : nullptr,
+                            (const uint32_t*)m->inst_off.ptr, m->vis, fused, s));
   }
   return GS_OK;
 }
@@ -514,17 +585,8 @@ gs_status gs_adam_step(gs_map* m, int32_t ne, float* const* exposure_states, voi
     if (!exposure_states[e]) return fail(GS_ERR_INVALID, "exposure_states[" + std::to_string(e) + "] is NULL");
     ea.p[e] = exposure_states[e];
   }
-  LrArg lr{};
+  const LrArg lr = lr_table(m);
   const gs_map_desc& d = m->desc;
-  for (int f = 0; f < m->F; ++f) {
-    float r = d.lr_sh_rest;
-    if (f < 3) r = d.lr_mean;
-    else if (f < 6) r = d.lr_log_scale;
-    else if (f < 10) r = d.lr_quat;
-    else if (f < 11) r = d.lr_opacity;
-    else if (f < 14) r = d.lr_sh_dc;
-    lr.lr[f] = r;
-  }
   hipStream_t s = (hipStream_t)stream;
   StageTimer t(m, s, GS_STAGE_ADAM);
   GS_HIP(adam_step(m->buf, m->cap, m->F, (int32_t)m->n, m->vis, lr, m->d_step, m->d_bc, d.beta1, d.beta2, d.eps,
@@ -625,26 +687,134 @@ gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image,
   const int nk = (int)m->kf.size();
   std::vector<gs_view> vv(nk);
   std::vector<gs_frame> ff(nk);
-  std::vector<const float*> dl(nk);
-  std::vector<float*> eg(nk), es(nk);
+  std::vector<const float*> tg(nk);
+  std::vector<float*> dl(nk), es(nk);
   for (int j = 0; j < nk; ++j) {
     KeyframeSlot& q = m->kf[j];
     vv[j] = q.view;
     ff[j] = gs_frame{q.rgb, q.T, q.nc};
+    tg[j] = q.image;
     dl[j] = q.dl;
-    eg[j] = q.state + 12;
     es[j] = q.state;
   }
-  for (int it = 0; it < iters; ++it) {
-    GS_TRY(gs_render(m, nk, vv.data(), ff.data(), stream));
-    for (int j = 0; j < nk; ++j) {
-      KeyframeSlot& q = m->kf[j];
-      GS_TRY(gs_loss(m, q.rgb, q.image, q.view.height, q.view.width, lambda, m->d_loss + j, q.dl, stream));
-    }
-    GS_TRY(gs_render_backward(m, nk, dl.data(), eg.data(), stream));
-    GS_TRY(gs_adam_step(m, nk, es.data(), stream));
-  }
+  for (int it = 0; it < iters; ++it)
+    GS_TRY(gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream));
   if (done_event) GS_HIP(hipEventRecord((hipEvent_t)done_event, s));
+  return GS_OK;
+}
+
+gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* frames, const float* const* targets,
+                  float lambda, float* const* exposure_states, float* const* dl_drgb, float* loss_dev, void* stream) {
+  g_err.clear();
+  if (!m || !views || !frames || !targets || !exposure_states || !dl_drgb || !loss_dev)
+    return fail(GS_ERR_INVALID, "NULL argument");
+  if (nv < 1 || nv > kMaxViews) return fail(GS_ERR_CAPACITY, "n_views must be in 1..16");
+  for (int v = 0; v < nv; ++v)
+    if (!targets[v] || !exposure_states[v] || !dl_drgb[v] || !frames[v].rgb)
+      return fail(GS_ERR_INVALID, "NULL entry in view " + std::to_string(v));
+  gs_view vv[kMaxViews];
+  const float* dl[kMaxViews];
+  float* eg[kMaxViews];
+  for (int v = 0; v < nv; ++v) {
+    vv[v] = views[v];
+    vv[v].exposure = exposure_states[v];
+    dl[v] = dl_drgb[v];
+    eg[v] = exposure_states[v] + 12;
+  }
+  GS_TRY(gs_render(m, nv, vv, frames, stream));
+  for (int v = 0; v < nv; ++v)
+    GS_TRY(gs_loss(m, frames[v].rgb, targets[v], vv[v].height, vv[v].width, lambda, loss_dev + v, dl_drgb[v],
+                   stream));
+  if (!m->fused_step) {
+    GS_TRY(gs_render_backward(m, nv, dl, eg, stream));
+    GS_TRY(gs_adam_step(m, nv, exposure_states, stream));
+    return GS_OK;
+  }
+  // one step: the gradient is complete after this backward, so Adam runs inside the
+  // projection backward (no gradient planes written and read back)
+  hipStream_t s = (hipStream_t)stream;
+  const gs_map_desc& d = m->desc;
+  GS_HIP(adam_prepare(m->d_step, m->d_bc, d.beta1, d.beta2, s));
+  AdamArg ad{};
+  ad.lr = lr_table(m);
+  ad.m = m->buf + 2 * (int64_t)m->F * m->cap;
+  ad.v = m->buf + 3 * (int64_t)m->F * m->cap;
+  ad.bc = m->d_bc;
+  ad.beta1 = d.beta1;
+  ad.beta2 = d.beta2;
+  ad.eps = d.eps;
+  GS_TRY(backward_impl(m, nv, dl, eg, &ad, s));
+  ExpArg ea{};
+  ea.n = nv;
+  for (int v = 0; v < nv; ++v) ea.p[v] = exposure_states[v];
+  {
+    StageTimer t(m, s, GS_STAGE_ADAM);
+    GS_HIP(adam_exposures(ea, m->d_bc, d.lr_exposure, d.beta1, d.beta2, d.eps, s));
+  }
+  m->h_step += 1;
+  return GS_OK;
+}
+
+gs_status gs_set_fused_step(gs_map* m, int32_t enable) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  m->fused_step = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_capture_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* frames,
+                          const float* const* targets, float lambda, float* const* exposure_states,
+                          float* const* dl_drgb, float* loss_dev, void* stream, gs_step_graph** out) {
+  g_err.clear();
+  if (!m || !out) return fail(GS_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (m->sync_plan) return fail(GS_ERR_STATE, "capture needs sync_plan = 0 (gs_set_instance_policy)");
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(GS_ERR_INVALID, "capture needs a non-default stream");
+  GS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  m->capturing = true;
+  const int64_t step_before = m->h_step;
+  gs_status st = gs_step(m, nv, views, frames, targets, lambda, exposure_states, dl_drgb, loss_dev, stream);
+  m->capturing = false;
+  m->h_step = step_before;
+  std::string msg = g_err;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != GS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(st, msg);
+  }
+  if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(GS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  gs_step_graph* g = new (std::nothrow) gs_step_graph();
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return fail(GS_ERR_OOM, "host allocation failed");
+  }
+  g->map = m;
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return GS_OK;
+}
+
+gs_status gs_launch_step(gs_step_graph* g, void* stream) {
+  if (!g) return fail(GS_ERR_INVALID, "graph is NULL");
+  GS_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  g->map->h_step += 1;
+  return GS_OK;
+}
+
+gs_status gs_destroy_step(gs_step_graph* g) {
+  if (!g) return GS_OK;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
   return GS_OK;
 }
 
@@ -679,7 +849,7 @@ gs_status gs_map_step_count(const gs_map* m, int64_t* t) {
   return GS_OK;
 }
 
-gs_status gs_debug_last_render(gs_map* m, void* stream, const uint64_t** keys, const uint32_t** vals,
+gs_status gs_debug_last_render(gs_map* m, void* stream, const uint32_t** keys, const uint32_t** vals,
                                int64_t* n_inst, const uint32_t** ranges, int64_t* n_tiles, const float** proj,
                                const uint32_t** counts) {
   if (!m) return fail(GS_ERR_INVALID, "map is NULL");
@@ -687,8 +857,14 @@ gs_status gs_debug_last_render(gs_map* m, void* stream, const uint64_t** keys, c
   hipStream_t s = (hipStream_t)stream;
   GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_ninst, 4, hipMemcpyDeviceToHost, s));
   GS_HIP(hipStreamSynchronize(s));
-  if (keys) *keys = (const uint64_t*)m->keys[m->sorted].ptr;
-  if (vals) *vals = (const uint32_t*)m->vals[m->sorted].ptr;
+  if (keys) *keys = (const uint32_t*)m->keys[m->sorted].ptr;
+  if (vals) {
+    GS_TRY(ensure(m, m->dbg_g, (size_t)std::max<int64_t>(m->inst_cap, 1) * 4, s));
+    GS_HIP(gather_gaussians((const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr, m->d_ninst,
+                            m->inst_cap, (uint32_t*)m->dbg_g.ptr, s));
+    GS_HIP(hipStreamSynchronize(s));
+    *vals = (const uint32_t*)m->dbg_g.ptr;
+  }
   if (n_inst) *n_inst = m->h_pinned[0];
   if (ranges) *ranges = (const uint32_t*)m->ranges.ptr;
   if (n_tiles) *n_tiles = m->last_va.total_tiles;
@@ -702,12 +878,7 @@ gs_status gs_set_instance_policy(gs_map* m, int32_t sync_plan, int64_t capacity)
   if (capacity < 0 || capacity > (int64_t)UINT32_MAX) return fail(GS_ERR_INVALID, "capacity out of range");
   if (capacity > m->inst_cap) {
     hipStream_t s = nullptr;
-    for (int b = 0; b < 2; ++b) {
-      GS_TRY(ensure(m, m->keys[b], (size_t)capacity * 8, s));
-      GS_TRY(ensure(m, m->vals[b], (size_t)capacity * 4, s));
-    }
-    GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(capacity) * 4, s));
-    m->inst_cap = capacity;
+    GS_TRY(ensure_instances(m, capacity, 0, s));
     GS_HIP(hipStreamSynchronize(s));
   }
   m->sync_plan = sync_plan != 0;
@@ -745,6 +916,13 @@ gs_status gs_stage_times(gs_map* m, void* stream, double* ms, int64_t* count) {
   }
   m->ev_marks.clear();
   m->ev_used = 0;
+  return GS_OK;
+}
+
+gs_status gs_set_deterministic(gs_map* m, int32_t enable) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  m->deterministic = enable != 0;
+  m->have_render = false;  // the next render sizes the per-instance buffers
   return GS_OK;
 }
 

@@ -1,12 +1,20 @@
-// Tile binning (Sec. III-A depth order, Sec. III-D.2 footprint tiles):
-//   exclusive scan of per-(view, Gaussian) tile counts -> instance offsets,
-//   duplicate each Gaussian once per tile its footprint reaches with the key
-//   (global tile << 32 | float bits of depth),
-//   stable LSD radix sort of (key, Gaussian) pairs on the significant key bits,
-//   [start, end) of every tile in the sorted list.
-// Kernels that depend on the instance count read it from device memory, so the whole
-// sequence has host-known launch shapes (graph-capturable); instances beyond the buffer
-// capacity are dropped and an overflow flag is raised.
+// Tile binning (Sec. III-A depth order, Sec. III-D.2 footprint tiles).
+//
+// The order the blend needs is (global tile, depth, Gaussian index). It is reached in two
+// small sorts instead of one wide one:
+//   1. a stable LSD radix sort of the (view, Gaussian) pairs by the float bits of their
+//      depth (4 passes over V*N 32-bit keys; pairs that reach no tile get the largest key);
+//   2. an exclusive scan of the tile counts in that order, then every pair emits its tile
+//      ids at its offset, so the instance list comes out in (depth, view-major index)
+//      order;
+//   3. a stable LSD radix sort of the instances by global tile id only
+//      (ceil(log2(tiles + 1)) bits, 2 passes up to 65535 tiles);
+//   4. [start, end) of every tile in the sorted list.
+// Stability makes the result identical to sorting the 64-bit keys tile << 32 | depth bits
+// with ties in emission order, at about a fifth of the bytes.
+// Kernels that depend on the instance count read it from device memory, so the sequence
+// has host-known launch shapes (graph-capturable). Instances beyond the buffer capacity
+// are dropped and flagged; the render is then empty.
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -38,16 +46,19 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   return wbase + incl - x;
 }
 
-// Pass 1: per-block local exclusive scan and block sums.
+// Pass 1: per-block local exclusive scan and block sums; element k is in[idx[k]] when idx
+// is given (a gather in another order), else in[k].
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint32_t* __restrict__ sums, int64_t n) {
+k_scan_local(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, uint32_t* __restrict__ out,
+             uint32_t* __restrict__ sums, int64_t n) {
   __shared__ uint32_t s_warp[kScanBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t tsum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < n) ? in[base + k] : 0u;
+    v[k] = 0u;
+    if (base + k < n) v[k] = idx ? in[idx[base + k]] : in[base + k];
     tsum += v[k];
   }
   uint32_t total;
@@ -70,9 +81,9 @@ k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ sums, int64_
 }
 
 // total = last offset + last count
-__global__ void k_scan_total(const uint32_t* __restrict__ in, const uint32_t* __restrict__ out, int64_t n,
-                             uint32_t* __restrict__ total) {
-  total[0] = n > 0 ? out[n - 1] + in[n - 1] : 0u;
+__global__ void k_scan_total(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx,
+                             const uint32_t* __restrict__ out, int64_t n, uint32_t* __restrict__ total) {
+  total[0] = n > 0 ? out[n - 1] + (idx ? in[idx[n - 1]] : in[n - 1]) : 0u;
 }
 
 int64_t scan_temp_elems(int64_t n) {
@@ -84,73 +95,31 @@ int64_t scan_temp_elems(int64_t n) {
   return t + 1;
 }
 
-// Exclusive scan of n u32 values (in may equal out); temp holds scan_temp_elems(n).
-hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s) {
+static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* temp,
+                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   uint32_t* sums = temp;
-  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, sums, n);
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, idx, out, sums, n);
   if (nb > 1) {
-    hipError_t e = exclusive_scan(sums, sums, nb, temp + nb, s);
+    hipError_t e = scan_impl(sums, nullptr, sums, nb, temp + nb, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanBlock), 0, s, out, sums, n);
   }
   return hipGetLastError();
 }
 
-hipError_t scan_counts(const uint32_t* counts, uint32_t* offsets, int64_t n, uint32_t* temp,
-                       uint32_t* total, hipStream_t s) {
-  hipError_t e = exclusive_scan(counts, offsets, n, temp, s);
+// Exclusive scan of n u32 values (in may equal out); temp holds scan_temp_elems(n).
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s) {
+  return scan_impl(in, nullptr, out, n, temp, s);
+}
+
+// offsets[k] = sum of counts[order[j]] for j < k; total = sum of all.
+hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* offsets, int64_t n,
+                       uint32_t* temp, uint32_t* total, hipStream_t s) {
+  hipError_t e = scan_impl(counts, order, offsets, n, temp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, counts, offsets, n, total);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------- duplicate
-__global__ void __launch_bounds__(256)
-k_duplicate(const float4* __restrict__ rec, const uint32_t* __restrict__ counts,
-            const uint32_t* __restrict__ offsets, int32_t N, ViewsArg va, uint64_t* __restrict__ keys,
-            uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ overflow) {
-  const int64_t vi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (vi >= (int64_t)va.n * N) return;
-  const uint32_t cnt = counts[vi];
-  if (cnt == 0) return;
-  const int v = (int)(vi / N);
-  const uint32_t g = (uint32_t)(vi - (int64_t)v * N);
-  const ViewDev& V = va.v[v];
-  const float4 r0 = rec[vi * 4], r1 = rec[vi * 4 + 1], r2 = rec[vi * 4 + 2], r3 = rec[vi * 4 + 3];
-  const uint32_t a = __float_as_uint(r3.x), b = __float_as_uint(r3.y);
-  const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
-  const uint64_t dbits = __float_as_uint(r2.y);
-  int64_t o = offsets[vi];
-  if (o + cnt > capacity) {
-    atomicOr(overflow, 1u);
-    return;
-  }
-  // Same predicate as the count pass; writes never leave this Gaussian's [o, o + cnt).
-  const int64_t end = o + cnt;
-  for (int ty = y0; ty <= y1 && o < end; ++ty)
-    for (int tx = x0; tx <= x1 && o < end; ++tx)
-      if (key_tile_hit(r0.x, r0.y, r0.z, r0.w, r1.x, r2.w, tx, ty)) {
-        const uint64_t tile = (uint64_t)(V.tile_base + ty * V.tiles_x + tx);
-        keys[o] = (tile << 32) | dbits;
-        vals[o] = g;
-        ++o;
-      }
-  // unreachable when both passes agree; a sentinel tile sorts last and is never ranged
-  for (; o < end; ++o) {
-    keys[o] = ~0ull;
-    vals[o] = 0u;
-  }
-}
-
-hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* offsets, int32_t N,
-                          const ViewsArg& va, uint64_t* keys, uint32_t* vals, int64_t capacity,
-                          uint32_t* overflow, hipStream_t s) {
-  const int64_t n = (int64_t)va.n * N;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rec, counts, offsets,
-                     N, va, keys, vals, capacity, overflow);
+  hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, counts, order, offsets, n, total);
   return hipGetLastError();
 }
 
@@ -163,31 +132,51 @@ constexpr int kSortItems = 8;                       // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;  // 2048 keys per block
 constexpr int kWaves = kSortBlock / 64;
 
-// Instances to process: all of them when they fit, none after an overflow (the render
-// is then empty and the overflow flag tells the host to re-plan).
+// Elements to process: all of them when they fit, none after an overflow (the render is
+// then empty and the overflow flag tells the host to re-plan).
 __device__ __forceinline__ uint32_t sort_count(const uint32_t* n_dev, int64_t cap) {
   const uint32_t n = n_dev[0];
   return (int64_t)n <= cap ? n : 0u;
 }
 
-__global__ void __launch_bounds__(kSortBlock)
-k_radix_hist(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
-             uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t s_h[256];
-  s_h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t n = sort_count(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int k = threadIdx.x; k < kSortTile; k += kSortBlock) {
-    const int64_t idx = base + k;
-    if (idx < n) atomicAdd(&s_h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+// Lanes of the wave whose digit equals this lane's (8 ballots), restricted to `ok` lanes.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool ok) {
+  uint64_t peers = __ballot(ok);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t m = __ballot((d >> b) & 1u);
+    peers &= ((d >> b) & 1u) ? m : ~m;
   }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
+  return peers;
 }
 
+template <typename K>
 __global__ void __launch_bounds__(kSortBlock)
-k_radix_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+k_radix_hist(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
+             uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t s_h[kWaves][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int d = lane; d < 256; d += 64) s_h[wid][d] = 0;
+  __syncthreads();
+  const uint32_t n = sort_count(n_dev, cap);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wid * (64 * kSortItems);
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t idx = base + r * 64 + lane;
+    const bool ok = idx < n;
+    const uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
+    // one LDS add per distinct digit of the wave
+    const uint64_t peers = digit_peers(d, ok);
+    if (ok && lane == __ffsll((long long)peers) - 1) s_h[wid][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  const int d = threadIdx.x;
+  hist[(int64_t)d * nblocks + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock)
+k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
                 uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
                 const uint32_t* __restrict__ hist_scan, int nblocks) {
   __shared__ uint32_t s_cnt[kWaves][256];
@@ -197,23 +186,18 @@ k_radix_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ v
   __syncthreads();
   const uint32_t n = sort_count(n_dev, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wid * (64 * kSortItems);
-  uint64_t key[kSortItems];
+  K key[kSortItems];
   uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t idx = base + r * 64 + lane;
     const bool ok = idx < n;
-    key[r] = ok ? kin[idx] : 0ull;
+    key[r] = ok ? kin[idx] : (K)0;
     val[r] = ok ? vin[idx] : 0u;
     const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
     dig[r] = d;
-    uint64_t peers = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1u);
-      peers &= ((d >> b) & 1u) ? m : ~m;
-    }
+    const uint64_t peers = digit_peers(d, ok);
     uint32_t prev = 0;
     const int leader = peers ? (__ffsll((long long)peers) - 1) : 0;
     if (ok && lane == leader) {
@@ -252,9 +236,9 @@ int64_t sort_temp_elems(int64_t cap) {
 }
 
 // Sorts (keys[0], vals[0]) on bits [0, nbits) using (keys[1], vals[1]) as the double buffer;
-// returns in *which the index of the buffer that holds the result.
-hipError_t radix_sort(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
-                      uint32_t* temp, int* which, hipStream_t s) {
+// *which receives the index of the buffer that holds the result.
+hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
+                          uint32_t* temp, int* which, hipStream_t s) {
   *which = 0;
   if (cap <= 0) return hipSuccess;
   const int nb = (int)((cap + kSortTile - 1) / kSortTile);
@@ -262,29 +246,139 @@ hipError_t radix_sort(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* n_de
   uint32_t* stemp = temp + (int64_t)256 * nb;
   int cur = 0;
   for (int shift = 0; shift < nbits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, s, keys[cur], n_dev, cap, shift, hist, nb);
+    hipLaunchKernelGGL(k_radix_hist<uint32_t>, dim3(nb), dim3(kSortBlock), 0, s, keys[cur], n_dev, cap, shift,
+                       hist, nb);
     hipError_t e = exclusive_scan(hist, hist, (int64_t)256 * nb, stemp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], n_dev, cap, shift, hist, nb);
+    hipLaunchKernelGGL(k_radix_scatter<uint32_t>, dim3(nb), dim3(kSortBlock), 0, s, keys[cur], vals[cur],
+                       keys[cur ^ 1], vals[cur ^ 1], n_dev, cap, shift, hist, nb);
     cur ^= 1;
   }
   *which = cur;
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------- duplicate
+// Thread k takes the k-th (view, Gaussian) pair in depth order and writes one instance per
+// tile its footprint reaches, at its scanned offset e: tiles_out[e] = global tile id,
+// vals_out[e] = e (the tile sort carries the emission index), emit_g[e] = Gaussian index;
+// inst_off[view * N + Gaussian] = first e of the pair. A block's pairs are consecutive, so
+// its instances form one contiguous range; it is assembled in LDS and written with
+// coalesced stores (direct stores if it is too long).
+constexpr int kDupLds = 4096;
+
+__global__ void __launch_bounds__(256)
+k_duplicate(const float4* __restrict__ rec, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ order,
+            const uint32_t* __restrict__ offsets, int32_t N, int64_t n_pairs, ViewsArg va,
+            uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ vals_out, uint32_t* __restrict__ emit_g,
+            uint32_t* __restrict__ inst_off, int64_t capacity, uint32_t* __restrict__ overflow) {
+  __shared__ uint32_t s_tile[kDupLds];
+  __shared__ uint32_t s_g[kDupLds];
+  __shared__ int64_t s_lo, s_hi;
+  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t k = k0 + threadIdx.x;
+  uint32_t cnt = 0, vi = 0;
+  int64_t o = 0;
+  if (k < n_pairs) {
+    vi = order[k];
+    cnt = counts[vi];
+    o = offsets[k];
+    inst_off[vi] = (uint32_t)o;
+  }
+  if (threadIdx.x == 0) s_lo = o;
+  const int64_t klast = min(k0 + (int64_t)blockDim.x, n_pairs) - 1;
+  if (k == klast) s_hi = o + cnt;
+  __syncthreads();
+  const int64_t lo = s_lo, hi = s_hi;
+  if (hi > capacity) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
+  const bool staged = hi - lo <= kDupLds;
+  if (cnt > 0) {
+    const int v = (int)(vi / (uint32_t)N);
+    const uint32_t g = vi - (uint32_t)v * (uint32_t)N;
+    const ViewDev& V = va.v[v];
+    const float4 r0 = rec[(size_t)vi * 4], r1 = rec[(size_t)vi * 4 + 1], r2 = rec[(size_t)vi * 4 + 2],
+                 r3 = rec[(size_t)vi * 4 + 3];
+    const uint32_t a = __float_as_uint(r3.x), b = __float_as_uint(r3.y);
+    const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
+    // same predicate as the count pass; writes never leave this pair's [o, o + cnt)
+    const int64_t end = o + cnt;
+    int64_t w = o;
+    for (int ty = y0; ty <= y1 && w < end; ++ty)
+      for (int tx = x0; tx <= x1 && w < end; ++tx)
+        if (key_tile_hit(r0.x, r0.y, r0.z, r0.w, r1.x, r2.w, tx, ty)) {
+          const uint32_t tile = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+          if (staged) {
+            s_tile[w - lo] = tile;
+            s_g[w - lo] = g;
+          } else {
+            tiles_out[w] = tile;
+            vals_out[w] = (uint32_t)w;
+            emit_g[w] = g;
+          }
+          ++w;
+        }
+    // unreachable when both passes agree; the sentinel tile sorts after every real tile
+    for (; w < end; ++w) {
+      if (staged) {
+        s_tile[w - lo] = 0xffffffffu;
+        s_g[w - lo] = 0u;
+      } else {
+        tiles_out[w] = 0xffffffffu;
+        vals_out[w] = (uint32_t)w;
+        emit_g[w] = 0u;
+      }
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < hi - lo; t += blockDim.x) {
+      tiles_out[lo + t] = s_tile[t];
+      vals_out[lo + t] = (uint32_t)(lo + t);
+      emit_g[lo + t] = s_g[t];
+    }
+  }
+}
+
+hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
+                          int32_t N, const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g,
+                          uint32_t* inst_off, int64_t capacity, uint32_t* overflow, hipStream_t s) {
+  const int64_t n = (int64_t)va.n * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rec, counts, order, offsets,
+                     N, n, va, tiles, vals, emit_g, inst_off, capacity, overflow);
+  return hipGetLastError();
+}
+
+// Gaussian index of every instance in blend order (for inspection).
+__global__ void __launch_bounds__(256)
+k_gather_g(const uint32_t* __restrict__ vals, const uint32_t* __restrict__ emit_g, const uint32_t* __restrict__ n_dev,
+           int64_t cap, uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < sort_count(n_dev, cap)) out[i] = emit_g[vals[i]];
+}
+
+hipError_t gather_gaussians(const uint32_t* vals, const uint32_t* emit_g, const uint32_t* n_dev, int64_t cap,
+                            uint32_t* out, hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_g, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, vals, emit_g, n_dev, cap, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------- ranges
 __global__ void __launch_bounds__(256)
-k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap,
+k_ranges(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ n_dev, int64_t cap,
          uint2* __restrict__ ranges, uint32_t n_tiles) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = sort_count(n_dev, cap);
   if (i >= n) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
+  const uint32_t t = tiles[i];
   if (i == 0) {
     if (t < n_tiles) ranges[t].x = 0;
   } else {
-    const uint32_t tp = (uint32_t)(keys[i - 1] >> 32);
+    const uint32_t tp = tiles[i - 1];
     if (tp != t) {
       if (tp < n_tiles) ranges[tp].y = (uint32_t)i;
       if (t < n_tiles) ranges[t].x = (uint32_t)i;
@@ -293,10 +387,10 @@ k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, 
   if (i == (int64_t)n - 1 && t < n_tiles) ranges[t].y = n;
 }
 
-hipError_t tile_ranges(const uint64_t* keys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
+hipError_t tile_ranges(const uint32_t* tiles, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
                        hipStream_t s) {
   if (cap <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, n_dev, cap, ranges,
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, tiles, n_dev, cap, ranges,
                      (uint32_t)n_tiles);
   return hipGetLastError();
 }

@@ -318,6 +318,18 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const f
   }
 }
 
+// One Adam update of a parameter (Sec. III-D.2 sparse Adam, Sec. IV-A.1 rates). Shared by
+// the Adam kernels so that every path takes the same rounding steps.
+__device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, float lr, float beta1,
+                                            float beta2, float eps, float bc1, float bc2) {
+#pragma clang fp contract(off)
+  const float mm = beta1 * m + (1.0f - beta1) * g;
+  const float vv = beta2 * v + (1.0f - beta2) * (g * g);
+  m = mm;
+  v = vv;
+  p = p - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
 __device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

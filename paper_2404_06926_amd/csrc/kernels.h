@@ -17,31 +17,51 @@ struct ExpArg {
   float* p[kMaxExposures];
 };
 
+// Sparse Adam applied inside the projection backward (one mapping step).
+struct AdamArg {
+  LrArg lr;
+  float* m;
+  float* v;
+  const float* bc;   // device bias corrections 1 - beta1^t, 1 - beta2^t
+  float beta1, beta2, eps;
+};
+
 // projection (project.hip)
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                           float4* rec, uint32_t* counts, hipStream_t s);
-hipError_t project_backward(int deg, const float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va,
-                            float near_z, const uint32_t* counts, float4* g2d, uint8_t* vis, hipStream_t s);
+                           float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, hipStream_t s);
+// With inst_grad != nullptr the 2D gradients are the sums, in emission order, of the
+// instance records [inst_off[vi], inst_off[vi] + counts[vi]); otherwise they come from g2d.
+// With adam != nullptr the Adam update of each row is applied in the same kernel (one step).
+hipError_t project_backward(int deg, float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
+                            const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
+                            uint8_t* vis, const AdamArg* adam, hipStream_t s);
 
 // binning (binning.hip)
 int64_t scan_temp_elems(int64_t n);
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s);
-hipError_t scan_counts(const uint32_t* counts, uint32_t* offsets, int64_t n, uint32_t* temp, uint32_t* total,
-                       hipStream_t s);
-hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* offsets, int32_t N,
-                          const ViewsArg& va, uint64_t* keys, uint32_t* vals, int64_t capacity,
-                          uint32_t* overflow, hipStream_t s);
+hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* offsets, int64_t n,
+                       uint32_t* temp, uint32_t* total, hipStream_t s);
+hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
+                          int32_t N, const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g,
+                          uint32_t* inst_off, int64_t capacity, uint32_t* overflow, hipStream_t s);
+hipError_t gather_gaussians(const uint32_t* vals, const uint32_t* emit_g, const uint32_t* n_dev, int64_t cap,
+                            uint32_t* out, hipStream_t s);
 int64_t sort_temp_elems(int64_t cap);
-hipError_t radix_sort(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
-                      uint32_t* temp, int* which, hipStream_t s);
-hipError_t tile_ranges(const uint64_t* keys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
+hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
+                          uint32_t* temp, int* which, hipStream_t s);
+hipError_t tile_ranges(const uint32_t* tiles, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
                        hipStream_t s);
 
 // blending (blend.hip)
+// vals: emission index of each instance in blend order; emit_g: Gaussian of each emission index.
 hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                         const uint2* ranges, hipStream_t s);
+                         const uint32_t* emit_g, const uint2* ranges, hipStream_t s);
+// Gradients of (mean2d, conic, opacity, colour) per (view, Gaussian): with inst_grad == nullptr
+// they are added to g2d with wave-reduced atomics; otherwise every instance's gradient is
+// written to inst_grad[emission index] (12 floats, fixed-order reduction, deterministic).
 hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                          const uint2* ranges, float* g2d, hipStream_t s);
+                          const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
+                          float* exp_part, hipStream_t s);
 
 // loss (loss.hip)
 int64_t loss_temp_floats(int H, int W);
@@ -52,6 +72,9 @@ hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lamb
 hipError_t adam_step(float* buf, int64_t cap, int32_t F, int32_t N, const uint8_t* vis, const LrArg& lr,
                      int64_t* step, float* bc, float beta1, float beta2, float eps, const ExpArg& ea,
                      float lr_exposure, hipStream_t s);
+hipError_t adam_prepare(int64_t* step, float* bc, float beta1, float beta2, hipStream_t s);
+hipError_t adam_exposures(const ExpArg& ea, const float* bc, float lr, float beta1, float beta2, float eps,
+                          hipStream_t s);
 hipError_t fill_u32(uint32_t* d, uint32_t val, int64_t n, hipStream_t s);
 hipError_t append_rows(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0, int64_t n, const float* means,
                        const float* ls, const float* quats, const float* logits, const float* sh, uint8_t* vis,

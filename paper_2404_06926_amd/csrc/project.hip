@@ -13,7 +13,8 @@ namespace gs {
 template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
-              float4* __restrict__ rec, uint32_t* __restrict__ counts) {
+              float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey,
+              uint32_t* __restrict__ dval) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -37,6 +38,9 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
           cnt += key_tile_hit(kp.mx, kp.my, kp.A, kp.B, kp.C, kp.thr, tx, ty) ? 1u : 0u;
     }
     counts[vi] = cnt;
+    // depth-sort key of the pair: float bits of a positive depth, largest key when unused
+    dkey[vi] = cnt ? __float_as_uint(kp.zh) : 0xffffffffu;
+    dval[vi] = (uint32_t)vi;
     if (cnt == 0) continue;
     // view-dependent colour: max(0, sum_k sh_k Y_k(dir) + 0.5)
     float dx = m0 - V.campos[0], dy = m1 - V.campos[1], dz = m2 - V.campos[2];
@@ -68,17 +72,23 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
 // reset to zero here, so the buffer is clean for the next backward). Output: gradients
 // added to the parameter planes, summed over views; vis[i] = 1 for Gaussians with a tile
 // in some view.
-template <int DEG>
+//
+// FUSED = true (one mapping step): instead of adding to the gradient planes, the kernel
+// adds any gradient already accumulated there, applies the sparse Adam update to the row
+// (same arithmetic as the separate Adam kernel), clears the accumulated gradient and the
+// visibility flag. Rows that reached no tile in this batch but were marked by an earlier
+// backward are updated from their accumulated gradient alone.
+template <int DEG, bool FUSED>
 __global__ void __launch_bounds__(256)
-k_project_bwd(const float* __restrict__ P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg va,
-              float near_z, const uint32_t* __restrict__ counts, float4* __restrict__ g2d,
-              uint8_t* __restrict__ vis) {
+k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg va, float near_z,
+              const uint32_t* __restrict__ counts, float4* __restrict__ g2d, const float4* __restrict__ inst_grad,
+              const uint32_t* __restrict__ inst_off, uint8_t* __restrict__ vis, AdamArg ad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
   bool any = false;
   for (int v = 0; v < va.n; ++v) any |= counts[(size_t)v * N + i] > 0;
-  if (!any) return;
+  if (!any && !(FUSED && vis[i])) return;
 
   const float mu[3] = {P[i], P[cap + i], P[2 * cap + i]};
   const float ls[3] = {P[3 * cap + i], P[4 * cap + i], P[5 * cap + i]};
@@ -86,7 +96,8 @@ k_project_bwd(const float* __restrict__ P, float* __restrict__ Gp, int64_t cap, 
   const float logit = P[10 * cap + i];
   // view-independent: normalised quaternion, rotation, scales, M = R S, Sigma = M M^T
   const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const float iqn = qn > 0.f ? 1.0f / qn : 0.f;
+  const float w = q[0] * iqn, x = q[1] * iqn, y = q[2] * iqn, z = q[3] * iqn;
   const float Rq[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
                        2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
                        2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
@@ -114,10 +125,25 @@ k_project_bwd(const float* __restrict__ P, float* __restrict__ Gp, int64_t cap, 
     const size_t vi = (size_t)v * N + i;
     if (counts[vi] == 0) continue;
     const ViewDev& V = va.v[v];
-    const float4 ga = g2d[vi * 4 + 0], gb = g2d[vi * 4 + 1], gc = g2d[vi * 4 + 2];
-    g2d[vi * 4 + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-    g2d[vi * 4 + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    g2d[vi * 4 + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 ga, gb, gc;
+    if (inst_grad) {
+      // deterministic: this pair's instance records, added in emission order
+      ga = gb = gc = make_float4(0.f, 0.f, 0.f, 0.f);
+      const uint32_t e0 = inst_off[vi], e1 = e0 + counts[vi];
+      for (uint32_t e = e0; e < e1; ++e) {
+        const float4 a = inst_grad[(size_t)e * 3], b = inst_grad[(size_t)e * 3 + 1], c = inst_grad[(size_t)e * 3 + 2];
+        ga.x += a.x; ga.y += a.y; ga.z += a.z; ga.w += a.w;
+        gb.x += b.x; gb.y += b.y; gb.z += b.z; gb.w += b.w;
+        gc.x += c.x;
+      }
+    } else {
+      ga = g2d[vi * 4 + 0];
+      gb = g2d[vi * 4 + 1];
+      gc = g2d[vi * 4 + 2];
+      g2d[vi * 4 + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      g2d[vi * 4 + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      g2d[vi * 4 + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     const float g_mx = ga.x, g_my = ga.y, g_A = ga.z, g_B = ga.w;
     const float g_C = gb.x, g_o = gb.y;
     const float g_col[3] = {gb.z, gb.w, gc.x};
@@ -246,57 +272,84 @@ k_project_bwd(const float* __restrict__ P, float* __restrict__ Gp, int64_t cap, 
   gq[3] = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] + y * gR[5] + x * gR[6] + y * gR[7]);
   const float qd = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
   const float unit[4] = {w, x, y, z};
-  float* g = Gp;
-  g[i] += gmu[0];
-  g[cap + i] += gmu[1];
-  g[2 * cap + i] += gmu[2];
+  float gl[11];
+  gl[0] = gmu[0];
+  gl[1] = gmu[1];
+  gl[2] = gmu[2];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g[(3 + k) * cap + i] += gls[k];
+  for (int k = 0; k < 3; ++k) gl[3 + k] = gls[k];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) g[(6 + k) * cap + i] += (gq[k] - qd * unit[k]) / qn;
-  g[10 * cap + i] += glogit;
+  for (int k = 0; k < 4; ++k) gl[6 + k] = (gq[k] - qd * unit[k]) * iqn;
+  gl[10] = glogit;
+  if (!FUSED) {
 #pragma unroll
-  for (int f = 0; f < 3 * K; ++f) g[(11 + f) * cap + i] += gsh[f];
-  vis[i] = 1;
+    for (int f = 0; f < 11; ++f) Gp[f * cap + i] += gl[f];
+#pragma unroll
+    for (int f = 0; f < 3 * K; ++f) Gp[(11 + f) * cap + i] += gsh[f];
+    vis[i] = 1;
+  } else {
+    const float bc1 = ad.bc[0], bc2 = ad.bc[1];
+    auto upd = [&](int f, float local) {
+      const int64_t k = (int64_t)f * cap + i;
+      const float acc = Gp[k];
+      const float gr = acc + local;  // what the separate path reads: 0 + gradient, plus earlier sums
+      if (acc != 0.0f) Gp[k] = 0.0f;
+      float pp = P[k], mm = ad.m[k], vv = ad.v[k];
+      adam_update(pp, mm, vv, gr, ad.lr.lr[f], ad.beta1, ad.beta2, ad.eps, bc1, bc2);
+      P[k] = pp;
+      ad.m[k] = mm;
+      ad.v[k] = vv;
+    };
+#pragma unroll
+    for (int f = 0; f < 11; ++f) upd(f, gl[f]);
+#pragma unroll
+    for (int f = 0; f < 3 * K; ++f) upd(11 + f, gsh[f]);
+    vis[i] = 0;
+  }
 }
 
 template <int DEG>
 static hipError_t launch_fwd(const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                             float4* rec, uint32_t* counts, hipStream_t s) {
+                             float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, hipStream_t s) {
   hipLaunchKernelGGL(k_project_fwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, cap, N, va,
-                     near_z, rec, counts);
+                     near_z, rec, counts, dkey, dval);
   return hipGetLastError();
 }
 
 template <int DEG>
-static hipError_t launch_bwd(const float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va,
-                             float near_z, const uint32_t* counts, float4* g2d, uint8_t* vis,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_project_bwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, G, cap, N, va,
-                     near_z, counts, g2d, vis);
+static hipError_t launch_bwd(float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
+                             const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
+                             uint8_t* vis, const AdamArg* ad, hipStream_t s) {
+  if (ad)
+    hipLaunchKernelGGL((k_project_bwd<DEG, true>), dim3((N + 255) / 256), dim3(256), 0, s, P, G, cap, N, va,
+                       near_z, counts, g2d, (const float4*)inst_grad, inst_off, vis, *ad);
+  else
+    hipLaunchKernelGGL((k_project_bwd<DEG, false>), dim3((N + 255) / 256), dim3(256), 0, s, P, G, cap, N, va,
+                       near_z, counts, g2d, (const float4*)inst_grad, inst_off, vis, AdamArg{});
   return hipGetLastError();
 }
 
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va,
-                           float near_z, float4* rec, uint32_t* counts, hipStream_t s) {
+                           float near_z, float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval,
+                           hipStream_t s) {
   if (N <= 0) return hipSuccess;
   switch (deg) {
-    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, s);
-    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, s);
-    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, s);
-    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, s);
+    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
+    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
+    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
+    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
   }
 }
 
-hipError_t project_backward(int deg, const float* P, float* G, int64_t cap, int32_t N,
-                            const ViewsArg& va, float near_z, const uint32_t* counts, float4* g2d,
-                            uint8_t* vis, hipStream_t s) {
+hipError_t project_backward(int deg, float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
+                            const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
+                            uint8_t* vis, const AdamArg* adam, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   switch (deg) {
-    case 0: return launch_bwd<0>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
-    case 1: return launch_bwd<1>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
-    case 2: return launch_bwd<2>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
-    default: return launch_bwd<3>(P, G, cap, N, va, near_z, counts, g2d, vis, s);
+    case 0: return launch_bwd<0>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
+    case 1: return launch_bwd<1>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
+    case 2: return launch_bwd<2>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
+    default: return launch_bwd<3>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
   }
 }
 

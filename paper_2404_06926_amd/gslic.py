@@ -92,11 +92,19 @@ _SIGS = {
     "gs_check_overflow": (_I32, [_P, _P, ctypes.POINTER(_I32)]),
     "gs_set_blend_config": (_I32, [_P, _I32, _I32]),
     "gs_set_stage_timing": (_I32, [_P, _I32]),
+    "gs_set_deterministic": (_I32, [_P, _I32]),
+    "gs_set_fused_step": (_I32, [_P, _I32]),
+    "gs_step": (_I32, [_P, _I32, ctypes.POINTER(GsView), ctypes.POINTER(GsFrame), ctypes.POINTER(_P), _F,
+                       ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _P]),
+    "gs_capture_step": (_I32, [_P, _I32, ctypes.POINTER(GsView), ctypes.POINTER(GsFrame), ctypes.POINTER(_P), _F,
+                               ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _P, ctypes.POINTER(_P)]),
+    "gs_launch_step": (_I32, [_P, _P]),
+    "gs_destroy_step": (_I32, [_P]),
     "gs_stage_times": (_I32, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
 }
 
 STAGES = ["project", "scan", "duplicate", "sort", "ranges", "blend", "loss", "blend_backward",
-          "project_backward", "adam"]
+          "project_backward", "adam", "depth_sort"]
 
 _lib = None
 
@@ -315,7 +323,10 @@ class GaussianMap:
             fr[k] = GsFrame(f.rgb.data_ptr(), f.final_T.data_ptr(), f.n_contrib.data_ptr())
             out.append(f)
         _check(lib().gs_render(self.handle, nv, views, fr, _stream(stream)))
+        # the kernels of this render and of render_backward read these buffers
         self._last_frames = out
+        self._last_exposures = list(exposures) if exposures is not None else None
+        self._last_nv = nv
         return out
 
     def render_backward(self, dl_drgb: Sequence, dl_dexposure: Optional[Sequence] = None, stream=None):
@@ -349,6 +360,33 @@ class GaussianMap:
                                         iters, window, float(lam), float(o_init), ev, _stream(stream)))
         self._keep = [image, xyz, rgb]
 
+    def _step_args(self, cams, frames, targets, exposure_states, grads, loss_out):
+        nv = len(cams)
+        views = (GsView * nv)(*[make_view(c) for c in cams])
+        fr = (GsFrame * nv)(*[GsFrame(f.rgb.data_ptr(), f.final_T.data_ptr(), f.n_contrib.data_ptr())
+                              for f in frames])
+        tg = (_P * nv)(*[t.data_ptr() for t in targets])
+        es = (_P * nv)(*[e.data_ptr() for e in exposure_states])
+        gr = (_P * nv)(*[g.data_ptr() for g in grads])
+        return nv, views, fr, tg, es, gr, _ptr(loss_out)
+
+    def step(self, cams, frames, targets, exposure_states, grads, loss_out, lam=0.2, stream=None):
+        """One mapping step (render, loss, backward, Adam) over the views in one batch."""
+        nv, views, fr, tg, es, gr, lo = self._step_args(cams, frames, targets, exposure_states, grads, loss_out)
+        _check(lib().gs_step(self.handle, nv, views, fr, tg, float(lam), es, gr, lo, _stream(stream)))
+        self._last_frames = frames
+        self._last_exposures = exposure_states
+        self._last_nv = nv
+
+    def capture_step(self, cams, frames, targets, exposure_states, grads, loss_out, lam=0.2, stream=None):
+        """A StepGraph replaying the same step; all tensors passed must stay alive."""
+        nv, views, fr, tg, es, gr, lo = self._step_args(cams, frames, targets, exposure_states, grads, loss_out)
+        h = _P()
+        _check(lib().gs_capture_step(self.handle, nv, views, fr, tg, float(lam), es, gr, lo, _stream(stream),
+                                     ctypes.byref(h)))
+        self._last_nv = nv
+        return StepGraph(h, keep=(frames, targets, exposure_states, grads, loss_out))
+
     # ------------------------------------------------------------- control
     def set_instance_policy(self, sync_plan: bool, capacity: int = 0):
         _check(lib().gs_set_instance_policy(self.handle, 1 if sync_plan else 0, int(capacity)))
@@ -357,6 +395,12 @@ class GaussianMap:
         o = _I32()
         _check(lib().gs_check_overflow(self.handle, _stream(stream), ctypes.byref(o)))
         return bool(o.value)
+
+    def set_fused_step(self, enable: bool):
+        _check(lib().gs_set_fused_step(self.handle, 1 if enable else 0))
+
+    def set_deterministic(self, enable: bool):
+        _check(lib().gs_set_deterministic(self.handle, 1 if enable else 0))
 
     def set_stage_timing(self, enable: bool):
         _check(lib().gs_set_stage_timing(self.handle, 1 if enable else 0))
@@ -369,8 +413,8 @@ class GaussianMap:
         return {name: (ms[k], cnt[k]) for k, name in enumerate(STAGES)}
 
     def debug_last_render(self, stream=None):
-        """Copies of the last render's sorted keys (int64 bits of the uint64 keys), values,
-        tile ranges and per-(view, Gaussian) projection records."""
+        """Copies of the last render's instance tiles and Gaussian indices (blend order),
+        tile ranges, per-(view, Gaussian) projection records and tile counts."""
         torch = _torch()
         k, v, r, p, c = _P(), _P(), _P(), _P(), _P()
         ni, nt = _I64(), _I64()
@@ -378,13 +422,13 @@ class GaussianMap:
                                           ctypes.byref(ni), ctypes.byref(r), ctypes.byref(nt), ctypes.byref(p),
                                           ctypes.byref(c)))
         n, T = ni.value, nt.value
-        nv = len(self._last_frames)
+        nv = self._last_nv
         out = dict(n_inst=n, n_tiles=T)
         if n > 0:
-            out["keys"] = self.allocator.view(k.value, 8 * n).view(torch.int64)[:n].clone()
+            out["tiles"] = self.allocator.view(k.value, 4 * n).view(torch.int32)[:n].clone()
             out["vals"] = self.allocator.view(v.value, 4 * n).view(torch.int32)[:n].clone()
         else:
-            out["keys"] = torch.zeros(0, dtype=torch.int64, device=self.device)
+            out["tiles"] = torch.zeros(0, dtype=torch.int32, device=self.device)
             out["vals"] = torch.zeros(0, dtype=torch.int32, device=self.device)
         out["ranges"] = self.allocator.view(r.value, 8 * T).view(torch.int32).view(T, 2).clone()
         out["proj"] = self.allocator.view(p.value, 64 * nv * max(self.n, 1)).view(torch.float32).view(
@@ -392,6 +436,28 @@ class GaussianMap:
         out["counts"] = self.allocator.view(c.value, 4 * nv * max(self.n, 1)).view(torch.int32).view(
             nv, max(self.n, 1))[:, : self.n].clone()
         return out
+
+
+class StepGraph:
+    """A captured mapping step (gs_capture_step); launch() replays it on a stream."""
+
+    def __init__(self, handle, keep=()):
+        self.handle = handle
+        self.keep = keep
+
+    def launch(self, stream=None):
+        _check(lib().gs_launch_step(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().gs_destroy_step(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class RenderFunction:

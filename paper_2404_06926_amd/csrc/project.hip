@@ -69,88 +69,173 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
 
 // Adjoint of the projection. Input: per (view, Gaussian) gradients of
 // (mean2d x, y, conic A, B, C, opacity, colour r, g, b) in 64-B records (consumed and
-// reset to zero here, so the buffer is clean for the next backward). Output: gradients
+// reset to zero here, so the buffer is clean for the next backward), or, in deterministic
+// mode, the sums of the pair's per-instance records in emission order. Output: gradients
 // added to the parameter planes, summed over views; vis[i] = 1 for Gaussians with a tile
 // in some view.
+//
+// Two phases keep register pressure low: first the colour (SH coefficients and the view
+// direction), which needs only the mean; then the geometry (mean, scale, rotation,
+// opacity), which needs the covariance.
 //
 // FUSED = true (one mapping step): instead of adding to the gradient planes, the kernel
 // adds any gradient already accumulated there, applies the sparse Adam update to the row
 // (same arithmetic as the separate Adam kernel), clears the accumulated gradient and the
 // visibility flag. Rows that reached no tile in this batch but were marked by an earlier
 // backward are updated from their accumulated gradient alone.
-template <int DEG, bool FUSED>
-__global__ void __launch_bounds__(256)
+//
+// The SH gradients of a single-view batch (MULTI = false) are emitted as soon as they are
+// formed; with several views they are summed in per-lane LDS slots first.
+__device__ __forceinline__ void pair_grad(size_t vi, const uint32_t* __restrict__ counts,
+                                          const float4* __restrict__ g2d, const float4* __restrict__ inst_grad,
+                                          const uint32_t* __restrict__ inst_off, float4& ga, float4& gb,
+                                          float4& gc) {
+  if (inst_grad) {
+    ga = gb = gc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t e0 = inst_off[vi], e1 = e0 + counts[vi];
+    for (uint32_t e = e0; e < e1; ++e) {
+      const float4 a = inst_grad[(size_t)e * 3], b = inst_grad[(size_t)e * 3 + 1], c = inst_grad[(size_t)e * 3 + 2];
+      ga.x += a.x; ga.y += a.y; ga.z += a.z; ga.w += a.w;
+      gb.x += b.x; gb.y += b.y; gb.z += b.z; gb.w += b.w;
+      gc.x += c.x;
+    }
+  } else {
+    ga = g2d[vi * 4 + 0];
+    gb = g2d[vi * 4 + 1];
+    gc = g2d[vi * 4 + 2];
+  }
+}
+
+template <int DEG, bool FUSED, bool MULTI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg va, float near_z,
               const uint32_t* __restrict__ counts, float4* __restrict__ g2d, const float4* __restrict__ inst_grad,
               const uint32_t* __restrict__ inst_off, uint8_t* __restrict__ vis, AdamArg ad) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ float s_gsh[MULTI ? 3 * K : 1][MULTI ? 256 : 1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  constexpr int K = (DEG + 1) * (DEG + 1);
+  // gradient g of plane f: added to the gradient planes, or one Adam update of the row
+  auto emit = [&](int f, float g) {
+    const int64_t k = (int64_t)f * cap + i;
+    if (!FUSED) {
+      Gp[k] += g;
+    } else {
+      const float acc = Gp[k];
+      const float gr = acc + g;  // what the separate path reads: 0 + gradient, plus earlier sums
+      if (acc != 0.0f) Gp[k] = 0.0f;
+      float pp = P[k], mm = ad.m[k], vv = ad.v[k];
+      adam_update(pp, mm, vv, gr, ad.lr.lr[f], ad.beta1, ad.beta2, ad.eps, ad.bc[0], ad.bc[1]);
+      P[k] = pp;
+      ad.m[k] = mm;
+      ad.v[k] = vv;
+    }
+  };
   bool any = false;
   for (int v = 0; v < va.n; ++v) any |= counts[(size_t)v * N + i] > 0;
   if (!any && !(FUSED && vis[i])) return;
 
-  const float mu[3] = {P[i], P[cap + i], P[2 * cap + i]};
-  const float ls[3] = {P[3 * cap + i], P[4 * cap + i], P[5 * cap + i]};
-  const float q[4] = {P[6 * cap + i], P[7 * cap + i], P[8 * cap + i], P[9 * cap + i]};
-  const float logit = P[10 * cap + i];
-  // view-independent: normalised quaternion, rotation, scales, M = R S, Sigma = M M^T
-  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float mu0 = P[i], mu1 = P[cap + i], mu2 = P[2 * cap + i];
+  float gmu[3] = {0.f, 0.f, 0.f};
+
+  // ---- phase 1: colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = normalised (mu - campos)
+  if (MULTI)
+    for (int f = 0; f < 3 * K; ++f) s_gsh[f][threadIdx.x] = 0.0f;
+  bool sh_done = false;  // single view: SH planes already emitted
+  for (int v = 0; v < va.n; ++v) {
+    const size_t vi = (size_t)v * N + i;
+    if (counts[vi] == 0) continue;
+    const ViewDev& V = va.v[v];
+    float4 ga, gb, gc;
+    pair_grad(vi, counts, g2d, inst_grad, inst_off, ga, gb, gc);
+    const float g_col[3] = {gb.z, gb.w, gc.x};
+    const float dv0 = mu0 - V.campos[0], dv1 = mu1 - V.campos[1], dv2 = mu2 - V.campos[2];
+    const float inv = rsqrtf(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
+    const float d0 = dv0 * inv, d1 = dv1 * inv, d2 = dv2 * inv;
+    float Y[K];
+    sh_basis<DEG>(d0, d1, d2, Y);
+    float wsum[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wsum[k] = 0.f;
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ++ch) {
+      float shc[K];
+      float raw = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        shc[k] = P[(int64_t)(11 + 3 * k + ch) * cap + i];
+        raw += shc[k] * Y[k];
+      }
+      const float gcol = raw < 0.0f ? 0.0f : g_col[ch];  // clamped channel: no gradient
+#pragma unroll 4
+      for (int k = 0; k < K; ++k) {
+        wsum[k] += gcol * shc[k];
+        if (MULTI)
+          s_gsh[3 * k + ch][threadIdx.x] += gcol * Y[k];
+        else
+          emit(11 + 3 * k + ch, gcol * Y[k]);
+      }
+    }
+    if (!MULTI) sh_done = true;
+    if (DEG > 0) {
+      float gdx, gdy, gdz;
+      sh_basis_grad<DEG>(d0, d1, d2, wsum, gdx, gdy, gdz);
+      const float dot = gdx * d0 + gdy * d1 + gdz * d2;
+      gmu[0] += (gdx - dot * d0) * inv;
+      gmu[1] += (gdy - dot * d1) * inv;
+      gmu[2] += (gdz - dot * d2) * inv;
+    }
+  }
+  if (MULTI) {
+    for (int f = 0; f < 3 * K; ++f) emit(11 + f, s_gsh[f][threadIdx.x]);
+  } else if (!sh_done) {
+    // single view without a tile in this batch (fused path, marked earlier): zero local part
+    for (int f = 0; f < 3 * K; ++f) emit(11 + f, 0.0f);
+  }
+
+  // ---- phase 2: geometry. Normalised quaternion, rotation, scales, M = R S, Sigma = M M^T
+  const float q0 = P[6 * cap + i], q1 = P[7 * cap + i], q2 = P[8 * cap + i], q3 = P[9 * cap + i];
+  const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
   const float iqn = qn > 0.f ? 1.0f / qn : 0.f;
-  const float w = q[0] * iqn, x = q[1] * iqn, y = q[2] * iqn, z = q[3] * iqn;
+  const float w = q0 * iqn, x = q1 * iqn, y = q2 * iqn, z = q3 * iqn;
   const float Rq[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
                        2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
                        2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
-  const float s[3] = {__expf(ls[0]), __expf(ls[1]), __expf(ls[2])};
+  const float s[3] = {__expf(P[3 * cap + i]), __expf(P[4 * cap + i]), __expf(P[5 * cap + i])};
   float M[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) M[3 * r + k] = Rq[3 * r + k] * s[k];
-  float Sg[9];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Sg[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
-  const float op = 1.0f / (1.0f + __expf(-logit));
-
-  float gmu[3] = {0, 0, 0};
+  float Sg[6];  // 00 01 02 11 12 22
+  Sg[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  Sg[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  Sg[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  Sg[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  Sg[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  Sg[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  const float op = 1.0f / (1.0f + __expf(-P[10 * cap + i]));
   float gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   float glogit = 0.0f;
-  float gsh[3 * K];
-#pragma unroll
-  for (int f = 0; f < 3 * K; ++f) gsh[f] = 0.0f;
 
   for (int v = 0; v < va.n; ++v) {
     const size_t vi = (size_t)v * N + i;
     if (counts[vi] == 0) continue;
     const ViewDev& V = va.v[v];
     float4 ga, gb, gc;
-    if (inst_grad) {
-      // deterministic: this pair's instance records, added in emission order
-      ga = gb = gc = make_float4(0.f, 0.f, 0.f, 0.f);
-      const uint32_t e0 = inst_off[vi], e1 = e0 + counts[vi];
-      for (uint32_t e = e0; e < e1; ++e) {
-        const float4 a = inst_grad[(size_t)e * 3], b = inst_grad[(size_t)e * 3 + 1], c = inst_grad[(size_t)e * 3 + 2];
-        ga.x += a.x; ga.y += a.y; ga.z += a.z; ga.w += a.w;
-        gb.x += b.x; gb.y += b.y; gb.z += b.z; gb.w += b.w;
-        gc.x += c.x;
-      }
-    } else {
-      ga = g2d[vi * 4 + 0];
-      gb = g2d[vi * 4 + 1];
-      gc = g2d[vi * 4 + 2];
-      g2d[vi * 4 + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-      g2d[vi * 4 + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-      g2d[vi * 4 + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pair_grad(vi, counts, g2d, inst_grad, inst_off, ga, gb, gc);
+    if (!inst_grad) {
+      const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+      g2d[vi * 4 + 0] = zero;
+      g2d[vi * 4 + 1] = zero;
+      g2d[vi * 4 + 2] = zero;
     }
     const float g_mx = ga.x, g_my = ga.y, g_A = ga.z, g_B = ga.w;
     const float g_C = gb.x, g_o = gb.y;
-    const float g_col[3] = {gb.z, gb.w, gc.x};
     const float* W = V.R;
-    const float xh = W[0] * mu[0] + W[1] * mu[1] + W[2] * mu[2] + V.t[0];
-    const float yh = W[3] * mu[0] + W[4] * mu[1] + W[5] * mu[2] + V.t[1];
-    const float zh = W[6] * mu[0] + W[7] * mu[1] + W[8] * mu[2] + V.t[2];
+    const float xh = W[0] * mu0 + W[1] * mu1 + W[2] * mu2 + V.t[0];
+    const float yh = W[3] * mu0 + W[4] * mu1 + W[5] * mu2 + V.t[1];
+    const float zh = W[6] * mu0 + W[7] * mu1 + W[8] * mu2 + V.t[2];
     const float iz = 1.0f / zh, iz2 = iz * iz;
     const float limx = 1.3f * (0.5f * (float)V.W / V.fx), limy = 1.3f * (0.5f * (float)V.H / V.fy);
     const float rx = xh * iz, ry = yh * iz;
@@ -163,12 +248,11 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
       T0[k] = J00 * W[k] + J02 * W[6 + k];
       T1[k] = J11 * W[3 + k] + J12 * W[6 + k];
     }
-    float ST0[3], ST1[3];  // Sigma T0, Sigma T1
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      ST0[r] = Sg[3 * r] * T0[0] + Sg[3 * r + 1] * T0[1] + Sg[3 * r + 2] * T0[2];
-      ST1[r] = Sg[3 * r] * T1[0] + Sg[3 * r + 1] * T1[1] + Sg[3 * r + 2] * T1[2];
-    }
+    // Sigma T0, Sigma T1
+    const float ST0[3] = {Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2], Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2],
+                          Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2]};
+    const float ST1[3] = {Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2], Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2],
+                          Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2]};
     const float a = T0[0] * ST0[0] + T0[1] * ST0[1] + T0[2] * ST0[2] + 0.3f;
     const float b = T0[0] * ST1[0] + T0[1] * ST1[1] + T0[2] * ST1[2];
     const float c = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2] + 0.3f;
@@ -178,19 +262,19 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     const float g_a = (-c * c * g_A + b * c * g_B - b * b * g_C) * id2;
     const float g_b = (2.f * b * c * g_A - (a * c + b * b) * g_B + 2.f * a * b * g_C) * id2;
     const float g_c = (-b * b * g_A + a * b * g_B - a * a * g_C) * id2;
-    // Sigma' = T Sigma T^T: dL/dSigma (symmetric part) and dL/dT
-    //   dL/dM = 2 Psym M with Psym = g_a T0 T0^T + g_b (T0 T1^T + T1 T0^T)/2 + g_c T1 T1^T
-    float Pm[9];
+    // Sigma' = T Sigma T^T: dL/dM = 2 Psym M with
+    // Psym = g_a T0 T0^T + g_b (T0 T1^T + T1 T0^T) / 2 + g_c T1 T1^T
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r) {
+      const float u = g_a * T0[r] + 0.5f * g_b * T1[r];   // row r of Psym = u T0^T + t T1^T
+      const float t = 0.5f * g_b * T0[r] + g_c * T1[r];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        Pm[3 * r + k] = g_a * T0[r] * T0[k] + 0.5f * g_b * (T0[r] * T1[k] + T1[r] * T0[k]) + g_c * T1[r] * T1[k];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        gM[3 * r + k] += 2.f * (Pm[3 * r] * M[k] + Pm[3 * r + 1] * M[3 + k] + Pm[3 * r + 2] * M[6 + k]);
+      for (int k = 0; k < 3; ++k) {
+        const float t0m = T0[0] * M[k] + T0[1] * M[3 + k] + T0[2] * M[6 + k];
+        const float t1m = T1[0] * M[k] + T1[1] * M[3 + k] + T1[2] * M[6 + k];
+        gM[3 * r + k] += 2.f * (u * t0m + t * t1m);
+      }
+    }
     float gT0[3], gT1[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -225,35 +309,6 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     gmu[1] += W[1] * gx + W[4] * gy + W[7] * gz;
     gmu[2] += W[2] * gx + W[5] * gy + W[8] * gz;
     glogit += g_o * op * (1.0f - op);
-    // colour through the SH direction
-    float dv[3] = {mu[0] - V.campos[0], mu[1] - V.campos[1], mu[2] - V.campos[2]};
-    const float inv = rsqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    const float d[3] = {dv[0] * inv, dv[1] * inv, dv[2] * inv};
-    float Y[K];
-    sh_basis<DEG>(d[0], d[1], d[2], Y);
-    float wsum[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) wsum[k] = 0.f;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float raw = 0.5f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) raw += P[(11 + 3 * k + ch) * cap + i] * Y[k];
-      if (raw < 0.0f) continue;  // clamped channel: no gradient
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        gsh[3 * k + ch] += g_col[ch] * Y[k];
-        wsum[k] += g_col[ch] * P[(11 + 3 * k + ch) * cap + i];
-      }
-    }
-    if (DEG > 0) {
-      float gdx, gdy, gdz;
-      sh_basis_grad<DEG>(d[0], d[1], d[2], wsum, gdx, gdy, gdz);
-      const float dot = gdx * d[0] + gdy * d[1] + gdz * d[2];
-      gmu[0] += (gdx - dot * d[0]) * inv;
-      gmu[1] += (gdy - dot * d[1]) * inv;
-      gmu[2] += (gdz - dot * d[2]) * inv;
-    }
   }
   // M = R diag(s): scales and rotation
   float gls[3], gR[9];
@@ -272,40 +327,15 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   gq[3] = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] + y * gR[5] + x * gR[6] + y * gR[7]);
   const float qd = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
   const float unit[4] = {w, x, y, z};
-  float gl[11];
-  gl[0] = gmu[0];
-  gl[1] = gmu[1];
-  gl[2] = gmu[2];
+  emit(0, gmu[0]);
+  emit(1, gmu[1]);
+  emit(2, gmu[2]);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gl[3 + k] = gls[k];
+  for (int k = 0; k < 3; ++k) emit(3 + k, gls[k]);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) gl[6 + k] = (gq[k] - qd * unit[k]) * iqn;
-  gl[10] = glogit;
-  if (!FUSED) {
-#pragma unroll
-    for (int f = 0; f < 11; ++f) Gp[f * cap + i] += gl[f];
-#pragma unroll
-    for (int f = 0; f < 3 * K; ++f) Gp[(11 + f) * cap + i] += gsh[f];
-    vis[i] = 1;
-  } else {
-    const float bc1 = ad.bc[0], bc2 = ad.bc[1];
-    auto upd = [&](int f, float local) {
-      const int64_t k = (int64_t)f * cap + i;
-      const float acc = Gp[k];
-      const float gr = acc + local;  // what the separate path reads: 0 + gradient, plus earlier sums
-      if (acc != 0.0f) Gp[k] = 0.0f;
-      float pp = P[k], mm = ad.m[k], vv = ad.v[k];
-      adam_update(pp, mm, vv, gr, ad.lr.lr[f], ad.beta1, ad.beta2, ad.eps, bc1, bc2);
-      P[k] = pp;
-      ad.m[k] = mm;
-      ad.v[k] = vv;
-    };
-#pragma unroll
-    for (int f = 0; f < 11; ++f) upd(f, gl[f]);
-#pragma unroll
-    for (int f = 0; f < 3 * K; ++f) upd(11 + f, gsh[f]);
-    vis[i] = 0;
-  }
+  for (int k = 0; k < 4; ++k) emit(6 + k, (gq[k] - qd * unit[k]) * iqn);
+  emit(10, glogit);
+  vis[i] = FUSED ? 0 : 1;
 }
 
 template <int DEG>
@@ -320,12 +350,24 @@ template <int DEG>
 static hipError_t launch_bwd(float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                              const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
                              uint8_t* vis, const AdamArg* ad, hipStream_t s) {
-  if (ad)
-    hipLaunchKernelGGL((k_project_bwd<DEG, true>), dim3((N + 255) / 256), dim3(256), 0, s, P, G, cap, N, va,
-                       near_z, counts, g2d, (const float4*)inst_grad, inst_off, vis, *ad);
-  else
-    hipLaunchKernelGGL((k_project_bwd<DEG, false>), dim3((N + 255) / 256), dim3(256), 0, s, P, G, cap, N, va,
-                       near_z, counts, g2d, (const float4*)inst_grad, inst_off, vis, AdamArg{});
+  const dim3 grid((N + 255) / 256), block(256);
+  const float4* ig = (const float4*)inst_grad;
+  const AdamArg a = ad ? *ad : AdamArg{};
+  if (va.n == 1) {
+    if (ad)
+      hipLaunchKernelGGL((k_project_bwd<DEG, true, false>), grid, block, 0, s, P, G, cap, N, va, near_z, counts, g2d,
+                         ig, inst_off, vis, a);
+    else
+      hipLaunchKernelGGL((k_project_bwd<DEG, false, false>), grid, block, 0, s, P, G, cap, N, va, near_z, counts,
+                         g2d, ig, inst_off, vis, a);
+  } else {
+    if (ad)
+      hipLaunchKernelGGL((k_project_bwd<DEG, true, true>), grid, block, 0, s, P, G, cap, N, va, near_z, counts, g2d,
+                         ig, inst_off, vis, a);
+    else
+      hipLaunchKernelGGL((k_project_bwd<DEG, false, true>), grid, block, 0, s, P, G, cap, N, va, near_z, counts,
+                         g2d, ig, inst_off, vis, a);
+  }
   return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@ composes the per-view steps in the paper's order:
 
     project (Sec. III-A, Eq. 1-3) -> emit (tile, Gaussian) pairs for tiles the footprint
     reaches (Sec. III-D.2) -> stable sort by (tile, depth) (Sec. III-A) -> per-tile ranges
-    -> blend front to back with exposure (Eq. 5, Sec. III-C.3) -> loss (Eq. 9)
+    -> blend front to back with exposure (Eq. 5, Sec. III-C.3), depth and opacity maps
+    (Eq. 6-7) -> loss (Eq. 9)
     -> adjoint -> sparse Adam (Sec. III-D.2, Sec. IV-A.1).
 
 Cameras are ``float64[16]`` = R_cw row-major (9), t_cw (3), fx, fy, cx, cy. Parameter rows
@@ -163,12 +164,14 @@ def _cat(projs, name):
 
 def render(projs, views, bins, tie_alpha=0.0, tie_T=0.0):
     """Tiled blend of every view. Returns per-view dicts with out (3,H,W), pre, T_final,
-    n_contrib and tie flags."""
+    n_contrib, tie flags, the depth map D and the opacity map O (H,W)."""
     mean2d, conic = _cat(projs, "mean2d"), _cat(projs, "conic")
     opac, colour = _cat(projs, "opacity"), _cat(projs, "colour")
+    depth = _cat(projs, "depth")
     res, base = [], 0
     for v in views:
         P = v.W * v.H
+        D, O = np.zeros(P), np.zeros(P)
         out, pre = np.zeros(3 * P), np.zeros(3 * P)
         Tf, nc, tie = np.zeros(P), np.zeros(P, np.int32), np.zeros(P, np.int32)
         ncon, sig = np.zeros(P, np.int32), np.zeros(P, np.uint64)
@@ -178,11 +181,12 @@ def render(projs, views, bins, tie_alpha=0.0, tie_T=0.0):
                               _p(bins["ranges"]), _p(bins["val"]), _p(mean2d), _p(conic),
                               _p(opac), _p(colour), _p(E), _p(bg), ctypes.c_double(tie_alpha),
                               ctypes.c_double(tie_T), _p(out), _p(pre), _p(Tf), _p(nc), _p(tie),
-                              _p(ncon), _p(sig))
+                              _p(ncon), _p(sig), _p(depth), _p(D), _p(O))
         res.append(dict(out=out.reshape(3, v.H, v.W), pre=pre.reshape(3, v.H, v.W),
                         T_final=Tf.reshape(v.H, v.W), n_contrib=nc.reshape(v.H, v.W),
                         tie=tie.reshape(v.H, v.W), n_contributors=ncon.reshape(v.H, v.W),
-                        signature=sig.reshape(v.H, v.W)))
+                        signature=sig.reshape(v.H, v.W), depth=D.reshape(v.H, v.W),
+                        opacity=O.reshape(v.H, v.W)))
         base += v.n_tiles
     return res
 
@@ -191,10 +195,12 @@ def render_pixels(projs, views, bins, view_index, pix, tie_alpha=0.0, tie_T=0.0)
     """Tiled blend of one view at the flat pixel indices `pix` only."""
     mean2d, conic = _cat(projs, "mean2d"), _cat(projs, "conic")
     opac, colour = _cat(projs, "opacity"), _cat(projs, "colour")
+    depth = _cat(projs, "depth")
     base = sum(v.n_tiles for v in views[:view_index])
     v = views[view_index]
     pix = np.ascontiguousarray(pix, dtype=np.int64)
     n = pix.shape[0]
+    D, O = np.zeros(n), np.zeros(n)
     out, Tf = np.zeros((n, 3)), np.zeros(n)
     nc, tie = np.zeros(n, np.int32), np.zeros(n, np.int32)
     E = np.ascontiguousarray(v.E, dtype=np.float64)
@@ -203,8 +209,8 @@ def render_pixels(projs, views, bins, view_index, pix, tie_alpha=0.0, tie_T=0.0)
                                  _p(bins["ranges"]), _p(bins["val"]), _p(mean2d), _p(conic), _p(opac),
                                  _p(colour), _p(E), _p(bg), ctypes.c_double(tie_alpha),
                                  ctypes.c_double(tie_T), ctypes.c_int64(n), _p(pix), _p(out), _p(Tf),
-                                 _p(nc), _p(tie))
-    return dict(out=out, T_final=Tf, n_contrib=nc, tie=tie)
+                                 _p(nc), _p(tie), _p(depth), _p(D), _p(O))
+    return dict(out=out, T_final=Tf, n_contrib=nc, tie=tie, depth=D, opacity=O)
 
 
 def render_brute(proj, view: OView):
@@ -212,14 +218,16 @@ def render_brute(proj, view: OView):
     N = proj["count"].shape[0]
     P = view.W * view.H
     out, Tf, nc = np.zeros(3 * P), np.zeros(P), np.zeros(P, np.int32)
+    D, O = np.zeros(P), np.zeros(P)
     E = np.ascontiguousarray(view.E, dtype=np.float64)
     bg = np.ascontiguousarray(view.bg, dtype=np.float64)
     lib().or_render_brute(ctypes.c_int(N), ctypes.c_int(view.W), ctypes.c_int(view.H),
                           _p(proj["visible"]), _p(proj["depth"]), _p(proj["mean2d"]),
                           _p(proj["conic"]), _p(proj["opacity"]), _p(proj["colour"]), _p(E),
-                          _p(bg), _p(out), _p(Tf), _p(nc))
+                          _p(bg), _p(out), _p(Tf), _p(nc), _p(D), _p(O))
     return dict(out=out.reshape(3, view.H, view.W), T_final=Tf.reshape(view.H, view.W),
-                n_contributors=nc.reshape(view.H, view.W))
+                n_contributors=nc.reshape(view.H, view.W), depth=D.reshape(view.H, view.W),
+                opacity=O.reshape(view.H, view.W))
 
 
 def loss(out, gt, lam):
@@ -234,24 +242,31 @@ def loss(out, gt, lam):
     return float(L), g, float(ss.value)
 
 
-def blend_backward(projs, views, bins, gouts, tie_alpha=0.0, tie_T=0.0):
-    """Adjoint of the blend: per view, per Gaussian (mean2d 2, conic 3, opacity, colour 3)
-    gradients, exposure gradients (12) and tie flags."""
+def blend_backward(projs, views, bins, gouts, tie_alpha=0.0, tie_T=0.0, gdepths=None, gopacs=None):
+    """Adjoint of the blend: per view, per Gaussian (mean2d 2, conic 3, opacity, colour 3,
+    depth) gradients, exposure gradients (12) and tie flags. gdepths / gopacs: optional
+    per-view dL/dD and dL/dO maps (H, W)."""
     mean2d, conic = _cat(projs, "mean2d"), _cat(projs, "conic")
     opac, colour = _cat(projs, "opacity"), _cat(projs, "colour")
+    depth = _cat(projs, "depth")
     Ntot = mean2d.shape[0]
-    g2d = np.zeros((Ntot, 9))
+    g2d = np.zeros((Ntot, 10))
     gtie = np.zeros(Ntot, np.uint8)
     gEs, base = [], 0
-    for v, go in zip(views, gouts):
+    for k, (v, go) in enumerate(zip(views, gouts)):
         gE = np.zeros(12)
         E = np.ascontiguousarray(v.E, dtype=np.float64)
         bg = np.ascontiguousarray(v.bg, dtype=np.float64)
         go = np.ascontiguousarray(go, dtype=np.float64).reshape(-1)
+        gD = None if gdepths is None or gdepths[k] is None else \
+            np.ascontiguousarray(gdepths[k], dtype=np.float64).reshape(-1)
+        gO = None if gopacs is None or gopacs[k] is None else \
+            np.ascontiguousarray(gopacs[k], dtype=np.float64).reshape(-1)
         lib().or_blend_backward(ctypes.c_int(v.W), ctypes.c_int(v.H), ctypes.c_int64(base),
                                 _p(bins["ranges"]), _p(bins["val"]), _p(mean2d), _p(conic),
                                 _p(opac), _p(colour), _p(E), _p(bg), ctypes.c_double(tie_alpha),
-                                ctypes.c_double(tie_T), _p(go), _p(g2d), _p(gE), _p(gtie))
+                                ctypes.c_double(tie_T), _p(go), _p(g2d), _p(gE), _p(gtie), _p(depth),
+                                _p(gD) if gD is not None else None, _p(gO) if gO is not None else None)
         gEs.append(gE)
         base += v.n_tiles
     Ns = [p["count"].shape[0] for p in projs]
@@ -300,10 +315,10 @@ def forward(params, deg, views, fp64=False, tie_alpha=0.0, tie_T=0.0):
     return projs, bins, rend
 
 
-def backward(params, deg, views, projs, bins, gouts, tie_alpha=0.0, tie_T=0.0):
+def backward(params, deg, views, projs, bins, gouts, tie_alpha=0.0, tie_T=0.0, gdepths=None, gopacs=None):
     """Full adjoint: parameter-row gradients summed over views, exposure gradients per view,
-    per-Gaussian tie flags (OR over views)."""
-    g2ds, gEs, gties = blend_backward(projs, views, bins, gouts, tie_alpha, tie_T)
+    per-Gaussian tie flags (OR over views). gdepths / gopacs: optional dL/dD and dL/dO."""
+    g2ds, gEs, gties = blend_backward(projs, views, bins, gouts, tie_alpha, tie_T, gdepths, gopacs)
     gp = np.zeros_like(np.asarray(params, dtype=np.float64))
     tie = np.zeros(gp.shape[0], np.uint8)
     for v, pr, g2d, gt in zip(views, projs, g2ds, gties):

@@ -463,22 +463,39 @@ int blend_pixel(const BlendIn& in, const uint32_t* ids, int n, double px, double
   return ncon;
 }
 
+// Colour (Eq. 5, background behind the last contributor, then the exposure affine), and
+// optionally the depth map D = sum_i d_i a_i T_i (Eq. 6) and the opacity map
+// O = sum_i a_i T_i (Eq. 7) as the plain sums over the contributors.
 void finish_pixel(const BlendIn& in, const std::vector<PairRec>& rec, double Tf, double* pre,
-                  double* out) {
+                  double* out, double* D = nullptr, double* O = nullptr) {
   double Cc[3] = {0, 0, 0};
   for (const PairRec& r : rec)
     for (int ch = 0; ch < 3; ++ch) Cc[ch] += in.colour[3 * r.g + ch] * r.alpha * r.T;
   for (int ch = 0; ch < 3; ++ch) pre[ch] = Cc[ch] + Tf * in.bg[ch];
   for (int r = 0; r < 3; ++r)
     out[r] = in.E[4 * r] * pre[0] + in.E[4 * r + 1] * pre[1] + in.E[4 * r + 2] * pre[2] + in.E[4 * r + 3];
+  if (D) {
+    double s = 0.0;
+    for (const PairRec& r : rec) s += in.depth[r.g] * r.alpha * r.T;
+    *D = s;
+  }
+  if (O) {
+    double s = 0.0;
+    for (const PairRec& r : rec) s += r.alpha * r.T;
+    *O = s;
+  }
 }
 
 // Adjoint of Eq. 5 + exposure at one pixel, written with suffix sums:
 //   pre = sum_i c_i a_i T_i + T_N bg,   T_i = prod_{j<i} (1 - a_j)
 //   d pre / d c_i = a_i T_i,   d pre / d a_i = T_i c_i - S_i / (1 - a_i),
 //   S_i = sum_{k>i} c_k a_k T_k + T_N bg.
+// D (Eq. 6) and O (Eq. 7) are the same sums with c_i replaced by d_i and by 1 and no
+// background term; gD and gO are dL/dD and dL/dO at this pixel (0 when not used).
+// Per-Gaussian gradient rows (N x 10): mean2d x, y, conic A, B, C, opacity, colour r, g, b,
+// camera-frame depth d.
 void pixel_adjoint(const BlendIn& in, const std::vector<PairRec>& rec, double Tf, const double* pre,
-                   const double* gout, double* g2d /*N x 9*/, double* gE) {
+                   const double* gout, double gD, double gO, double* g2d /*N x 10*/, double* gE) {
   double G[3];
   for (int c = 0; c < 3; ++c) G[c] = in.E[c] * gout[0] + in.E[4 + c] * gout[1] + in.E[8 + c] * gout[2];
   for (int r = 0; r < 3; ++r) {
@@ -492,9 +509,15 @@ void pixel_adjoint(const BlendIn& in, const std::vector<PairRec>& rec, double Tf
     for (int c = 0; c < 3; ++c)
       S[3 * i + c] = S[3 * (i + 1) + c] + (i + 1 < n ? in.colour[3 * rec[i + 1].g + c] * rec[i + 1].alpha * rec[i + 1].T : 0.0);
   // S[3*i + c] now holds S_i (contributions strictly behind i, plus background)
+  std::vector<double> SD(n + 1, 0.0), SO(n + 1, 0.0);  // the same suffix sums for D and O
+  for (int i = n - 2; i >= 0; --i) {
+    const PairRec& b = rec[i + 1];
+    SD[i] = SD[i + 1] + in.depth[b.g] * b.alpha * b.T;
+    SO[i] = SO[i + 1] + b.alpha * b.T;
+  }
   for (int i = 0; i < n; ++i) {
     const PairRec& r = rec[i];
-    double* gg = g2d + 9 * (size_t)r.g;
+    double* gg = g2d + 10 * (size_t)r.g;
     double da = 0.0;
     for (int c = 0; c < 3; ++c) {
       const double dc = r.alpha * r.T * G[c];
@@ -502,6 +525,13 @@ void pixel_adjoint(const BlendIn& in, const std::vector<PairRec>& rec, double Tf
       gg[6 + c] += dc;
       da += G[c] * (r.T * in.colour[3 * r.g + c] - S[3 * i + c] / (1.0 - r.alpha));
     }
+    if (gD != 0.0) {
+      const double dd = r.alpha * r.T * gD;
+#pragma omp atomic
+      gg[9] += dd;
+      da += gD * (r.T * in.depth[r.g] - SD[i] / (1.0 - r.alpha));
+    }
+    if (gO != 0.0) da += gO * (r.T - SO[i] / (1.0 - r.alpha));
     if (r.araw > kAlphaMax) continue;  // capped alpha: no gradient through it
     const double A = in.conic[3 * r.g], B = in.conic[3 * r.g + 1], C = in.conic[3 * r.g + 2];
     const double dpow = da * r.araw;  // d alpha / d power = alpha
@@ -539,7 +569,7 @@ void gauss_window(double* w) {
 
 extern "C" {
 
-int or_version() { return 3; }
+int or_version() { return 4; }
 
 // Per-Gaussian projection for one view. fp64 != 0 runs the key path in FP64, otherwise in
 // the fixed FP32 order. Outputs are per Gaussian (double arrays hold the exact values of
@@ -603,9 +633,10 @@ void or_render_tiled(int W, int H, int64_t tile_base, const int64_t* ranges /*gl
                      const uint32_t* vals, const double* mean2d, const double* conic,
                      const double* opac, const double* colour, const double* E, const double* bg,
                      double tie_alpha, double tie_T, double* out, double* pre, double* Tfinal,
-                     int32_t* ncontrib, int32_t* tie, int32_t* ncon, uint64_t* sig) {
+                     int32_t* ncontrib, int32_t* tie, int32_t* ncon, uint64_t* sig,
+                     const double* depth, double* Dout, double* Oout) {
   const int tiles_x = (W + 15) / 16;
-  BlendIn in{mean2d, conic, opac, colour, nullptr, E, bg, tie_alpha, tie_T};
+  BlendIn in{mean2d, conic, opac, colour, depth, E, bg, tie_alpha, tie_T};
   const int64_t P = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t pix = 0; pix < P; ++pix) {
@@ -617,7 +648,7 @@ void or_render_tiled(int W, int H, int64_t tile_base, const int64_t* ranges /*gl
     int nc, tf;
     const int k = blend_pixel(in, vals + s, (int)(e - s), x + 0.5, y + 0.5, &rec, &Tf, &nc, &tf);
     double pr[3], o[3];
-    finish_pixel(in, rec, Tf, pr, o);
+    finish_pixel(in, rec, Tf, pr, o, (Dout && depth) ? Dout + pix : nullptr, Oout ? Oout + pix : nullptr);
     for (int c = 0; c < 3; ++c) { out[c * P + pix] = o[c]; pre[c * P + pix] = pr[c]; }
     Tfinal[pix] = Tf;
     ncontrib[pix] = nc;
@@ -641,10 +672,11 @@ void or_render_tiled_pixels(int W, int H, int64_t tile_base, const int64_t* rang
                             const double* mean2d, const double* conic, const double* opac,
                             const double* colour, const double* E, const double* bg, double tie_alpha,
                             double tie_T, int64_t npix, const int64_t* pix, double* out /*npix x 3*/,
-                            double* Tfinal, int32_t* ncontrib, int32_t* tie) {
+                            double* Tfinal, int32_t* ncontrib, int32_t* tie, const double* depth,
+                            double* Dout, double* Oout) {
   const int tiles_x = (W + 15) / 16;
   (void)H;
-  BlendIn in{mean2d, conic, opac, colour, nullptr, E, bg, tie_alpha, tie_T};
+  BlendIn in{mean2d, conic, opac, colour, depth, E, bg, tie_alpha, tie_T};
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < npix; ++k) {
     const int x = (int)(pix[k] % W), y = (int)(pix[k] / W);
@@ -655,7 +687,7 @@ void or_render_tiled_pixels(int W, int H, int64_t tile_base, const int64_t* rang
     int nc, tf;
     blend_pixel(in, vals + s, (int)(e - s), x + 0.5, y + 0.5, &rec, &Tf, &nc, &tf);
     double pr[3], o[3];
-    finish_pixel(in, rec, Tf, pr, o);
+    finish_pixel(in, rec, Tf, pr, o, (Dout && depth) ? Dout + k : nullptr, Oout ? Oout + k : nullptr);
     for (int c = 0; c < 3; ++c) out[3 * k + c] = o[c];
     Tfinal[k] = Tf;
     ncontrib[k] = nc;
@@ -668,13 +700,13 @@ void or_render_tiled_pixels(int W, int H, int64_t tile_base, const int64_t* rang
 void or_render_brute(int N, int W, int H, const uint8_t* visible, const double* depth,
                      const double* mean2d, const double* conic, const double* opac,
                      const double* colour, const double* E, const double* bg, double* out,
-                     double* Tfinal, int32_t* ncon) {
+                     double* Tfinal, int32_t* ncon, double* Dout, double* Oout) {
   std::vector<uint32_t> order;
   for (int i = 0; i < N; ++i)
     if (visible[i]) order.push_back((uint32_t)i);
   std::stable_sort(order.begin(), order.end(),
                    [&](uint32_t a, uint32_t b) { return depth[a] < depth[b]; });
-  BlendIn in{mean2d, conic, opac, colour, nullptr, E, bg, 0.0, 0.0};
+  BlendIn in{mean2d, conic, opac, colour, depth, E, bg, 0.0, 0.0};
   const int64_t P = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t pix = 0; pix < P; ++pix) {
@@ -684,23 +716,25 @@ void or_render_brute(int N, int W, int H, const uint8_t* visible, const double* 
     int nc, tf;
     int k = blend_pixel(in, order.data(), (int)order.size(), x + 0.5, y + 0.5, &rec, &Tf, &nc, &tf);
     double pr[3], o[3];
-    finish_pixel(in, rec, Tf, pr, o);
+    finish_pixel(in, rec, Tf, pr, o, Dout ? Dout + pix : nullptr, Oout ? Oout + pix : nullptr);
     for (int c = 0; c < 3; ++c) out[c * P + pix] = o[c];
     Tfinal[pix] = Tf;
     ncon[pix] = k;
   }
 }
 
-// Adjoint of the tiled blend of one view: from dL/dout (CHW) to per-Gaussian gradients of
-// (mean2d x, y, conic A, B, C, opacity, colour r, g, b) accumulated into g2d (N x 9), and
-// of the exposure into gE (12). Gaussians evaluated at a tie pixel are flagged in gtie.
+// Adjoint of the tiled blend of one view: from dL/dout (CHW) and optionally dL/dD and
+// dL/dO (H x W, may be NULL) to per-Gaussian gradients of (mean2d x, y, conic A, B, C,
+// opacity, colour r, g, b, depth) accumulated into g2d (N x 10), and of the exposure into
+// gE (12). Gaussians evaluated at a tie pixel are flagged in gtie.
 void or_blend_backward(int W, int H, int64_t tile_base, const int64_t* ranges, const uint32_t* vals,
                        const double* mean2d, const double* conic, const double* opac,
                        const double* colour, const double* E, const double* bg,
                        double tie_alpha, double tie_T, const double* gout, double* g2d,
-                       double* gE, uint8_t* gtie) {
+                       double* gE, uint8_t* gtie, const double* depth, const double* gDmap,
+                       const double* gOmap) {
   const int tiles_x = (W + 15) / 16;
-  BlendIn in{mean2d, conic, opac, colour, nullptr, E, bg, tie_alpha, tie_T};
+  BlendIn in{mean2d, conic, opac, colour, depth, E, bg, tie_alpha, tie_T};
   const int64_t P = (int64_t)W * H;
   double gEacc[12] = {0};
 #pragma omp parallel
@@ -724,7 +758,7 @@ void or_blend_backward(int W, int H, int64_t tile_base, const int64_t* ranges, c
       double pr[3], o[3];
       finish_pixel(in, rec, Tf, pr, o);
       double go[3] = {gout[pix], gout[P + pix], gout[2 * P + pix]};
-      pixel_adjoint(in, rec, Tf, pr, go, g2d, gEl);
+      pixel_adjoint(in, rec, Tf, pr, go, gDmap ? gDmap[pix] : 0.0, gOmap ? gOmap[pix] : 0.0, g2d, gEl);
     }
 #pragma omp critical
     for (int k = 0; k < 12; ++k) gEacc[k] += gEl[k];
@@ -733,9 +767,10 @@ void or_blend_backward(int W, int H, int64_t tile_base, const int64_t* ranges, c
 }
 
 // Chain rule from the per-Gaussian 2D gradients of one view to the parameters (N x F),
-// accumulated into gparams. The Jacobian of (mean2d, conic, opacity, colour) with respect
-// to (mean, log-scale, quaternion, logit) is evaluated exactly with dual numbers through
-// the same projection as the forward pass (FP64); SH enters the colour linearly.
+// accumulated into gparams. The Jacobian of (mean2d, conic, opacity, colour, camera-frame
+// depth) with respect to (mean, log-scale, quaternion, logit) is evaluated exactly with dual
+// numbers through the same projection as the forward pass (FP64); SH enters the colour
+// linearly. g2d rows are N x 10 as written by or_blend_backward.
 void or_project_backward(int N, int deg, const double* params, const double* camv, int W, int H,
                          double near_z, const uint8_t* visible, const double* g2d, double* gparams) {
   const int K = (deg + 1) * (deg + 1), F = 11 + 3 * K;
@@ -744,7 +779,7 @@ void or_project_backward(int N, int deg, const double* params, const double* cam
   for (int i = 0; i < N; ++i) {
     if (!visible[i]) continue;
     const double* prm = params + (size_t)i * F;
-    const double* g = g2d + 9 * (size_t)i;
+    const double* g = g2d + 10 * (size_t)i;
     D11 geo[kGeo];
     for (int k = 0; k < kGeo; ++k) { geo[k] = D11(prm[k]); geo[k].d[k] = 1.0; }
     Proj<D11> P = project<D11>(prm, cam, near_z, geo);
@@ -753,11 +788,11 @@ void or_project_backward(int N, int deg, const double* params, const double* cam
     bool cl[3];
     double Y[16];
     sh_colour<D11>(deg, prm, geo, cam, col, cl, Y);
-    const D11* outs[9] = {&P.mx, &P.my, &P.ca, &P.cb, &P.cc, &P.op, &col[0], &col[1], &col[2]};
+    const D11* outs[10] = {&P.mx, &P.my, &P.ca, &P.cb, &P.cc, &P.op, &col[0], &col[1], &col[2], &P.zh};
     double* gp = gparams + (size_t)i * F;
     for (int k = 0; k < kGeo; ++k) {
       double s = 0.0;
-      for (int o = 0; o < 9; ++o) s += g[o] * outs[o]->d[k];
+      for (int o = 0; o < 10; ++o) s += g[o] * outs[o]->d[k];
       gp[k] += s;
     }
     for (int k = 0; k < K; ++k)

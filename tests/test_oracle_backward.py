@@ -13,11 +13,23 @@ def _fwd(params, deg, v):
     return projs, bins, rend[0]
 
 
-def _fd_check(params, deg, v, coords, h=1e-4, skip_frac=0.05, tol=2e-5):
+def _fd_check(params, deg, v, coords, h=1e-4, skip_frac=0.05, tol=2e-5, maps=False, colour=True):
+    """L = sum w * out (+ sum wD * D + sum wO * O with maps): the adjoint against central
+    differences of L, skipping coordinates whose step changes a contributor set."""
     rng = np.random.default_rng(1)
     projs, bins, r0 = _fwd(params, deg, v)
-    w = rng.normal(size=r0["out"].shape)           # L = sum w * out (linear functional)
-    gp, gE, _ = oracle.backward(params, deg, [v], projs, bins, [w])
+    w = rng.normal(size=r0["out"].shape) * (1.0 if colour else 0.0)
+    wD = rng.normal(size=r0["depth"].shape) if maps else None
+    wO = rng.normal(size=r0["opacity"].shape) if maps else None
+
+    def L(r):
+        val = (w * r["out"]).sum()
+        if maps:
+            val += (wD * r["depth"]).sum() + (wO * r["opacity"]).sum()
+        return val
+
+    gp, gE, _ = oracle.backward(params, deg, [v], projs, bins, [w],
+                                gdepths=[wD] if maps else None, gopacs=[wO] if maps else None)
     scale = np.abs(gp).max()
     skipped, checked, worst = 0, 0, 0.0
     for (i, f) in coords:
@@ -28,7 +40,7 @@ def _fd_check(params, deg, v, coords, h=1e-4, skip_frac=0.05, tol=2e-5):
             p[i, f] += sgn * h
             pr, bn, r = _fwd(p, deg, v)
             same &= np.array_equal(r["signature"], r0["signature"]) and np.array_equal(bn["val"], bins["val"])
-            vals.append((w * r["out"]).sum())
+            vals.append(L(r))
         if not same:
             skipped += 1
             continue
@@ -61,6 +73,40 @@ def test_adjoint_matches_finite_differences_sh3():
     wf = w.reshape(3, -1)
     expect = np.concatenate([wf @ pre.T, wf.sum(1, keepdims=True)], axis=1).reshape(12)
     np.testing.assert_allclose(gE[0], expect, rtol=1e-10)
+
+
+@pytest.mark.parametrize("colour", [False, True])
+def test_depth_and_opacity_map_adjoint_matches_finite_differences(colour):
+    # Eq. 6-7: L = sum wD D + sum wO O (+ sum w out), D = sum d_i a_i T_i with d_i the
+    # camera-frame depth, O = sum a_i T_i. Every geometric coordinate of sampled Gaussians.
+    cam = scenes.pinhole(48, 40, 40.0)
+    cam.R = scenes.axis_angle([0.1, -0.2, 0.05]).astype(np.float32)
+    cam.t = np.array([0.3, -0.2, 0.5], np.float32)
+    cam.exposure = scenes.random_exposure(21)
+    params = scenes.frustum_gaussians(200, 1, scenes.pinhole(48, 40, 40.0), seed=21).astype(np.float64)
+    v = oview(cam)
+    proj = oracle.project(params, 1, v, fp64=True)
+    vis = np.nonzero(proj["visible"])[0]
+    rng = np.random.default_rng(3)
+    coords = [(int(rng.choice(vis)), f) for f in range(params.shape[1]) for _ in range(3)]
+    checked, worst, _, _, _ = _fd_check(params, 1, v, coords, maps=True, colour=colour)
+    assert checked >= 0.95 * len(coords)
+
+
+def test_depth_map_gradient_reaches_only_geometry():
+    # D and O do not depend on SH or on the exposure: with L = sum wD D + sum wO O the SH
+    # columns and dL/dE are exactly zero, and the mean gradient is non-zero.
+    cam = scenes.pinhole(40, 32, 30.0)
+    cam.exposure = scenes.random_exposure(4)
+    params = scenes.frustum_gaussians(100, 2, cam, seed=4).astype(np.float64)
+    v = oview(cam)
+    projs, bins, r0 = _fwd(params, 2, v)
+    rng = np.random.default_rng(5)
+    gp, gE, _ = oracle.backward(params, 2, [v], projs, bins, [np.zeros((3, 32, 40))],
+                                gdepths=[rng.normal(size=(32, 40))], gopacs=[rng.normal(size=(32, 40))])
+    assert np.all(gp[:, 11:] == 0.0)
+    assert np.all(gE[0] == 0.0)
+    assert np.abs(gp[:, 0:3]).max() > 0
 
 
 def test_exposure_gradient_finite_differences():

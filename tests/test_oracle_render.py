@@ -43,6 +43,68 @@ def test_single_isotropic_gaussian_image_closed_form():
     assert abs(inside.sum() - area) <= 2 * np.pi * np.sqrt(2 * np.log(255 * o) * var) + 4
 
 
+def test_single_gaussian_depth_and_opacity_maps_closed_form():
+    # Eq. 6-7 for one Gaussian on the axis at depth Z: D = Z a and O = a where a >= 1/255.
+    cam = scenes.pinhole(64, 48, 50.0)
+    s, Z, o, f = 0.1, 5.0, 0.8, 50.0
+    _, _, r, _ = render_rows(gauss_row([0, 0, Z], np.log(s), logit=logit(o)), cam)
+    var = (f * s / Z) ** 2 + 0.3
+    ys, xs = np.mgrid[0:48, 0:64]
+    a = np.minimum(0.99, o * np.exp(-0.5 * ((xs + 0.5 - 32) ** 2 + (ys + 0.5 - 24) ** 2) / var))
+    a = np.where(a >= AMIN, a, 0.0)
+    tie = np.abs(a * 255 - 1) < 1e-9
+    np.testing.assert_allclose(r["depth"][~tie], (Z * a)[~tie], atol=1e-12)
+    np.testing.assert_allclose(r["opacity"][~tie], a[~tie], atol=1e-12)
+
+
+def test_two_gaussians_depth_and_opacity_maps():
+    # D = d1 a1 + d2 a2 (1 - a1), O = a1 + a2 (1 - a1), with d the camera-frame depth of a
+    # camera that is rotated and translated (depth is z in the camera frame, not |x|).
+    cam = scenes.pinhole(64, 48, 50.0)
+    cam.R = scenes.axis_angle([0.0, 0.15, 0.0]).astype(np.float32)
+    cam.t = np.array([0.1, 0.0, 0.4], np.float32)
+    g1 = gauss_row([0.6, 0.0, 4.0], np.log(0.09), logit=logit(0.6))
+    g2 = gauss_row([0.7, 0.03, 6.5], np.log(0.14), logit=logit(0.7))
+    pr, _, r, _ = render_rows(np.stack([g1, g2]), cam)
+    Rm = cam.R.astype(np.float64)
+    d = [(Rm @ g[0:3] + cam.t)[2] for g in (g1, g2)]
+    np.testing.assert_allclose(pr["depth"], d, rtol=1e-12)
+    ys, xs = np.mgrid[0:48, 0:64]
+
+    def alpha(k):
+        mx, my = pr["mean2d"][k]
+        A, B, C = pr["conic"][k]
+        dx, dy = xs + 0.5 - mx, ys + 0.5 - my
+        a = np.minimum(0.99, pr["opacity"][k] * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + C * dy * dy)))
+        return np.where(a >= AMIN, a, 0.0)
+
+    a1, a2 = alpha(0), alpha(1)
+    np.testing.assert_allclose(r["depth"], d[0] * a1 + d[1] * a2 * (1 - a1), atol=1e-12)
+    np.testing.assert_allclose(r["opacity"], a1 + a2 * (1 - a1), atol=1e-12)
+
+
+def test_opacity_map_equals_one_minus_final_transmittance():
+    # O = sum a_i prod_{j<i}(1 - a_j) telescopes to 1 - prod_i (1 - a_i) = 1 - T_final, and
+    # D lies within [min d, max d] * O of the pixel's contributors (a weighted mean times O).
+    cam = scenes.pinhole(96, 64, 80.0)
+    params = scenes.frustum_gaussians(3000, 0, cam, seed=17, log_scale_mean=-2.5).astype(np.float64)
+    pr, _, r, _ = render_rows(params, cam)
+    np.testing.assert_allclose(r["opacity"], 1.0 - r["T_final"], atol=1e-12)
+    vis = pr["visible"] > 0
+    dmin, dmax = pr["depth"][vis].min(), pr["depth"][vis].max()
+    assert np.all(r["depth"] >= dmin * r["opacity"] - 1e-9)
+    assert np.all(r["depth"] <= dmax * r["opacity"] + 1e-9)
+
+
+def test_depth_and_opacity_maps_tiled_equal_brute_force():
+    cam = scenes.pinhole(80, 56, 60.0)
+    params = scenes.frustum_gaussians(1500, 0, cam, seed=23, log_scale_mean=-2.7).astype(np.float64)
+    pr, _, r, v = render_rows(params, cam)
+    b = oracle.render_brute(pr, v)
+    np.testing.assert_allclose(r["depth"], b["depth"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r["opacity"], b["opacity"], rtol=1e-12, atol=1e-12)
+
+
 def test_opacity_integral_of_wide_gaussian():
     # sum over pixels of alpha -> 2 pi o sqrt(det Sigma') (1 - 1/(255 o)) for wide footprints
     cam = scenes.pinhole(256, 192, 200.0)

@@ -70,6 +70,8 @@ typedef struct {
   float near_z;              /* cull depth <= near_z (camera frame); 0.2 */
   float lr_mean, lr_log_scale, lr_quat, lr_opacity, lr_sh_dc, lr_sh_rest, lr_exposure;
   float beta1, beta2, eps;   /* Adam */
+  float expand_tau;          /* keyframe expansion threshold tau of Eq. 8 (0.99, Sec. IV-A.1);
+                                <= 0 appends every point of a keyframe */
 } gs_map_desc;
 
 /* One camera of a step. The pose maps world points into the camera frame
@@ -92,11 +94,17 @@ typedef struct {
  *                             Eq. 7); NULL = kept inside the map's workspace
  *   n_contrib uint32[H][W]    list position after the last contributing Gaussian of the
  *                             pixel's tile list; NULL = kept inside the workspace
+ *   depth     float[H][W]     depth map D = sum_i d_i a_i T_i, d_i the Gaussian's
+ *                             camera-frame depth (Sec. III-A Eq. 6); NULL = not computed
+ *   opacity   float[H][W]     opacity map O = sum_i a_i T_i = 1 - final_T (Eq. 7);
+ *                             NULL = not computed
  * When given, final_T and n_contrib must stay alive until gs_render_backward. */
 typedef struct {
   float* rgb;
   float* final_T;
   uint32_t* n_contrib;
+  float* depth;
+  float* opacity;
 } gs_frame;
 
 /* Defaults: SH 3, near 0.2, 3DGS learning rates, Adam (0.9, 0.999, 1e-15). */
@@ -124,6 +132,24 @@ gs_status gs_add_gaussians(gs_map* map, int64_t n, const float* means, const flo
 gs_status gs_add_points(gs_map* map, int64_t n, const float* xyz, const float* rgb,
                         const gs_view* view, float o_init, void* stream);
 
+/* Map expansion (Sec. III-C.2, Eq. 8): render the opacity map O of the current map at
+ * `view`, keep the points (device xyz, rgb: n_points x 3) whose projection falls inside
+ * the image on a pixel with O < tau, and append them in input order as Gaussians by the
+ * Sec. III-C.1 rule (as gs_add_points). The pixel of a point is decided in FP32:
+ * x_c = ((R00 x + R01 y) + R02 z) + t0 (likewise y_c, z_c), u = f_x (x_c / z_c) + c_x,
+ * v likewise; inside when z_c > near_z, 0 <= u < width, 0 <= v < height; pixel =
+ * (floor u, floor v). *n_added (host, may be NULL) receives the number appended; the call
+ * waits for the stream to read it. The render replaces the map's last render (a
+ * gs_render_backward cannot follow). GS_ERR_INVALID for tau <= 0 or o_init outside (0, 1). */
+gs_status gs_expand(gs_map* map, const gs_view* view, int64_t n_points, const float* xyz, const float* rgb,
+                    float tau, float o_init, int64_t* n_added, void* stream);
+
+/* Sky Gaussians (Sec. III-C.1): one Gaussian at each of the n >= 2 device positions xyz
+ * (n x 3; the caller draws them, e.g. on the upper hemisphere of radius R), white SH DC,
+ * opacity o_sky, identity rotation, isotropic scale = distance to the closest other of
+ * these positions (brute force on the device). */
+gs_status gs_add_sky(gs_map* map, int64_t n, const float* xyz, float o_sky, void* stream);
+
 /* Forward pass over n_views views of the same map in one batch (Sec. III-A Eq. 1-5,
  * Sec. III-C.3 exposure, Sec. III-D.2 tile culling). Tiles of all views are numbered
  * consecutively and processed by the same launches. Saves what gs_render_backward needs. */
@@ -131,11 +157,14 @@ gs_status gs_render(gs_map* map, int32_t n_views, const gs_view* views, const gs
                     void* stream);
 
 /* Reverse pass of the immediately preceding gs_render on this map (same n_views).
- * dL_drgb[v]: device float[3][H][W]. dL_dexposure[v]: device float[12] that receives
+ * dL_drgb[v]: device float[3][H][W]. dL_ddepth[v], dL_dopacity[v]: device float[H][W]
+ * gradients of the depth and opacity maps (Eq. 6-7); the arrays or any entry may be NULL
+ * (no gradient through that map). dL_dexposure[v]: device float[12] that receives
  * (+=) dL/d[A|b]; the array or any entry may be NULL. Parameter gradients are added to
  * the map's gradient planes (they accumulate until gs_adam_step) and the Gaussians seen
  * by any view are marked for the next sparse Adam step. GS_ERR_STATE without a render. */
 gs_status gs_render_backward(gs_map* map, int32_t n_views, const float* const* dL_drgb,
+                             const float* const* dL_ddepth, const float* const* dL_dopacity,
                              float* const* dL_dexposure, void* stream);
 
 /* One sparse Adam step (Sec. III-D.2, Sec. IV-A.1): rows marked since the last step move,
@@ -155,7 +184,8 @@ gs_status gs_loss(gs_map* map, const float* out, const float* gt, int32_t height
                   float lambda, float* loss_dev, float* dL_dout, void* stream);
 
 /* One mapping job on a keyframe (Sec. III-C): append Gaussians from the keyframe's points
- * (gs_add_points with o_init), store the keyframe (pose, a copy of `image`, an identity
+ * (gs_expand with the map's expand_tau, Eq. 8, or gs_add_points when expand_tau <= 0; with
+ * o_init), store the keyframe (pose, a copy of `image`, an identity
  * exposure with fresh Adam state) in a window of the `window` most recent keyframes
  * (window <= GS_MAX_VIEWS), then run `iters` steps, each = one batched gs_render over
  * the window, Eq. 9 loss per keyframe, gs_render_backward, gs_adam_step (Gaussians and
@@ -165,6 +195,22 @@ gs_status gs_submit_keyframe(gs_map* map, const gs_view* view, const float* imag
                              int64_t n_points, const float* xyz, const float* rgb,
                              int32_t iters, int32_t window, float lambda, float o_init,
                              void* done_event, void* stream);
+
+/* The paper's keyframe schedule (Sec. III-C.3): every keyframe is kept for the session.
+ * gs_add_keyframe expands the map with the keyframe's points (as gs_submit_keyframe) and
+ * keeps the keyframe (pose, a copy of `image`, an identity exposure with fresh Adam state)
+ * under the id written to *keyframe_id (0, 1, 2, ... in call order).
+ * gs_optimize_keyframes runs one mapping step (gs_step over that single keyframe: render,
+ * Eq. 9 loss, backward, Adam over the Gaussians and that keyframe's exposure) per entry of
+ * ids, sequentially in the given order. The selection of K keyframes and their shuffle
+ * are the caller's random draws, passed in as ids. done_event (hipEvent_t, may be NULL) is
+ * recorded after the last step. gs_keyframe_count reports how many are kept. */
+gs_status gs_add_keyframe(gs_map* map, const gs_view* view, const float* image, int64_t n_points,
+                          const float* xyz, const float* rgb, float o_init, int32_t* keyframe_id,
+                          void* stream);
+gs_status gs_optimize_keyframes(gs_map* map, int32_t n, const int32_t* ids, float lambda,
+                                void* done_event, void* stream);
+gs_status gs_keyframe_count(gs_map* map, int32_t* count);
 
 /* One mapping step over n_views keyframes of one map (Sec. III-C.3): one batched
  * gs_render, the Eq. 9 loss of every view against targets[v] (device float[3][H][W]),
@@ -273,7 +319,9 @@ gs_status gs_stage_times(gs_map* map, void* stream, double* ms, int64_t* count);
 gs_status gs_set_deterministic(gs_map* map, int32_t enable);
 
 /* Launch configuration of the blend kernels: pixels per lane in the forward and backward
- * (1, 2 or 4). Results do not depend on it beyond FP32 summation order. */
+ * (1, 2 or 4; default 1 and 4). With p pixels per lane a tile is processed by 256 / p
+ * lanes and each list entry's LDS reads and gradient reductions are shared by p pixels.
+ * Results do not depend on it beyond FP32 summation order. */
 gs_status gs_set_blend_config(gs_map* map, int32_t fwd_px_per_lane, int32_t bwd_px_per_lane);
 
 #ifdef __cplusplus

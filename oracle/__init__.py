@@ -325,3 +325,90 @@ def backward(params, deg, views, projs, bins, gouts, tie_alpha=0.0, tie_T=0.0, g
         gp += project_backward(params, deg, v, pr["visible"], g2d)
         tie |= gt
     return gp, gEs, tie
+
+
+# ------------------------------------------------------------------ map growth
+# Sec. III-C.1 (initialisation from points, sky) and Sec. III-C.2 (expansion, Eq. 8).
+# Plain numpy; the pixel a point falls on is an integer decision and is taken in the FP32
+# order of the key path (x_c = ((R00 x + R01 y) + R02 z) + t0, u = f_x (x_c / z_c) + c_x).
+
+SH_C0 = 0.28209479177387814   # Y_00 = 1 / (2 sqrt(pi))
+
+
+def point_pixels(xyz, view: OView, near=NEAR_Z):
+    """(inside, px, py, z) of each point under the view: camera-frame z > near and the
+    projection (u, v) within [0, W) x [0, H); px = floor(u), py = floor(v)."""
+    f32 = np.float32
+    c = np.asarray(view.cam, np.float64).astype(f32)
+    p = np.asarray(xyz, np.float64).astype(f32)
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    xc = ((c[0] * x + c[1] * y) + c[2] * z) + c[9]
+    yc = ((c[3] * x + c[4] * y) + c[5] * z) + c[10]
+    zc = ((c[6] * x + c[7] * y) + c[8] * z) + c[11]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = c[12] * (xc / zc) + c[14]
+        v = c[13] * (yc / zc) + c[15]
+    inside = (zc > f32(near)) & (u >= 0) & (u < f32(view.W)) & (v >= 0) & (v < f32(view.H))
+    px = np.where(inside, np.floor(np.where(inside, u, 0)), -1).astype(np.int64)
+    py = np.where(inside, np.floor(np.where(inside, v, 0)), -1).astype(np.int64)
+    return inside, px, py, zc.astype(np.float64)
+
+
+def init_points(xyz, rgb, view: OView, o_init, deg, near=NEAR_Z):
+    """Sec. III-C.1: one Gaussian per point, centred on it, SH DC so that it renders as the
+    point's colour (colour = Y00 dc + 0.5), other SH 0, opacity o_init, identity rotation,
+    isotropic scale d / f_x with d the point's depth in the view (clamped below at near)."""
+    xyz = np.asarray(xyz, np.float64)
+    rgb = np.asarray(rgb, np.float64)
+    n = xyz.shape[0]
+    R = np.asarray(view.cam[:9], np.float64).reshape(3, 3)
+    d = xyz @ R[2] + view.cam[11]
+    ls = np.log(np.maximum(d, near) / view.cam[12])
+    K = n_sh(deg)
+    rows = np.zeros((n, 11 + 3 * K))
+    rows[:, 0:3] = xyz
+    rows[:, 3:6] = ls[:, None]
+    rows[:, 6] = 1.0
+    rows[:, 10] = np.log(o_init / (1.0 - o_init))
+    rows[:, 11:14] = (rgb - 0.5) / SH_C0
+    return rows
+
+
+def expansion_select(xyz, view: OView, opacity, tau, near=NEAR_Z, tie=0.0):
+    """Eq. 8: M = O < tau over the keyframe's opacity map; a point is kept when it
+    projects inside the image onto a pixel of M. Returns (keep, tie_flags): tie_flags marks
+    points whose pixel has |O - tau| <= tie (a decision the FP32 path may take the other way)."""
+    inside, px, py, _ = point_pixels(xyz, view, near)
+    O = np.asarray(opacity, np.float64)
+    o = np.where(inside, O[np.maximum(py, 0), np.maximum(px, 0)], np.inf)
+    keep = inside & (o < tau)
+    ties = inside & (np.abs(o - tau) <= tie)
+    return keep, ties
+
+
+def nearest_neighbour_distance(xyz):
+    """Distance from every point to its closest other point (brute force)."""
+    p = np.asarray(xyz, np.float64)
+    n = p.shape[0]
+    out = np.full(n, np.inf)
+    for s in range(0, n, 1024):
+        d2 = ((p[s:s + 1024, None, :] - p[None, :, :]) ** 2).sum(-1)
+        idx = np.arange(s, min(s + 1024, n))
+        d2[idx - s, idx] = np.inf
+        out[s:s + 1024] = np.sqrt(d2.min(axis=1))
+    return out
+
+
+def init_sky(xyz, o_sky, deg):
+    """Sec. III-C.1 sky Gaussians at the given positions: white SH DC (colour 1), opacity
+    o_sky, identity rotation, isotropic scale = distance to the closest other sky Gaussian."""
+    xyz = np.asarray(xyz, np.float64)
+    n = xyz.shape[0]
+    K = n_sh(deg)
+    rows = np.zeros((n, 11 + 3 * K))
+    rows[:, 0:3] = xyz
+    rows[:, 3:6] = np.log(nearest_neighbour_distance(xyz))[:, None]
+    rows[:, 6] = 1.0
+    rows[:, 10] = np.log(o_sky / (1.0 - o_sky))
+    rows[:, 11:14] = (1.0 - 0.5) / SH_C0
+    return rows

@@ -54,6 +54,15 @@ struct KeyframeSlot {
   size_t pix_bytes = 0;        // bytes of one float plane of this slot's buffers
 };
 
+// A keyframe kept for the whole session (the random-K schedule): pose, owned copy of the
+// target image, exposure state [E | grad | m | v].
+struct ArchivedKeyframe {
+  gs_view view{};
+  float* image = nullptr;
+  float* state = nullptr;
+  size_t pix_bytes = 0;
+};
+
 struct gs_map {
   gs_map_desc desc{};
   gs_allocator alloc{};
@@ -76,8 +85,10 @@ struct gs_map {
   DevBuf emit_g, inst_off;     // Gaussian of each emission index; first emission index per pair
   DevBuf inst_grad, exp_part;  // deterministic backward: per-instance gradients, per-tile exposure sums
   DevBuf dbg_g;                // Gaussian index per instance in blend order (inspection only)
+  DevBuf gr_rgb, gr_T, gr_flags, gr_off, gr_tmp, gr_d2;  // map growth: render, selection, scan, sky
   bool deterministic = false;
   bool fused_step = true;      // gs_step applies Adam inside the projection backward
+  int fwd_px = 1, bwd_px = 4;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
   uint32_t* d_nvn = nullptr;   // number of (view, Gaussian) pairs of the last render
   int64_t vn_cap = 0, inst_cap = 0, tiles_cap = 0, pix_cap = 0;
   bool sync_plan = true;
@@ -89,6 +100,9 @@ struct gs_map {
   // keyframe window
   std::vector<KeyframeSlot> kf;
   int kf_next = 0;
+  // all keyframes (random-K schedule) and the single-view buffers its steps share
+  std::vector<ArchivedKeyframe> archive;
+  DevBuf ar_rgb, ar_T, ar_nc, ar_dl;
   // per-stage timing: event pairs recorded since the last query
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -248,6 +262,10 @@ void fill_viewdev(ViewDev& d, const gs_view& v) {
   d.exposure = v.exposure;
   d.dl_drgb = nullptr;
   d.dl_dexp = nullptr;
+  d.out_depth = nullptr;
+  d.out_opac = nullptr;
+  d.dl_ddepth = nullptr;
+  d.dl_dopac = nullptr;
 }
 
 // Records a start event for `stage` (when timing is on); stage_end records the stop.
@@ -293,6 +311,7 @@ void gs_default_desc(gs_map_desc* d) {
   d->beta1 = 0.9f;
   d->beta2 = 0.999f;
   d->eps = 1e-15f;
+  d->expand_tau = 0.99f;
 }
 
 const char* gs_last_error(void) { return g_err.c_str(); }
@@ -370,7 +389,8 @@ gs_status gs_destroy_map(gs_map* m) {
   DevBuf* bufs[] = {&m->rec, &m->counts, &m->offsets, &m->scan_tmp, &m->g2d, &m->keys[0], &m->keys[1],
                     &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp,
                     &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
-                    &m->inst_grad, &m->exp_part, &m->dbg_g};
+                    &m->inst_grad, &m->exp_part, &m->dbg_g, &m->gr_rgb, &m->gr_T, &m->gr_flags,
+                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl};
   for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
   for (KeyframeSlot& k : m->kf) {
     dev_free(m, k.image, 3 * k.pix_bytes, s);
@@ -379,6 +399,10 @@ gs_status gs_destroy_map(gs_map* m) {
     dev_free(m, k.T, k.pix_bytes, s);
     dev_free(m, k.nc, k.pix_bytes, s);
     dev_free(m, k.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+  }
+  for (ArchivedKeyframe& a : m->archive) {
+    dev_free(m, a.image, 3 * a.pix_bytes, s);
+    dev_free(m, a.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
   }
   if (m->h_pinned) (void)hipHostFree(m->h_pinned);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
@@ -419,6 +443,70 @@ gs_status gs_add_points(gs_map* m, int64_t n, const float* xyz, const float* rgb
   fill_viewdev(V, *view);
   const float logit0 = std::log(o_init / (1.0f - o_init));
   GS_HIP(init_points(m->buf, m->cap, m->F, m->K, m->n, n, xyz, rgb, V, m->desc.near_z, logit0, m->vis, s));
+  m->n += n;
+  m->have_render = false;
+  return GS_OK;
+}
+
+gs_status gs_expand(gs_map* m, const gs_view* view, int64_t n, const float* xyz, const float* rgb, float tau,
+                    float o_init, int64_t* n_added, void* stream) {
+  g_err.clear();
+  if (n_added) *n_added = 0;
+  if (!m || !view) return fail(GS_ERR_INVALID, "map and view must not be NULL");
+  if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+  if (!(tau > 0.f)) return fail(GS_ERR_INVALID, "tau must be > 0");
+  if (!(o_init > 0.f && o_init < 1.f)) return fail(GS_ERR_INVALID, "o_init must be in (0, 1)");
+  if (n == 0) return GS_OK;
+  if (!xyz || !rgb) return fail(GS_ERR_INVALID, "xyz and rgb must not be NULL");
+  if (m->capturing) return fail(GS_ERR_STATE, "expansion waits on the host and cannot be captured");
+  GS_TRY(check_view(*view, 0));
+  if (m->n + n > (int64_t)INT32_MAX) return fail(GS_ERR_CAPACITY, "more than 2^31-1 Gaussians");
+  if (n > (int64_t)UINT32_MAX) return fail(GS_ERR_CAPACITY, "too many points");
+  hipStream_t s = (hipStream_t)stream;
+  // O = 1 - T_final of the current map at the keyframe view
+  const int64_t P = (int64_t)view->width * view->height;
+  GS_TRY(ensure(m, m->gr_rgb, (size_t)P * 3 * 4, s));
+  GS_TRY(ensure(m, m->gr_T, (size_t)P * 4, s));
+  gs_frame fr{(float*)m->gr_rgb.ptr, (float*)m->gr_T.ptr, nullptr, nullptr, nullptr};
+  GS_TRY(gs_render(m, 1, view, &fr, stream));
+  m->have_render = false;  // the map grows below; this render has no backward
+  GS_TRY(ensure(m, m->gr_flags, (size_t)n * 4, s));
+  GS_TRY(ensure(m, m->gr_off, (size_t)n * 4, s));
+  GS_TRY(ensure(m, m->gr_tmp, (size_t)scan_temp_elems(n) * 4, s));
+  uint32_t* flags = (uint32_t*)m->gr_flags.ptr;
+  uint32_t* off = (uint32_t*)m->gr_off.ptr;
+  ViewDev V{};
+  fill_viewdev(V, *view);
+  GS_HIP(expand_flags(xyz, n, V, (const float*)m->gr_T.ptr, tau, m->desc.near_z, flags, s));
+  GS_HIP(exclusive_scan(flags, off, n, (uint32_t*)m->gr_tmp.ptr, s));
+  GS_HIP(hipMemcpyAsync(m->h_pinned, off + (n - 1), 4, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipMemcpyAsync(m->h_pinned + 1, flags + (n - 1), 4, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
+  const int64_t k = (int64_t)m->h_pinned[0] + (int64_t)m->h_pinned[1];
+  if (k > 0) {
+    GS_TRY(grow_capacity(m, m->n + k, s));
+    const float logit0 = std::log(o_init / (1.0f - o_init));
+    GS_HIP(init_selected(m->buf, m->cap, m->F, m->K, m->n, n, xyz, rgb, flags, off, V, m->desc.near_z, logit0,
+                         m->vis, s));
+    m->n += k;
+  }
+  if (n_added) *n_added = k;
+  return GS_OK;
+}
+
+gs_status gs_add_sky(gs_map* m, int64_t n, const float* xyz, float o_sky, void* stream) {
+  g_err.clear();
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (n == 0) return GS_OK;
+  if (n < 2) return fail(GS_ERR_INVALID, "sky initialisation needs n >= 2 (nearest-neighbour scale)");
+  if (!xyz) return fail(GS_ERR_INVALID, "xyz must not be NULL");
+  if (!(o_sky > 0.f && o_sky < 1.f)) return fail(GS_ERR_INVALID, "o_sky must be in (0, 1)");
+  if (m->n + n > (int64_t)INT32_MAX) return fail(GS_ERR_CAPACITY, "more than 2^31-1 Gaussians");
+  hipStream_t s = (hipStream_t)stream;
+  GS_TRY(ensure(m, m->gr_d2, (size_t)n * 4, s));
+  GS_TRY(grow_capacity(m, m->n + n, s));
+  const float logit0 = std::log(o_sky / (1.0f - o_sky));
+  GS_HIP(init_sky(m->buf, m->cap, m->F, m->K, m->n, n, xyz, (float*)m->gr_d2.ptr, logit0, m->vis, s));
   m->n += n;
   m->have_render = false;
   return GS_OK;
@@ -467,6 +555,8 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     d.out_rgb = frames[v].rgb;
     d.out_T = frames[v].final_T ? frames[v].final_T : (float*)m->pixT.ptr + d.pix_base;
     d.out_nc = frames[v].n_contrib ? frames[v].n_contrib : (uint32_t*)m->pixN.ptr + d.pix_base;
+    d.out_depth = frames[v].depth;
+    d.out_opac = frames[v].opacity;
   }
   float4* rec = (float4*)m->rec.ptr;
   uint32_t* counts = (uint32_t*)m->counts.ptr;
@@ -523,7 +613,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   }
   {
     StageTimer t(m, s, GS_STAGE_BLEND);
-    GS_HIP(blend_forward(va, rec, N, vals[which], (const uint32_t*)m->emit_g.ptr, ranges, s));
+    GS_HIP(blend_forward(va, rec, N, vals[which], (const uint32_t*)m->emit_g.ptr, ranges, m->fwd_px, s));
   }
   m->have_render = true;
   m->last_va = va;
@@ -532,17 +622,19 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   return GS_OK;
 }
 
-static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
-                               const AdamArg* fused, hipStream_t s);
+static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
+                               const float* const* dL_dopacity, float* const* dL_dexposure, const AdamArg* fused,
+                               hipStream_t s);
 
-gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
-                             void* stream) {
+gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
+                             const float* const* dL_dopacity, float* const* dL_dexposure, void* stream) {
   g_err.clear();
-  return backward_impl(m, nv, dL_drgb, dL_dexposure, nullptr, (hipStream_t)stream);
+  return backward_impl(m, nv, dL_drgb, dL_ddepth, dL_dopacity, dL_dexposure, nullptr, (hipStream_t)stream);
 }
 
-static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, float* const* dL_dexposure,
-                               const AdamArg* fused, hipStream_t stream) {
+static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
+                               const float* const* dL_dopacity, float* const* dL_dexposure, const AdamArg* fused,
+                               hipStream_t stream) {
   if (!m || !dL_drgb) return fail(GS_ERR_INVALID, "map and dL_drgb must not be NULL");
   if (!m->have_render) return fail(GS_ERR_STATE, "render_backward needs a preceding render of the same map");
   if (nv != m->last_va.n) return fail(GS_ERR_STATE, "n_views differs from the preceding render");
@@ -554,6 +646,8 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
   for (int v = 0; v < nv; ++v) {
     va.v[v].dl_drgb = dL_drgb[v];
     va.v[v].dl_dexp = dL_dexposure ? dL_dexposure[v] : nullptr;
+    va.v[v].dl_ddepth = dL_ddepth ? dL_ddepth[v] : nullptr;
+    va.v[v].dl_dopac = dL_dopacity ? dL_dopacity[v] : nullptr;
   }
   const int32_t N = m->last_N;
   float4* rec = (float4*)m->rec.ptr;
@@ -562,7 +656,7 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
     StageTimer t(m, s, GS_STAGE_BLEND_BACKWARD);
     GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr,
                           (const uint2*)m->ranges.ptr, g2d, m->deterministic ? (float*)m->inst_grad.ptr : nullptr,
-                          (float*)m->exp_part.ptr, s));
+                          (float*)m->exp_part.ptr, m->bwd_px, s));
   }
   {
     StageTimer t(m, s, GS_STAGE_PROJECT_BACKWARD);
@@ -619,7 +713,12 @@ gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image,
   if (n_points < 0 || (n_points > 0 && (!xyz || !rgb))) return fail(GS_ERR_INVALID, "bad point arguments");
   GS_TRY(check_view(*view, 0));
   hipStream_t s = (hipStream_t)stream;
-  if (n_points > 0) GS_TRY(gs_add_points(m, n_points, xyz, rgb, view, o_init, stream));
+  if (n_points > 0) {
+    if (m->desc.expand_tau > 0.f)
+      GS_TRY(gs_expand(m, view, n_points, xyz, rgb, m->desc.expand_tau, o_init, nullptr, stream));
+    else
+      GS_TRY(gs_add_points(m, n_points, xyz, rgb, view, o_init, stream));
+  }
   // keyframe slot (ring of `window`)
   if ((int)m->kf.size() > window) {
     for (size_t k = window; k < m->kf.size(); ++k) {
@@ -692,7 +791,7 @@ gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image,
   for (int j = 0; j < nk; ++j) {
     KeyframeSlot& q = m->kf[j];
     vv[j] = q.view;
-    ff[j] = gs_frame{q.rgb, q.T, q.nc};
+    ff[j] = gs_frame{q.rgb, q.T, q.nc, nullptr, nullptr};
     tg[j] = q.image;
     dl[j] = q.dl;
     es[j] = q.state;
@@ -700,6 +799,78 @@ gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image,
   for (int it = 0; it < iters; ++it)
     GS_TRY(gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream));
   if (done_event) GS_HIP(hipEventRecord((hipEvent_t)done_event, s));
+  return GS_OK;
+}
+
+gs_status gs_add_keyframe(gs_map* m, const gs_view* view, const float* image, int64_t n_points, const float* xyz,
+                          const float* rgb, float o_init, int32_t* keyframe_id, void* stream) {
+  g_err.clear();
+  if (keyframe_id) *keyframe_id = -1;
+  if (!m || !view || !image) return fail(GS_ERR_INVALID, "map, view and image must not be NULL");
+  if (n_points < 0 || (n_points > 0 && (!xyz || !rgb))) return fail(GS_ERR_INVALID, "bad point arguments");
+  if (m->archive.size() >= (size_t)INT32_MAX) return fail(GS_ERR_CAPACITY, "too many keyframes");
+  GS_TRY(check_view(*view, 0));
+  hipStream_t s = (hipStream_t)stream;
+  if (n_points > 0) {
+    if (m->desc.expand_tau > 0.f)
+      GS_TRY(gs_expand(m, view, n_points, xyz, rgb, m->desc.expand_tau, o_init, nullptr, stream));
+    else
+      GS_TRY(gs_add_points(m, n_points, xyz, rgb, view, o_init, stream));
+  }
+  ArchivedKeyframe a;
+  a.pix_bytes = (size_t)view->width * view->height * sizeof(float);
+  a.image = (float*)dev_alloc(m, 3 * a.pix_bytes, s);
+  a.state = (float*)dev_alloc(m, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+  if (!a.image || !a.state) {
+    dev_free(m, a.image, 3 * a.pix_bytes, s);
+    dev_free(m, a.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+    return fail(GS_ERR_OOM, "keyframe buffers");
+  }
+  GS_HIP(hipMemcpyAsync(a.image, image, 3 * a.pix_bytes, hipMemcpyDeviceToDevice, s));
+  // identity exposure, zero gradient and moments
+  GS_HIP(fill_u32((uint32_t*)a.state, 0u, GS_EXPOSURE_STATE_FLOATS, s));
+  GS_HIP(fill_u32((uint32_t*)a.state + 0, 0x3f800000u, 1, s));
+  GS_HIP(fill_u32((uint32_t*)a.state + 5, 0x3f800000u, 1, s));
+  GS_HIP(fill_u32((uint32_t*)a.state + 10, 0x3f800000u, 1, s));
+  a.view = *view;
+  a.view.exposure = a.state;
+  m->archive.push_back(a);
+  if (keyframe_id) *keyframe_id = (int32_t)(m->archive.size() - 1);
+  return GS_OK;
+}
+
+gs_status gs_optimize_keyframes(gs_map* m, int32_t n, const int32_t* ids, float lambda, void* done_event,
+                                void* stream) {
+  g_err.clear();
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (n < 0 || (n > 0 && !ids)) return fail(GS_ERR_INVALID, "bad keyframe list");
+  for (int32_t k = 0; k < n; ++k)
+    if (ids[k] < 0 || (size_t)ids[k] >= m->archive.size())
+      return fail(GS_ERR_INVALID, "keyframe id " + std::to_string(ids[k]) + " out of range");
+  hipStream_t s = (hipStream_t)stream;
+  size_t pb = 0;
+  for (int32_t k = 0; k < n; ++k) pb = std::max(pb, m->archive[ids[k]].pix_bytes);
+  if (n > 0) {
+    GS_TRY(ensure(m, m->ar_rgb, 3 * pb, s));
+    GS_TRY(ensure(m, m->ar_dl, 3 * pb, s));
+    GS_TRY(ensure(m, m->ar_T, pb, s));
+    GS_TRY(ensure(m, m->ar_nc, pb, s));
+  }
+  for (int32_t k = 0; k < n; ++k) {
+    ArchivedKeyframe& a = m->archive[ids[k]];
+    gs_frame fr{(float*)m->ar_rgb.ptr, (float*)m->ar_T.ptr, (uint32_t*)m->ar_nc.ptr, nullptr, nullptr};
+    const float* tg = a.image;
+    float* es = a.state;
+    float* dl = (float*)m->ar_dl.ptr;
+    GS_TRY(gs_step(m, 1, &a.view, &fr, &tg, lambda, &es, &dl, m->d_loss, stream));
+  }
+  if (done_event) GS_HIP(hipEventRecord((hipEvent_t)done_event, s));
+  return GS_OK;
+}
+
+gs_status gs_keyframe_count(gs_map* m, int32_t* count) {
+  if (!m || !count) return fail(GS_ERR_INVALID, "NULL argument");
+  *count = (int32_t)m->archive.size();
   return GS_OK;
 }
 
@@ -726,7 +897,7 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
     GS_TRY(gs_loss(m, frames[v].rgb, targets[v], vv[v].height, vv[v].width, lambda, loss_dev + v, dl_drgb[v],
                    stream));
   if (!m->fused_step) {
-    GS_TRY(gs_render_backward(m, nv, dl, eg, stream));
+    GS_TRY(gs_render_backward(m, nv, dl, nullptr, nullptr, eg, stream));
     GS_TRY(gs_adam_step(m, nv, exposure_states, stream));
     return GS_OK;
   }
@@ -743,7 +914,7 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   ad.beta1 = d.beta1;
   ad.beta2 = d.beta2;
   ad.eps = d.eps;
-  GS_TRY(backward_impl(m, nv, dl, eg, &ad, s));
+  GS_TRY(backward_impl(m, nv, dl, nullptr, nullptr, eg, &ad, s));
   ExpArg ea{};
   ea.n = nv;
   for (int v = 0; v < nv; ++v) ea.p[v] = exposure_states[v];
@@ -928,7 +1099,11 @@ gs_status gs_set_deterministic(gs_map* m, int32_t enable) {
 
 gs_status gs_set_blend_config(gs_map* m, int32_t fwd, int32_t bwd) {
   if (!m) return fail(GS_ERR_INVALID, "map is NULL");
-  if (fwd != 1 || bwd != 1) return fail(GS_ERR_UNIMPLEMENTED, "only one pixel per lane is built");
+  auto ok = [](int32_t px) { return px == 1 || px == 2 || px == 4; };
+  if (!ok(fwd) || !ok(bwd)) return fail(GS_ERR_INVALID, "pixels per lane must be 1, 2 or 4");
+  if (m->capturing) return fail(GS_ERR_STATE, "cannot change the blend configuration while capturing");
+  m->fwd_px = fwd;
+  m->bwd_px = bwd;
   return GS_OK;
 }
 

@@ -303,23 +303,35 @@ k_duplicate(const float4* __restrict__ rec, const uint32_t* __restrict__ counts,
                  r3 = rec[(size_t)vi * 4 + 3];
     const uint32_t a = __float_as_uint(r3.x), b = __float_as_uint(r3.y);
     const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
-    // same predicate as the count pass; writes never leave this pair's [o, o + cnt)
+    const int rw = x1 - x0 + 1;
     const int64_t end = o + cnt;
     int64_t w = o;
-    for (int ty = y0; ty <= y1 && w < end; ++ty)
-      for (int tx = x0; tx <= x1 && w < end; ++tx)
-        if (key_tile_hit(r0.x, r0.y, r0.z, r0.w, r1.x, r2.w, tx, ty)) {
-          const uint32_t tile = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
-          if (staged) {
-            s_tile[w - lo] = tile;
-            s_g[w - lo] = g;
-          } else {
-            tiles_out[w] = tile;
-            vals_out[w] = (uint32_t)w;
-            emit_g[w] = g;
-          }
-          ++w;
-        }
+    auto put = [&](int tx, int ty) {
+      const uint32_t tile = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+      if (staged) {
+        s_tile[w - lo] = tile;
+        s_g[w - lo] = g;
+      } else {
+        tiles_out[w] = tile;
+        vals_out[w] = (uint32_t)w;
+        emit_g[w] = g;
+      }
+      ++w;
+    };
+    if (rw * (y1 - y0 + 1) <= 64) {
+      // the count pass recorded which tiles passed
+      uint64_t hits = (uint64_t)__float_as_uint(r3.z) | ((uint64_t)__float_as_uint(r3.w) << 32);
+      while (hits && w < end) {
+        const int k = __ffsll((long long)hits) - 1;
+        hits &= hits - 1;
+        put(x0 + k % rw, y0 + k / rw);
+      }
+    } else {
+      // same predicate as the count pass; writes never leave this pair's [o, o + cnt)
+      for (int ty = y0; ty <= y1 && w < end; ++ty)
+        for (int tx = x0; tx <= x1 && w < end; ++tx)
+          if (key_tile_hit(r0.x, r0.y, r0.z, r0.w, r1.x, r2.w, tx, ty)) put(tx, ty);
+    }
     // unreachable when both passes agree; the sentinel tile sorts after every real tile
     for (; w < end; ++w) {
       if (staged) {

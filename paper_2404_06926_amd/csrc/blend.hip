@@ -9,6 +9,12 @@
 // threshold widened by 1e-4 (relative and absolute), so a skipped entry would have been
 // skipped by the per-pixel alpha cut-off as well and the outputs are unchanged.
 //
+// Launch shapes: PX pixels per lane (1, 2 or 4), 256 / PX lanes per tile, so the per-entry
+// LDS reads and the per-Gaussian wave reductions of the backward are shared by PX pixels.
+//
+// The forward also writes, for views that ask, the depth map (Eq. 6) and the opacity map
+// (Eq. 7, as 1 - T_final).
+//
 // The forward saves per pixel the final transmittance and the list position after the
 // last contributor; the backward starts from them (no forward replay), walks the list
 // from that position down to 0, recovers T_i = T_{i+1} / (1 - alpha_i), keeps the colour
@@ -76,147 +82,235 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   return x;
 }
 
-__global__ void __launch_bounds__(kBlendBlock)
+// Pixels of a lane. PX pixels per lane, 256 / PX lanes (4 / PX waves) per tile:
+//   PX = 1: wave w owns quadrant w, one pixel per lane;
+//   PX = 2: wave w owns the 8-wide column half w, pixels (x, y) and (x, y + 8);
+//   PX = 4: one wave owns the tile, pixel k of a lane lies in quadrant k.
+// Quadrant q covers x half q & 1 and y half q >> 1 of the tile.
+template <int PX>
+__device__ __forceinline__ void lane_pixel(int wid, int lane, int k, int& lx, int& ly) {
+  if (PX == 1) {
+    lx = 8 * (wid & 1) + (lane & 7);
+    ly = 8 * (wid >> 1) + (lane >> 3);
+  } else if (PX == 2) {
+    lx = 8 * wid + (lane & 7);
+    ly = 8 * k + (lane >> 3);
+  } else {
+    lx = 8 * (k & 1) + (lane & 7);
+    ly = 8 * (k >> 1) + (lane >> 3);
+  }
+}
+
+template <int PX>
+__device__ __forceinline__ int pixel_quadrant(int wid, int k) {
+  return PX == 1 ? wid : (PX == 2 ? wid + 2 * k : k);
+}
+
+// DEPTH: also accumulate the depth map D = sum d_i a_i T_i (Eq. 6) for views that ask.
+template <int PX, bool DEPTH>
+__global__ void __launch_bounds__(kBlendBlock / PX)
 k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
             const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges) {
-  __shared__ float4 s_a[kBlendBlock];   // mx, my, A, B
-  __shared__ float4 s_b[kBlendBlock];   // C, o, r, g
-  __shared__ float s_c[kBlendBlock];    // b
-  __shared__ uint8_t s_m[kBlendBlock];  // quadrant mask
+  constexpr int NT = kBlendBlock / PX;
+  __shared__ float4 s_a[NT];   // mx, my, A, B
+  __shared__ float4 s_b[NT];   // C, o, r, g
+  __shared__ float s_c[NT];    // b
+  __shared__ float s_d[DEPTH ? NT : 1];  // camera-frame depth
+  __shared__ uint8_t s_m[NT];  // quadrant mask
   const int tile = blockIdx.x;
   const int v = view_of_tile(va, tile);
   const ViewDev& V = va.v[v];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int px = tx * kTile + 8 * (wid & 1) + (lane & 7);
-  const int py = ty * kTile + 8 * (wid >> 1) + (lane >> 3);
-  const bool inside = px < V.W && py < V.H;
-  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
   const int n = (int)(rg.y - rg.x);
   const float4* vrec = rec + (size_t)v * N * 4;
 
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t last = 0;
-  bool done = !inside;
-  for (int base = 0; base < n; base += kBlendBlock) {
-    if (__syncthreads_count(done) == kBlendBlock) break;
-    const int k = base + (int)threadIdx.x;
-    if (k < n) {
-      const uint32_t g = emit_g[vals[rg.x + k]];
+  float pxc[PX], pyc[PX], T[PX], C0[PX], C1[PX], C2[PX], Dm[PX];
+  uint32_t last[PX];
+  bool done[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    int lx, ly;
+    lane_pixel<PX>(wid, lane, k, lx, ly);
+    const int px = tx * kTile + lx, py = ty * kTile + ly;
+    pxc[k] = (float)px + 0.5f;
+    pyc[k] = (float)py + 0.5f;
+    done[k] = !(px < V.W && py < V.H);
+    T[k] = 1.0f;
+    C0[k] = C1[k] = C2[k] = Dm[k] = 0.0f;
+    last[k] = 0;
+  }
+  auto all_done = [&]() {
+    bool d = true;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) d = d && done[k];
+    return d;
+  };
+  bool lane_done = all_done();
+  for (int base = 0; base < n; base += NT) {
+    if (__syncthreads_count(lane_done) == NT) break;
+    const int kk = base + (int)threadIdx.x;
+    if (kk < n) {
+      const uint32_t g = emit_g[vals[rg.x + kk]];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
       s_a[threadIdx.x] = r0;
       s_b[threadIdx.x] = r1;
       s_c[threadIdx.x] = r2.x;
+      if (DEPTH) s_d[threadIdx.x] = r2.y;
       s_m[threadIdx.x] = (uint8_t)quadrant_mask(r0, r1, r2.w, tx, ty);
     }
     __syncthreads();
-    const int cnt = min(kBlendBlock, n - base);
-    if (!done) {
+    const int cnt = min(NT, n - base);
+    if (!lane_done) {
       for (int j = 0; j < cnt; ++j) {
-        if (!((s_m[j] >> wid) & 1u)) continue;
+        const uint32_t m = s_m[j];
         const float4 a = s_a[j];
         const float4 b = s_b[j];
-        float dx, dy;
-        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
-        if (power > 0.0f) continue;
-        const float alpha = fminf(kAlphaMax, b.y * __expf(power));
-        if (alpha < kAlphaMin) continue;
-        const float Tn = T * (1.0f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          if (!((m >> pixel_quadrant<PX>(wid, k)) & 1u) || done[k]) continue;
+          float dx, dy;
+          const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
+          if (power > 0.0f) continue;
+          const float alpha = fminf(kAlphaMax, b.y * __expf(power));
+          if (alpha < kAlphaMin) continue;
+          const float Tn = T[k] * (1.0f - alpha);
+          if (Tn < kTMin) {
+            done[k] = true;
+            continue;
+          }
+          const float w = alpha * T[k];
+          C0[k] += b.z * w;
+          C1[k] += b.w * w;
+          C2[k] += s_c[j] * w;
+          if (DEPTH) Dm[k] += s_d[j] * w;
+          T[k] = Tn;
+          last[k] = (uint32_t)(base + j + 1);
         }
-        const float w = alpha * T;
-        C0 += b.z * w;
-        C1 += b.w * w;
-        C2 += s_c[j] * w;
-        T = Tn;
-        last = (uint32_t)(base + j + 1);
+        lane_done = all_done();
+        if (lane_done) break;
       }
     }
   }
-  if (!inside) return;
-  const int64_t p = (int64_t)py * V.W + px;
   const int64_t P = (int64_t)V.W * V.H;
-  const float pre0 = C0 + T * V.bg[0], pre1 = C1 + T * V.bg[1], pre2 = C2 + T * V.bg[2];
-  float o0 = pre0, o1 = pre1, o2 = pre2;
-  if (V.exposure) {
-    const float* E = V.exposure;
-    o0 = E[0] * pre0 + E[1] * pre1 + E[2] * pre2 + E[3];
-    o1 = E[4] * pre0 + E[5] * pre1 + E[6] * pre2 + E[7];
-    o2 = E[8] * pre0 + E[9] * pre1 + E[10] * pre2 + E[11];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const int px = (int)pxc[k], py = (int)pyc[k];
+    if (px >= V.W || py >= V.H) continue;
+    const int64_t p = (int64_t)py * V.W + px;
+    const float pre0 = C0[k] + T[k] * V.bg[0], pre1 = C1[k] + T[k] * V.bg[1], pre2 = C2[k] + T[k] * V.bg[2];
+    float o0 = pre0, o1 = pre1, o2 = pre2;
+    if (V.exposure) {
+      const float* E = V.exposure;
+      o0 = E[0] * pre0 + E[1] * pre1 + E[2] * pre2 + E[3];
+      o1 = E[4] * pre0 + E[5] * pre1 + E[6] * pre2 + E[7];
+      o2 = E[8] * pre0 + E[9] * pre1 + E[10] * pre2 + E[11];
+    }
+    V.out_rgb[p] = o0;
+    V.out_rgb[P + p] = o1;
+    V.out_rgb[2 * P + p] = o2;
+    V.out_T[p] = T[k];
+    V.out_nc[p] = last[k];
+    if (DEPTH && V.out_depth) V.out_depth[p] = Dm[k];
+    if (V.out_opac) V.out_opac[p] = 1.0f - T[k];  // Eq. 7 telescoped: sum a_i T_i = 1 - T_final
   }
-  V.out_rgb[p] = o0;
-  V.out_rgb[P + p] = o1;
-  V.out_rgb[2 * P + p] = o2;
-  V.out_T[p] = T;
-  V.out_nc[p] = last;
 }
 
 // DET = false: each wave's per-Gaussian sums go to g2d with float atomics.
-// DET = true: the four waves' sums are added in wave order in LDS and every instance's
+// DET = true: the waves' sums are added in wave order in LDS and every instance's
 // gradient is written to inst_grad[emission index]; the exposure gradient of each tile is
 // written to exp_part[tile] for a fixed-order reduction. No atomics, so the result does not
 // depend on scheduling.
-template <bool DET>
-__global__ void __launch_bounds__(kBlendBlock)
+// MAPS: views may carry dL/dD and dL/dO (Eq. 6-7); they add to dL/dalpha through the same
+// behind-the-Gaussian recursion with d_i and 1 in place of the colour (no background), and
+// give a tenth gradient, dL/d(camera-frame depth) = sum_px a_i T_i dL/dD.
+template <int PX, bool DET, bool MAPS>
+__global__ void __launch_bounds__(kBlendBlock / PX)
 k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
             const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, float* __restrict__ g2d,
             float* __restrict__ inst_grad, float* __restrict__ exp_part) {
-  __shared__ float4 s_a[kBlendBlock];
-  __shared__ float4 s_b[kBlendBlock];
-  __shared__ float s_c[kBlendBlock];
-  __shared__ uint32_t s_g[kBlendBlock];
-  __shared__ uint32_t s_e[DET ? kBlendBlock : 1];
-  __shared__ float s_part[DET ? kBlendBlock / 64 : 1][DET ? kBlendBlock : 1][9];
-  __shared__ uint8_t s_m[kBlendBlock];
-  __shared__ float s_red[kBlendBlock / 64][12];
-  __shared__ uint32_t s_wmax[kBlendBlock / 64];
+  constexpr int NT = kBlendBlock / PX;
+  constexpr int NW = NT / 64;
+  constexpr int NG = MAPS ? 10 : 9;  // gradient terms per Gaussian
+  __shared__ float4 s_a[NT];
+  __shared__ float4 s_b[NT];
+  __shared__ float s_c[NT];
+  __shared__ float s_d[MAPS ? NT : 1];
+  __shared__ uint32_t s_g[NT];
+  __shared__ uint32_t s_e[DET ? NT : 1];
+  __shared__ float s_part[DET ? NW : 1][DET ? NT : 1][NG];
+  __shared__ uint8_t s_m[NT];
+  __shared__ float s_red[NW][12];
+  __shared__ uint32_t s_wmax[NW];
   const int tile = blockIdx.x;
   const int v = view_of_tile(va, tile);
   const ViewDev& V = va.v[v];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int px = tx * kTile + 8 * (wid & 1) + (lane & 7);
-  const int py = ty * kTile + 8 * (wid >> 1) + (lane >> 3);
-  const bool inside = px < V.W && py < V.H;
-  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 rg = ranges[tile];
   const float4* vrec = rec + (size_t)v * N * 4;
   float* vg = g2d + (size_t)v * N * kGradFloats;
-
-  const int64_t p = (int64_t)py * V.W + px;
   const int64_t P = (int64_t)V.W * V.H;
-  float T = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  uint32_t nc = 0;
-  if (inside) {
-    T = V.out_T[p];
-    nc = V.out_nc[p];
-    g0 = V.dl_drgb[p];
-    g1 = V.dl_drgb[P + p];
-    g2 = V.dl_drgb[2 * P + p];
+
+  // per pixel: transmittance (recovered backwards), last contributor, dL/d(out), dL/d(pre)
+  float pxc[PX], pyc[PX], T[PX], g0[PX], g1[PX], g2[PX], G0[PX], G1[PX], G2[PX];
+  float B0[PX], B1[PX], B2[PX];  // colour seen behind the current Gaussian, normalised
+  float gD[PX], gO[PX], BD[PX], BO[PX];  // map gradients and the maps seen behind (MAPS)
+  uint32_t nc[PX];
+  bool inside[PX];
+  uint32_t ncmax = 0;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    int lx, ly;
+    lane_pixel<PX>(wid, lane, k, lx, ly);
+    const int px = tx * kTile + lx, py = ty * kTile + ly;
+    pxc[k] = (float)px + 0.5f;
+    pyc[k] = (float)py + 0.5f;
+    inside[k] = px < V.W && py < V.H;
+    T[k] = 1.0f;
+    g0[k] = g1[k] = g2[k] = 0.0f;
+    gD[k] = gO[k] = BD[k] = BO[k] = 0.0f;
+    nc[k] = 0;
+    if (inside[k]) {
+      const int64_t p = (int64_t)py * V.W + px;
+      T[k] = V.out_T[p];
+      nc[k] = V.out_nc[p];
+      g0[k] = V.dl_drgb[p];
+      g1[k] = V.dl_drgb[P + p];
+      g2[k] = V.dl_drgb[2 * P + p];
+      if (MAPS) {
+        if (V.dl_ddepth) gD[k] = V.dl_ddepth[p];
+        if (V.dl_dopac) gO[k] = V.dl_dopac[p];
+      }
+    }
+    // dL/d(pre-exposure colour) = A^T g
+    G0[k] = g0[k];
+    G1[k] = g1[k];
+    G2[k] = g2[k];
+    if (V.exposure) {
+      const float* E = V.exposure;
+      G0[k] = E[0] * g0[k] + E[4] * g1[k] + E[8] * g2[k];
+      G1[k] = E[1] * g0[k] + E[5] * g1[k] + E[9] * g2[k];
+      G2[k] = E[2] * g0[k] + E[6] * g1[k] + E[10] * g2[k];
+    }
+    B0[k] = V.bg[0];
+    B1[k] = V.bg[1];
+    B2[k] = V.bg[2];
+    ncmax = max(ncmax, nc[k]);
   }
-  // dL/d(pre-exposure colour) = A^T g
-  float G0 = g0, G1 = g1, G2 = g2;
-  if (V.exposure) {
-    const float* E = V.exposure;
-    G0 = E[0] * g0 + E[4] * g1 + E[8] * g2;
-    G1 = E[1] * g0 + E[5] * g1 + E[9] * g2;
-    G2 = E[2] * g0 + E[6] * g1 + E[10] * g2;
-  }
-  const uint32_t wmax = wave_max_u32(nc);
+  const uint32_t wmax = wave_max_u32(ncmax);
   if (lane == 0) s_wmax[wid] = wmax;
   __syncthreads();
-  const int nmax = (int)max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
-  // colour seen behind the current Gaussian, normalised by the transmittance in front of it
-  float B0 = V.bg[0], B1 = V.bg[1], B2 = V.bg[2];
+  int nmax = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) nmax = max(nmax, (int)s_wmax[w]);
 
-  for (int end = nmax; end > 0; end -= kBlendBlock) {
-    const int base = max(0, end - kBlendBlock);
+  for (int end = nmax; end > 0; end -= NT) {
+    const int base = max(0, end - NT);
     const int cnt = end - base;
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
@@ -227,70 +321,79 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       s_a[threadIdx.x] = r0;
       s_b[threadIdx.x] = r1;
       s_c[threadIdx.x] = r2.x;
+      if (MAPS) s_d[threadIdx.x] = r2.y;
       s_g[threadIdx.x] = g;
       s_m[threadIdx.x] = (uint8_t)quadrant_mask(r0, r1, r2.w, tx, ty);
       if (DET) {
         s_e[threadIdx.x] = e;
 #pragma unroll
-        for (int w = 0; w < kBlendBlock / 64; ++w)
+        for (int w = 0; w < NW; ++w)
 #pragma unroll
-          for (int f = 0; f < 9; ++f) s_part[w][threadIdx.x][f] = 0.f;
+          for (int f = 0; f < NG; ++f) s_part[w][threadIdx.x][f] = 0.f;
       }
     }
     __syncthreads();
     const int jtop = min(cnt, (int)wmax - base) - 1;  // entries at or past the wave's max are idle
     for (int j = jtop; j >= 0; --j) {
-      if (!((s_m[j] >> wid) & 1u)) continue;
+      const uint32_t m = s_m[j];
       const int pos = base + j;
       const float4 a = s_a[j];
       const float4 b = s_b[j];
-      bool contrib = pos < (int)nc;
-      float dx = 0.f, dy = 0.f, ex = 0.f, araw = 0.f, alpha = 0.f;
-      if (contrib) {
-        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
-        if (power > 0.0f) {
-          contrib = false;
-        } else {
-          ex = __expf(power);
-          araw = b.y * ex;
-          alpha = fminf(kAlphaMax, araw);
-          if (alpha < kAlphaMin) contrib = false;
-        }
-      }
-      if (!__any(contrib)) continue;
-      float gv[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (contrib) {
-        const float c0 = b.z, c1 = b.w, c2 = s_c[j];
+      const float c2 = s_c[j];
+      const float dep = MAPS ? s_d[j] : 0.0f;
+      float gv[NG];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) gv[f] = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        if (!((m >> pixel_quadrant<PX>(wid, k)) & 1u)) continue;
+        if (pos >= (int)nc[k]) continue;
+        float dx, dy;
+        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
+        if (power > 0.0f) continue;
+        const float ex = __expf(power);
+        const float araw = b.y * ex;
+        const float alpha = fminf(kAlphaMax, araw);
+        if (alpha < kAlphaMin) continue;
+        any = true;
         const float oma = 1.0f - alpha;
-        T = T * __builtin_amdgcn_rcpf(oma);  // transmittance in front of this Gaussian
-        const float w = alpha * T;
-        gv[6] = w * G0;
-        gv[7] = w * G1;
-        gv[8] = w * G2;
-        const float dalpha = T * ((c0 - B0) * G0 + (c1 - B1) * G1 + (c2 - B2) * G2);
-        B0 = alpha * c0 + oma * B0;
-        B1 = alpha * c1 + oma * B1;
-        B2 = alpha * c2 + oma * B2;
+        T[k] = T[k] * __builtin_amdgcn_rcpf(oma);  // transmittance in front of this Gaussian
+        const float w = alpha * T[k];
+        gv[6] += w * G0[k];
+        gv[7] += w * G1[k];
+        gv[8] += w * G2[k];
+        float dalpha = T[k] * ((b.z - B0[k]) * G0[k] + (b.w - B1[k]) * G1[k] + (c2 - B2[k]) * G2[k]);
+        B0[k] = alpha * b.z + oma * B0[k];
+        B1[k] = alpha * b.w + oma * B1[k];
+        B2[k] = alpha * c2 + oma * B2[k];
+        if (MAPS) {
+          dalpha += T[k] * ((dep - BD[k]) * gD[k] + (1.0f - BO[k]) * gO[k]);
+          BD[k] = alpha * dep + oma * BD[k];
+          BO[k] = alpha + oma * BO[k];
+          gv[9] += w * gD[k];
+        }
         if (araw <= kAlphaMax) {
           const float dpow = dalpha * alpha;
-          gv[0] = dpow * (a.z * dx + a.w * dy);
-          gv[1] = dpow * (a.w * dx + b.x * dy);
-          gv[2] = -0.5f * dpow * dx * dx;
-          gv[3] = -dpow * dx * dy;
-          gv[4] = -0.5f * dpow * dy * dy;
-          gv[5] = dalpha * ex;
+          gv[0] += dpow * (a.z * dx + a.w * dy);
+          gv[1] += dpow * (a.w * dx + b.x * dy);
+          gv[2] += -0.5f * dpow * dx * dx;
+          gv[3] += -dpow * dx * dy;
+          gv[4] += -0.5f * dpow * dy * dy;
+          gv[5] += dalpha * ex;
         }
       }
+      if (!__any(any)) continue;
 #pragma unroll
-      for (int f = 0; f < 9; ++f) gv[f] = wave_sum_to_63(gv[f]);
+      for (int f = 0; f < NG; ++f) gv[f] = wave_sum_to_63(gv[f]);
       if (lane == 63) {
         if (DET) {
 #pragma unroll
-          for (int f = 0; f < 9; ++f) s_part[wid][j][f] = gv[f];
+          for (int f = 0; f < NG; ++f) s_part[wid][j][f] = gv[f];
         } else {
           float* dst = vg + (size_t)s_g[j] * kGradFloats;
 #pragma unroll
-          for (int f = 0; f < 9; ++f)
+          for (int f = 0; f < NG; ++f)
             if (gv[f] != 0.0f) unsafeAtomicAdd(dst + f, gv[f]);
         }
       }
@@ -298,22 +401,24 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     if (DET) {
       __syncthreads();
       if ((int)threadIdx.x < cnt) {
-        float sum[9];
+        float sum[NG];
 #pragma unroll
-        for (int f = 0; f < 9; ++f)
-          sum[f] = ((s_part[0][threadIdx.x][f] + s_part[1][threadIdx.x][f]) + s_part[2][threadIdx.x][f]) +
-                   s_part[3][threadIdx.x][f];
+        for (int f = 0; f < NG; ++f) {
+          sum[f] = s_part[0][threadIdx.x][f];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) sum[f] += s_part[w][threadIdx.x][f];
+        }
         float4* dst = (float4*)(inst_grad + (size_t)s_e[threadIdx.x] * 12);
         dst[0] = make_float4(sum[0], sum[1], sum[2], sum[3]);
         dst[1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
-        dst[2] = make_float4(sum[8], 0.f, 0.f, 0.f);
+        dst[2] = make_float4(sum[8], MAPS ? sum[NG - 1] : 0.f, 0.f, 0.f);
       }
     }
   }
   if (DET) {
     // entries past every pixel's last contributor carry no gradient
     const int n = (int)(rg.y - rg.x);
-    for (int k = nmax + (int)threadIdx.x; k < n; k += kBlendBlock) {
+    for (int k = nmax + (int)threadIdx.x; k < n; k += NT) {
       float4* dst = (float4*)(inst_grad + (size_t)vals[rg.x + k] * 12);
       const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
       dst[0] = z;
@@ -323,12 +428,16 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   }
   // exposure gradient: dL/dA = sum g pre^T, dL/db = sum g (pre = B after the walk)
   if (V.dl_dexp) {
-    float e[12];
-    e[0] = g0 * B0; e[1] = g0 * B1; e[2] = g0 * B2; e[3] = g0;
-    e[4] = g1 * B0; e[5] = g1 * B1; e[6] = g1 * B2; e[7] = g1;
-    e[8] = g2 * B0; e[9] = g2 * B1; e[10] = g2 * B2; e[11] = g2;
+    float e[12] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int f = 0; f < 12; ++f) e[f] = wave_sum_to_63(inside ? e[f] : 0.0f);
+    for (int k = 0; k < PX; ++k) {
+      if (!inside[k]) continue;
+      e[0] += g0[k] * B0[k]; e[1] += g0[k] * B1[k]; e[2] += g0[k] * B2[k]; e[3] += g0[k];
+      e[4] += g1[k] * B0[k]; e[5] += g1[k] * B1[k]; e[6] += g1[k] * B2[k]; e[7] += g1[k];
+      e[8] += g2[k] * B0[k]; e[9] += g2[k] * B1[k]; e[10] += g2[k] * B2[k]; e[11] += g2[k];
+    }
+#pragma unroll
+    for (int f = 0; f < 12; ++f) e[f] = wave_sum_to_63(e[f]);
     __syncthreads();
     if (lane == 63)
 #pragma unroll
@@ -336,7 +445,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     __syncthreads();
     if (threadIdx.x < 12) {
       float s = 0.f;
-      for (int w = 0; w < kBlendBlock / 64; ++w) s += s_red[w][threadIdx.x];
+      for (int w = 0; w < NW; ++w) s += s_red[w][threadIdx.x];
       if (DET)
         exp_part[(size_t)tile * 12 + threadIdx.x] = s;
       else
@@ -357,24 +466,66 @@ __global__ void k_exposure_reduce(ViewsArg va, const float* __restrict__ exp_par
   V.dl_dexp[f] += s;
 }
 
+template <int PX>
+static void launch_fwd(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                       const uint32_t* emit_g, const uint2* ranges, hipStream_t s) {
+  bool depth = false;
+  for (int v = 0; v < va.n; ++v) depth = depth || va.v[v].out_depth != nullptr;
+  if (depth)
+    hipLaunchKernelGGL((k_blend_fwd<PX, true>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec, N,
+                       vals, emit_g, ranges);
+  else
+    hipLaunchKernelGGL((k_blend_fwd<PX, false>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec, N,
+                       vals, emit_g, ranges);
+}
+
+template <int PX, bool MAPS>
+static void launch_bwd_maps(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                            const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
+                            float* exp_part, hipStream_t s) {
+  if (inst_grad) {
+    hipLaunchKernelGGL((k_blend_bwd<PX, true, MAPS>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec,
+                       N, vals, emit_g, ranges, g2d, inst_grad, exp_part);
+    hipLaunchKernelGGL(k_exposure_reduce, dim3(va.n), dim3(64), 0, s, va, exp_part);
+  } else {
+    hipLaunchKernelGGL((k_blend_bwd<PX, false, MAPS>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec,
+                       N, vals, emit_g, ranges, g2d, inst_grad, exp_part);
+  }
+}
+
+template <int PX>
+static void launch_bwd(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                       const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad, float* exp_part,
+                       hipStream_t s) {
+  bool maps = false;
+  for (int v = 0; v < va.n; ++v) maps = maps || va.v[v].dl_ddepth != nullptr || va.v[v].dl_dopac != nullptr;
+  if (maps)
+    launch_bwd_maps<PX, true>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s);
+  else
+    launch_bwd_maps<PX, false>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s);
+}
+
 hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                         const uint32_t* emit_g, const uint2* ranges, hipStream_t s) {
+                         const uint32_t* emit_g, const uint2* ranges, int px, hipStream_t s) {
   if (va.total_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_blend_fwd, dim3(va.total_tiles), dim3(kBlendBlock), 0, s, va, rec, N, vals, emit_g, ranges);
+  switch (px) {
+    case 1: launch_fwd<1>(va, rec, N, vals, emit_g, ranges, s); break;
+    case 2: launch_fwd<2>(va, rec, N, vals, emit_g, ranges, s); break;
+    case 4: launch_fwd<4>(va, rec, N, vals, emit_g, ranges, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                           const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
-                          float* exp_part, hipStream_t s) {
+                          float* exp_part, int px, hipStream_t s) {
   if (va.total_tiles <= 0) return hipSuccess;
-  if (inst_grad) {
-    hipLaunchKernelGGL(k_blend_bwd<true>, dim3(va.total_tiles), dim3(kBlendBlock), 0, s, va, rec, N, vals, emit_g,
-                       ranges, g2d, inst_grad, exp_part);
-    hipLaunchKernelGGL(k_exposure_reduce, dim3(va.n), dim3(64), 0, s, va, exp_part);
-  } else {
-    hipLaunchKernelGGL(k_blend_bwd<false>, dim3(va.total_tiles), dim3(kBlendBlock), 0, s, va, rec, N, vals, emit_g,
-                       ranges, g2d, inst_grad, exp_part);
+  switch (px) {
+    case 1: launch_bwd<1>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s); break;
+    case 2: launch_bwd<2>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s); break;
+    case 4: launch_bwd<4>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -12,7 +12,9 @@ namespace gs {
 constexpr int kTile = GS_TILE;        // 16x16 pixel tiles
 constexpr int kMaxViews = GS_MAX_VIEWS;
 constexpr int kRecFloats = 16;        // per (view, Gaussian) projection record, 64 B
-constexpr int kGradFloats = 16;       // per (view, Gaussian) 2D-gradient record, 64 B
+// per (view, Gaussian) 2D-gradient record, 64 B: [0..1] mean2d, [2..4] conic, [5] opacity,
+// [6..8] colour, [9] camera-frame depth (depth-map gradient), [10..15] unused
+constexpr int kGradFloats = 16;
 
 // Per-view constants, passed by value inside ViewsArg (so a captured graph keeps them).
 struct ViewDev {
@@ -31,6 +33,10 @@ struct ViewDev {
   uint32_t* out_nc;         // H x W
   const float* dl_drgb;     // 3 x H x W (backward)
   float* dl_dexp;           // 12 (backward, may be nullptr)
+  float* out_depth;         // H x W depth map (Eq. 6) or nullptr
+  float* out_opac;          // H x W opacity map (Eq. 7) or nullptr
+  const float* dl_ddepth;   // H x W (backward, may be nullptr)
+  const float* dl_dopac;    // H x W (backward, may be nullptr)
 };
 
 struct ViewsArg {
@@ -38,12 +44,17 @@ struct ViewsArg {
   int32_t total_tiles;
   ViewDev v[kMaxViews];
 };
+// passed by value to kernels: stays inside the 4 KiB kernel-argument space with room for
+// the other arguments
+static_assert(sizeof(ViewsArg) <= 3584, "ViewsArg too large for a kernel argument");
 
 // Projection record layout (floats), one per (view, Gaussian), view-major:
 //   [0] mean2d x  [1] mean2d y  [2] conic A  [3] conic B
 //   [4] conic C   [5] opacity   [6] red      [7] green
 //   [8] blue      [9] depth     [10] unused  [11] thr = 2 ln(255 o)
-//   [12] tile rect x0 | y0 << 16 (bits)   [13] x1 | y1 << 16 (bits)   [14..15] unused
+//   [12] tile rect x0 | y0 << 16 (bits)   [13] x1 | y1 << 16 (bits)
+//   [14..15] 64-bit mask of the tiles that pass the predicate, in row-major order inside
+//            the rectangle (complete when the rectangle has at most 64 tiles)
 // Only records whose tile count is > 0 are written.
 
 __device__ __forceinline__ int view_of_tile(const ViewsArg& va, int tile) {

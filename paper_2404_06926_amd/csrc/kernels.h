@@ -54,14 +54,15 @@ hipError_t tile_ranges(const uint32_t* tiles, const uint32_t* n_dev, int64_t cap
 
 // blending (blend.hip)
 // vals: emission index of each instance in blend order; emit_g: Gaussian of each emission index.
+// px: pixels per lane (1, 2 or 4), see blend.hip.
 hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                         const uint32_t* emit_g, const uint2* ranges, hipStream_t s);
-// Gradients of (mean2d, conic, opacity, colour) per (view, Gaussian): with inst_grad == nullptr
+                         const uint32_t* emit_g, const uint2* ranges, int px, hipStream_t s);
+// Gradients of (mean2d, conic, opacity, colour, depth) per (view, Gaussian): with inst_grad == nullptr
 // they are added to g2d with wave-reduced atomics; otherwise every instance's gradient is
 // written to inst_grad[emission index] (12 floats, fixed-order reduction, deterministic).
 hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                           const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
-                          float* exp_part, hipStream_t s);
+                          float* exp_part, int px, hipStream_t s);
 
 // loss (loss.hip)
 int64_t loss_temp_floats(int H, int W);
@@ -82,6 +83,15 @@ hipError_t append_rows(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0
 hipError_t init_points(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0, int64_t n, const float* xyz,
                        const float* rgb, const ViewDev& V, float near_z, float logit0, uint8_t* vis,
                        hipStream_t s);
+// map growth (growth.hip): Eq. 8 selection of points by the opacity of their pixel, the
+// selected points' rows, and sky rows from nearest-neighbour distances (d2: n floats).
+hipError_t expand_flags(const float* xyz, int64_t n, const ViewDev& V, const float* T, float tau, float near_z,
+                        uint32_t* flags, hipStream_t s);
+hipError_t init_selected(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0, int64_t n, const float* xyz,
+                         const float* rgb, const uint32_t* flags, const uint32_t* offsets, const ViewDev& V,
+                         float near_z, float logit0, uint8_t* vis, hipStream_t s);
+hipError_t init_sky(float* buf, int64_t cap, int32_t F, int32_t K, int64_t n0, int64_t n, const float* xyz,
+                    float* d2, float logit0, uint8_t* vis, hipStream_t s);
 hipError_t copy_planes(const float* src, int64_t cap0, float* dst, int64_t cap1, int64_t n, int nplanes,
                        hipStream_t s);
 

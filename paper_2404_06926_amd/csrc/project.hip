@@ -32,10 +32,15 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     const KeyProj kp = key_project(V, G, m0, m1, m2, logit, near_z);
     int r[4];
     uint32_t cnt = 0;
+    uint64_t hits = 0;  // passing tiles in row-major rectangle order (rectangles of <= 64 tiles)
     if (kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) {
+      int k = 0;
       for (int ty = r[1]; ty <= r[3]; ++ty)
-        for (int tx = r[0]; tx <= r[2]; ++tx)
-          cnt += key_tile_hit(kp.mx, kp.my, kp.A, kp.B, kp.C, kp.thr, tx, ty) ? 1u : 0u;
+        for (int tx = r[0]; tx <= r[2]; ++tx, ++k)
+          if (key_tile_hit(kp.mx, kp.my, kp.A, kp.B, kp.C, kp.thr, tx, ty)) {
+            ++cnt;
+            if (k < 64) hits |= 1ull << k;
+          }
     }
     counts[vi] = cnt;
     // depth-sort key of the pair: float bits of a positive depth, largest key when unused
@@ -63,7 +68,8 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     o[1] = make_float4(kp.C, kp.o, col[0], col[1]);
     o[2] = make_float4(col[2], kp.zh, 0.0f, kp.thr);
     o[3] = make_float4(__uint_as_float((uint32_t)r[0] | ((uint32_t)r[1] << 16)),
-                       __uint_as_float((uint32_t)r[2] | ((uint32_t)r[3] << 16)), 0.0f, 0.0f);
+                       __uint_as_float((uint32_t)r[2] | ((uint32_t)r[3] << 16)), __uint_as_float((uint32_t)hits),
+                       __uint_as_float((uint32_t)(hits >> 32)));
   }
 }
 
@@ -98,6 +104,7 @@ __device__ __forceinline__ void pair_grad(size_t vi, const uint32_t* __restrict_
       ga.x += a.x; ga.y += a.y; ga.z += a.z; ga.w += a.w;
       gb.x += b.x; gb.y += b.y; gb.z += b.z; gb.w += b.w;
       gc.x += c.x;
+      gc.y += c.y;
     }
   } else {
     ga = g2d[vi * 4 + 0];
@@ -286,7 +293,7 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     const float gJ11 = gT1[0] * W[3] + gT1[1] * W[4] + gT1[2] * W[5];
     const float gJ12 = gT1[0] * W[6] + gT1[1] * W[7] + gT1[2] * W[8];
     // camera-frame mean: through J and the 2D mean
-    float gx = 0.f, gy = 0.f, gz = 0.f;
+    float gx = 0.f, gy = 0.f, gz = gc.y;  // gc.y: gradient of the camera-frame depth (Eq. 6)
     gz += -V.fx * iz2 * gJ00 - V.fy * iz2 * gJ11;
     if (!clx) {
       gx += -V.fx * iz2 * gJ02;

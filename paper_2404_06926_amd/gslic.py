@@ -52,7 +52,8 @@ class GsMapDesc(ctypes.Structure):
                 ("lr_log_scale", ctypes.c_float), ("lr_quat", ctypes.c_float),
                 ("lr_opacity", ctypes.c_float), ("lr_sh_dc", ctypes.c_float),
                 ("lr_sh_rest", ctypes.c_float), ("lr_exposure", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("expand_tau", ctypes.c_float)]
 
 
 class GsView(ctypes.Structure):
@@ -63,7 +64,8 @@ class GsView(ctypes.Structure):
 
 
 class GsFrame(ctypes.Structure):
-    _fields_ = [("rgb", ctypes.c_void_p), ("final_T", ctypes.c_void_p), ("n_contrib", ctypes.c_void_p)]
+    _fields_ = [("rgb", ctypes.c_void_p), ("final_T", ctypes.c_void_p), ("n_contrib", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("opacity", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -74,8 +76,14 @@ _SIGS = {
     "gs_destroy_map": (_I32, [_P]),
     "gs_add_gaussians": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     "gs_add_points": (_I32, [_P, _I64, _P, _P, ctypes.POINTER(GsView), _F, _P]),
+    "gs_expand": (_I32, [_P, ctypes.POINTER(GsView), _I64, _P, _P, _F, _F, ctypes.POINTER(_I64), _P]),
+    "gs_add_sky": (_I32, [_P, _I64, _P, _F, _P]),
+    "gs_add_keyframe": (_I32, [_P, ctypes.POINTER(GsView), _P, _I64, _P, _P, _F, ctypes.POINTER(_I32), _P]),
+    "gs_optimize_keyframes": (_I32, [_P, _I32, ctypes.POINTER(_I32), _F, _P, _P]),
+    "gs_keyframe_count": (_I32, [_P, ctypes.POINTER(_I32)]),
     "gs_render": (_I32, [_P, _I32, ctypes.POINTER(GsView), ctypes.POINTER(GsFrame), _P]),
-    "gs_render_backward": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
+    "gs_render_backward": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                  ctypes.POINTER(_P), _P]),
     "gs_adam_step": (_I32, [_P, _I32, ctypes.POINTER(_P), _P]),
     "gs_loss": (_I32, [_P, _P, _P, _I32, _I32, _F, _P, _P, _P]),
     "gs_submit_keyframe": (_I32, [_P, ctypes.POINTER(GsView), _P, _I64, _P, _P, _I32, _I32, _F, _F, _P, _P]),
@@ -186,6 +194,14 @@ class Frame:
     rgb: "object"
     final_T: "object"
     n_contrib: "object"
+    depth: "object" = None      # depth map (Eq. 6), when asked for
+    opacity: "object" = None    # opacity map (Eq. 7), when asked for
+
+
+def _frame_struct(f) -> "GsFrame":
+    return GsFrame(f.rgb.data_ptr(), f.final_T.data_ptr(), f.n_contrib.data_ptr(),
+                   f.depth.data_ptr() if f.depth is not None else None,
+                   f.opacity.data_ptr() if f.opacity is not None else None)
 
 
 def make_view(cam, exposure=None) -> GsView:
@@ -304,8 +320,52 @@ class GaussianMap:
                                    float(o_init), _stream(stream)))
         self._keep = [xyz, rgb]
 
+    def expand(self, cam, xyz, rgb, tau=0.99, o_init=0.1, stream=None) -> int:
+        """Eq. 8 expansion at a keyframe view; returns the number of Gaussians appended."""
+        torch = _torch()
+        xyz = torch.as_tensor(xyz, dtype=torch.float32, device=self.device).contiguous()
+        rgb = torch.as_tensor(rgb, dtype=torch.float32, device=self.device).contiguous()
+        v = make_view(cam)
+        k = _I64()
+        _check(lib().gs_expand(self.handle, ctypes.byref(v), xyz.shape[0], _ptr(xyz), _ptr(rgb), float(tau),
+                               float(o_init), ctypes.byref(k), _stream(stream)))
+        self._keep = [xyz, rgb]
+        return int(k.value)
+
+    def add_sky(self, xyz, o_sky=0.7, stream=None):
+        """Sky Gaussians at the given positions (scale = nearest-neighbour distance)."""
+        torch = _torch()
+        xyz = torch.as_tensor(xyz, dtype=torch.float32, device=self.device).contiguous()
+        _check(lib().gs_add_sky(self.handle, xyz.shape[0], _ptr(xyz), float(o_sky), _stream(stream)))
+        self._keep = [xyz]
+
+    def add_keyframe(self, cam, image, xyz=None, rgb=None, o_init=0.1, stream=None) -> int:
+        """Keep a keyframe for the random-K schedule (after expanding the map with its
+        points); returns its id."""
+        n = 0 if xyz is None else int(xyz.shape[0])
+        v = make_view(cam)
+        kid = _I32()
+        _check(lib().gs_add_keyframe(self.handle, ctypes.byref(v), _ptr(image), n, _ptr(xyz), _ptr(rgb),
+                                     float(o_init), ctypes.byref(kid), _stream(stream)))
+        self._keep = [image, xyz, rgb]
+        return int(kid.value)
+
+    def optimize_keyframes(self, ids, lam=0.2, done_event=None, stream=None):
+        """One single-view mapping step per id, in the given order."""
+        arr = (_I32 * max(len(ids), 1))(*[int(i) for i in ids])
+        ev = ctypes.c_void_p(done_event.cuda_event) if done_event is not None else None
+        _check(lib().gs_optimize_keyframes(self.handle, len(ids), arr, float(lam), ev, _stream(stream)))
+
+    def keyframe_count(self) -> int:
+        c = _I32()
+        _check(lib().gs_keyframe_count(self.handle, ctypes.byref(c)))
+        return int(c.value)
+
     # ------------------------------------------------------------- the step
-    def render(self, cams: Sequence, exposures: Optional[Sequence] = None, frames=None, stream=None) -> List[Frame]:
+    def render(self, cams: Sequence, exposures: Optional[Sequence] = None, frames=None, stream=None,
+               depth: bool = False, opacity: bool = False) -> List[Frame]:
+        """Batched forward over the views; depth / opacity also return the depth and opacity
+        maps (Eq. 6-7) in frames allocated here."""
         torch = _torch()
         nv = len(cams)
         views = (GsView * nv)()
@@ -319,8 +379,10 @@ class GaussianMap:
             else:
                 f = Frame(torch.empty(3, c.height, c.width, device=self.device),
                           torch.empty(c.height, c.width, device=self.device),
-                          torch.empty(c.height, c.width, dtype=torch.int32, device=self.device))
-            fr[k] = GsFrame(f.rgb.data_ptr(), f.final_T.data_ptr(), f.n_contrib.data_ptr())
+                          torch.empty(c.height, c.width, dtype=torch.int32, device=self.device),
+                          torch.empty(c.height, c.width, device=self.device) if depth else None,
+                          torch.empty(c.height, c.width, device=self.device) if opacity else None)
+            fr[k] = _frame_struct(f)
             out.append(f)
         _check(lib().gs_render(self.handle, nv, views, fr, _stream(stream)))
         # the kernels of this render and of render_backward read these buffers
@@ -329,13 +391,18 @@ class GaussianMap:
         self._last_nv = nv
         return out
 
-    def render_backward(self, dl_drgb: Sequence, dl_dexposure: Optional[Sequence] = None, stream=None):
+    def render_backward(self, dl_drgb: Sequence, dl_dexposure: Optional[Sequence] = None, stream=None,
+                        dl_ddepth: Optional[Sequence] = None, dl_dopacity: Optional[Sequence] = None):
         nv = len(dl_drgb)
         dl = (_P * nv)(*[t.data_ptr() for t in dl_drgb])
-        de = None
-        if dl_dexposure is not None:
-            de = (_P * nv)(*[(t.data_ptr() if t is not None else None) for t in dl_dexposure])
-        _check(lib().gs_render_backward(self.handle, nv, dl, de, _stream(stream)))
+
+        def arr(ts):
+            if ts is None:
+                return None
+            return (_P * nv)(*[(t.data_ptr() if t is not None else None) for t in ts])
+
+        _check(lib().gs_render_backward(self.handle, nv, dl, arr(dl_ddepth), arr(dl_dopacity), arr(dl_dexposure),
+                                        _stream(stream)))
 
     def adam_step(self, exposure_states: Sequence = (), stream=None):
         ne = len(exposure_states)
@@ -363,7 +430,7 @@ class GaussianMap:
     def _step_args(self, cams, frames, targets, exposure_states, grads, loss_out):
         nv = len(cams)
         views = (GsView * nv)(*[make_view(c) for c in cams])
-        fr = (GsFrame * nv)(*[GsFrame(f.rgb.data_ptr(), f.final_T.data_ptr(), f.n_contrib.data_ptr())
+        fr = (GsFrame * nv)(*[_frame_struct(f)
                               for f in frames])
         tg = (_P * nv)(*[t.data_ptr() for t in targets])
         es = (_P * nv)(*[e.data_ptr() for e in exposure_states])
@@ -401,6 +468,10 @@ class GaussianMap:
 
     def set_deterministic(self, enable: bool):
         _check(lib().gs_set_deterministic(self.handle, 1 if enable else 0))
+
+    def set_blend_config(self, fwd_px_per_lane: int, bwd_px_per_lane: int):
+        """Pixels per lane (1, 2 or 4) of the forward and backward blend kernels."""
+        _check(lib().gs_set_blend_config(self.handle, int(fwd_px_per_lane), int(bwd_px_per_lane)))
 
     def set_stage_timing(self, enable: bool):
         _check(lib().gs_set_stage_timing(self.handle, 1 if enable else 0))

@@ -225,3 +225,127 @@ def smooth_image(seed: int, H: int, W: int, name: str = "image") -> np.ndarray:
             img[c] += a * np.sin(2 * np.pi * (fx_ * xx + fy_ * yy) + ph)
     img += 0.5 + r.normal(0, 0.02, img.shape)
     return np.clip(img, 0, 1).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------------------
+# Streaming street scene: a straight ego path along +x (world z-up), LiDAR-like points
+# arriving with the keyframes.
+
+STREET_MIX = (273, 182, 25)   # ground : facade : far-point proportions of outdoor_scene
+
+
+def street_layout(seed: int, length: float = 500.0) -> np.ndarray:
+    """Facade segments along both sides of the path: rows (x_start, x_end, y, height),
+    segments 10-25 m long with 3-8 m gaps, heights 6-15 m, at y = +-12 m."""
+    r = rng(seed, "street_layout")
+    segs = []
+    for y in (12.0, -12.0):
+        x = r.uniform(0, 5)
+        while x < length:
+            seg_len = r.uniform(10, 25)
+            segs.append((x, min(x + seg_len, length), y, r.uniform(6, 15)))
+            x += seg_len + r.uniform(3, 8)
+    return np.array(segs)
+
+
+def street_points(seed: int, layout: np.ndarray, x0: float, x1: float, n: int, key: str):
+    """n points of the slab x in [x0, x1] in the outdoor_scene proportions: ground
+    (|y| <= 15 m), facade segments of `layout`, sparse far points 30-80 m ahead of x0;
+    +-2 cm noise. Colours: grey ground, one colour per facade segment, random far points,
+    all with N(0, 0.03) noise. Returns (xyz (n, 3), rgb (n, 3)) float32."""
+    r = rng(seed, "street_points/" + key)
+    tot = sum(STREET_MIX)
+    n_g = int(round(n * STREET_MIX[0] / tot))
+    n_f = int(round(n * STREET_MIX[1] / tot))
+    n_t = n - n_g - n_f
+    ground = np.stack([r.uniform(x0, x1, n_g), r.uniform(-15, 15, n_g), np.zeros(n_g)], 1)
+    g_rgb = np.full((n_g, 3), 0.4)
+    ov0 = np.maximum(layout[:, 0], x0)
+    ov1 = np.minimum(layout[:, 1], x1)
+    w = np.maximum(ov1 - ov0, 0.0) * layout[:, 3]
+    if n_f and w.sum() > 0:
+        seg = r.choice(len(layout), n_f, p=w / w.sum())
+        fac = np.stack([r.uniform(ov0[seg], ov1[seg]), layout[seg, 2], r.uniform(0, layout[seg, 3])], 1)
+        seg_col = rng(seed, "street_facade_colours").uniform(0.2, 0.9, (len(layout), 3))
+        f_rgb = seg_col[seg]
+    else:  # no facade in the slab: those points go to the ground
+        fac = np.stack([r.uniform(x0, x1, n_f), r.uniform(-15, 15, n_f), np.zeros(n_f)], 1)
+        f_rgb = np.full((n_f, 3), 0.4)
+    rr = r.uniform(30, 80, n_t)
+    az = r.uniform(-np.pi / 2, np.pi / 2, n_t)
+    far = np.stack([x0 + rr * np.cos(az), rr * np.sin(az), r.uniform(0, 25, n_t)], 1)
+    t_rgb = r.uniform(0.1, 0.9, (n_t, 3))
+    xyz = np.concatenate([ground, fac, far]) + r.normal(0, 0.02, (n, 3))
+    rgb = np.clip(np.concatenate([g_rgb, f_rgb, t_rgb]) + r.normal(0, 0.03, (n, 3)), 0, 1)
+    return xyz.astype(np.float32), rgb.astype(np.float32)
+
+
+def street_gaussians(seed: int, xyz: np.ndarray, rgb: np.ndarray, deg: int, ref=None) -> np.ndarray:
+    """Gaussians on points: log-scales ln(d / 1000) + N(0, 0.3) with d the distance to the
+    point `ref` (or, with ref None, to the ego path: the line y = 0, z = 1.8 m), random unit
+    quaternions, logits N(0, 1), SH DC from the colour plus N(0, 0.05), higher SH N(0, 0.05)."""
+    n = xyz.shape[0]
+    if ref is None:
+        d = np.hypot(xyz[:, 1], xyz[:, 2] - 1.8)
+    else:
+        d = np.linalg.norm(xyz - np.asarray(ref, np.float64)[None, :], axis=1)
+    ls = np.log(np.maximum(d, 0.5) / 1000.0)[:, None] + rng(seed, "street_log_scales").normal(0, 0.3, (n, 3))
+    quats = random_quats(rng(seed, "street_quats"), n)
+    logits = rng(seed, "street_logits").normal(0.0, 1.0, n)
+    K = n_sh(deg)
+    sh = np.zeros((n, K, 3))
+    sh[:, 0, :] = (rgb - 0.5) / 0.28209479177387814 + rng(seed, "street_dc").normal(0, 0.05, (n, 3))
+    if K > 1:
+        sh[:, 1:, :] = rng(seed, "street_sh_rest").normal(0.0, 0.05, (n, K - 1, 3))
+    return _assemble(xyz, ls, quats, logits, sh)
+
+
+def stream_schedule(seed: int, duration_s: float, rate_hz: float = 10.0, length: float = 500.0):
+    """Keyframe arrival times (Poisson, rate_hz) and the ego position at each: speed
+    re-drawn from U[5, 15] m/s every 5 s, camera yaw = heading + N(0, 5 deg).
+    Returns (arrivals, x, yaw) arrays."""
+    r = rng(seed, "stream_schedule")
+    arrivals = []
+    t = 0.0
+    while True:
+        t += r.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        arrivals.append(t)
+    arrivals = np.array(arrivals)
+    n_seg = int(np.ceil(max(duration_s, 1e-9) / 5.0)) + 1
+    speeds = r.uniform(5, 15, n_seg)
+    seg_start = np.concatenate([[0.0], np.cumsum(speeds * 5.0)])
+
+    def pos(tt):
+        k = min(int(tt // 5.0), n_seg - 1)
+        return seg_start[k] + speeds[k] * (tt - 5.0 * k)
+
+    x = np.array([min(pos(a), length - 60.0) for a in arrivals])
+    yaw = r.normal(0, np.deg2rad(5.0), len(arrivals))
+    return arrivals, x, yaw
+
+
+def street_camera(x: float, yaw: float, width: int = 1280, height: int = 720, f: float = 1000.0) -> Camera:
+    """Camera 1.8 m above the path at x looking along heading +x rotated by yaw."""
+    return look_camera(width, height, f, (x, 0.0, 1.8), (np.cos(yaw), np.sin(yaw), 0.0))
+
+
+def sky_gaussians(seed: int, n: int, centre, radius: float, deg: int) -> np.ndarray:
+    """Sky shell: n Gaussians area-uniform on the upper hemisphere of `radius` around
+    `centre`, log-scales ln(mean point spacing) + N(0, 0.3), light-blue DC colour."""
+    r = rng(seed, "sky_points")
+    cz = r.uniform(0, 1, n)
+    ph = r.uniform(0, 2 * np.pi, n)
+    sr = np.sqrt(1 - cz ** 2)
+    c = np.asarray(centre, np.float64)
+    xyz = np.stack([c[0] + radius * sr * np.cos(ph), c[1] + radius * sr * np.sin(ph), c[2] + radius * cz], 1)
+    spacing = np.sqrt(2 * np.pi * radius ** 2 / max(n, 1))
+    ls = np.log(spacing) + rng(seed, "sky_log_scales").normal(0, 0.3, (n, 3))
+    quats = random_quats(rng(seed, "sky_quats"), n)
+    logits = rng(seed, "sky_logits").normal(0.0, 1.0, n)
+    K = n_sh(deg)
+    sh = np.zeros((n, K, 3))
+    sh[:, 0, :] = (np.array([0.6, 0.75, 0.9]) - 0.5) / 0.28209479177387814
+    sh[:, 0, :] += rng(seed, "sky_dc").normal(0, 0.05, (n, 3))
+    return _assemble(xyz, ls, quats, logits, sh)

@@ -115,36 +115,43 @@ class FakeBackend:
 
 
 class GpuBackend:
-    """Sessions on the HIP library: one GaussianMap and one stream per session."""
+    """Sessions on the HIP library: one GaussianMap, one stream and one host worker thread
+    per session. A job's library calls run on the session's worker (the library releases
+    the GIL and a host wait inside one session's job, such as the instance-count read of a
+    render, does not hold up the other sessions); its latency is measured with events on
+    the session's stream."""
 
     def __init__(self, device="cuda", iters=10, window=8, lam=0.2, o_init=0.1, deterministic=False,
-                 keep_final=False):
+                 keep_final=False, threaded=True, capacity=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.iters, self.window, self.lam, self.o_init = iters, window, lam, o_init
         self.deterministic = deterministic
         self.keep_final = keep_final
-        self.final = {}          # sid -> parameter planes at release (when keep_final)
+        self.threaded = threaded
+        self.capacity = capacity   # initial row capacity of every map (None: the initial rows)
+        self.final = {}            # sid -> parameter planes at release (when keep_final)
 
     def create(self, spec):
+        from concurrent.futures import ThreadPoolExecutor
         from . import gslic
         torch = self.torch
         stream = torch.cuda.Stream(device=self.device)
-        with torch.cuda.stream(stream):
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
             init = spec.init
             n0 = 0 if init is None else init.shape[0]
-            m = gslic.GaussianMap(sh_degree=spec.sh_degree, capacity=max(1024, n0), device=self.device)
+            m = gslic.GaussianMap(sh_degree=spec.sh_degree, capacity=max(1024, n0, self.capacity or 0),
+                                  device=self.device)
             m.set_deterministic(self.deterministic)
             if n0:
-                m.add_gaussians(torch.from_numpy(np.ascontiguousarray(init)).to(self.device))
-        return dict(map=m, stream=stream, keep=None, sid=spec.sid), spec.est_bytes
+                m.add_gaussians(torch.as_tensor(np.ascontiguousarray(init)).to(self.device))
+        ex = ThreadPoolExecutor(max_workers=1) if self.threaded else None
+        return dict(map=m, stream=stream, keep=None, sid=spec.sid, ex=ex), spec.est_bytes
 
-    def submit(self, h, job, now):
+    def _run(self, h, job, start, done):
         torch = self.torch
-        with torch.cuda.stream(h["stream"]):
-            start = torch.cuda.Event(enable_timing=True)
-            done = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.device(self.device), torch.cuda.stream(h["stream"]):
             start.record()
             img = torch.as_tensor(job.image).to(self.device, non_blocking=True)
             xyz = rgb = None
@@ -155,9 +162,24 @@ class GpuBackend:
                                      lam=self.lam, o_init=self.o_init)
             done.record()
             h["keep"] = (img, xyz, rgb)
-        return dict(start=start, done=done, t_submit=now)
+
+    def submit(self, h, job, now):
+        torch = self.torch
+        start = torch.cuda.Event(enable_timing=True)
+        done = torch.cuda.Event(enable_timing=True)
+        tok = dict(start=start, done=done, t_submit=now, fut=None)
+        if h["ex"] is not None:
+            tok["fut"] = h["ex"].submit(self._run, h, job, start, done)
+        else:
+            self._run(h, job, start, done)
+        return tok
 
     def poll(self, tok, now):
+        f = tok["fut"]
+        if f is not None:
+            if not f.done():
+                return None
+            f.result()   # raises what the job raised
         if not tok["done"].query():
             return None
         return tok["t_submit"] + tok["start"].elapsed_time(tok["done"]) * 1e-3
@@ -166,6 +188,8 @@ class GpuBackend:
         return h["map"].info()[2]
 
     def close(self, h):
+        if h["ex"] is not None:
+            h["ex"].shutdown(wait=True)
         h["stream"].synchronize()
         if self.keep_final:
             self.final[h["sid"]] = h["map"].params().clone()

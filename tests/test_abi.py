@@ -53,7 +53,7 @@ def test_defaults_and_validation_without_gpu(L):
     d.near_z = 0.0
     assert L.gs_create_map(ctypes.byref(d), None, ctypes.byref(h)) == gslic.GS_ERR_INVALID
     assert L.gs_render(None, 1, None, None, None) == gslic.GS_ERR_INVALID
-    assert L.gs_render_backward(None, 1, None, None, None) == gslic.GS_ERR_INVALID
+    assert L.gs_render_backward(None, 1, None, None, None, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_adam_step(None, 0, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_loss(None, None, None, 4, 4, 0.2, None, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_destroy_map(None) == gslic.GS_OK

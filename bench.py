@@ -108,7 +108,16 @@ def cpu_baseline(params, target_params, deg, cam, lam):
     F = params.shape[1]
     oracle.adam(params, gp, np.zeros_like(gp), np.zeros_like(gp), vis, np.full(F, 1e-3), 0.9, 0.999, 1e-15, 1)
     dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="iters/s", cores=threads, kind="oracle",
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=1.0 / dt, unit="iters/s", cores=threads, kind="oracle", cpu_model=model,
+                nproc=os.cpu_count(),
                 sample=f"one full step of the same workload (FP64 oracle, {dt:.1f} s; target render "
                        f"{t_target:.1f} s not counted)")
 
@@ -268,8 +277,9 @@ def run_serving(args, torch, gslic):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=1, help="timed regions of --steps steps; the median is reported")
     ap.add_argument("--workload", choices=["headline", "batch8", "stream", "multi"], default="headline")
     ap.add_argument("--duration", type=float, default=None,
                     help="serving workloads: seconds of keyframe arrivals (stream 5, multi 2)")
@@ -353,8 +363,9 @@ def main():
         graph = m.capture_step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
         for _ in range(args.warmup):
             graph.launch()
-        log(f"graph timed region ({args.steps} steps)")
-        ms_graph = timed(torch, graph.launch, args.steps)
+        log(f"graph timed regions ({args.repeats} x {args.steps} steps)")
+        runs = [timed(torch, graph.launch, args.steps) for _ in range(max(args.repeats, 1))]
+        ms_graph = float(np.median(runs))
     if m.check_overflow():
         raise RuntimeError("instance buffer overflow during the timed steps")
     ms = ms_graph if ms_graph is not None else ms_eager
@@ -370,33 +381,51 @@ def main():
     tile_passes = (int(np.ceil(np.log2(T_total + 1))) + 7) // 8
     V = len(cams)
 
-    per = {k: (v[0] / max(v[1], 1)) for k, v in stages.items()}
-    # algorithmic work per launch of each stage (bytes or FLOPs); per-unit figures in the design doc
+    per = {k: (v[0] / max(v[1], 1)) for k, v in stages.items() if v[1] > 0}
+    # algorithmic work per launch of each stage: bytes the method must move (all stages)
+    # and FLOPs (blend kernels, bound by the vector ALU); per-unit figures in the design doc
+    atomics = 36.0 * n_inst * (4 // bpx)   # one 9-float atomic add per wave and instance
     work = {
-        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + (64.0 + 12.0) * n_vis + 12.0 * V * args.n),
-        "depth_sort": ("hbm", 4 * 24.0 * V * args.n),
-        "scan": ("hbm", 12.0 * V * args.n),
-        "duplicate": ("hbm", 72.0 * n_vis + 8.0 * n_inst),
-        "sort": ("hbm", tile_passes * 20.0 * n_inst),
-        "ranges": ("hbm", 4.0 * n_inst + 8.0 * T_total),
-        "blend": ("alu", FWD_FLOPS_PER_PAIR * float(pairs)),
-        "loss": ("hbm", 132.0 * P),
-        "blend_backward": ("alu", BWD_FLOPS_PER_PAIR * float(pairs)),
-        "project_backward": ("hbm", 4.0 * F * n_vis * 3 + 96.0 * n_vis + 4.0 * V * args.n),
-        "adam": ("hbm", 32.0 * F * n_vis),
+        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + (64.0 + 12.0) * n_vis + 12.0 * V * args.n, 0),
+        "depth_sort": ("hbm", 4 * 24.0 * V * args.n, 0),
+        "scan": ("hbm", 12.0 * V * args.n, 0),
+        "duplicate": ("hbm", 24.0 * n_vis + 12.0 * n_inst, 0),
+        "sort": ("hbm", tile_passes * 20.0 * n_inst, 0),
+        "ranges": ("hbm", 4.0 * n_inst + 8.0 * T_total, 0),
+        "blend": ("alu", 40.0 * n_inst + 20.0 * P, FWD_FLOPS_PER_PAIR * float(pairs)),
+        "loss": ("hbm", 132.0 * P, 0),
+        "blend_backward": ("alu", 40.0 * n_inst + 32.0 * P + atomics, BWD_FLOPS_PER_PAIR * float(pairs)),
+        "project_backward": ("hbm", 4.0 * F * n_vis * 3 + 96.0 * n_vis + 4.0 * V * args.n, 0),
+        "adam": ("hbm", 32.0 * F * n_vis, 0),
     }
+    names = {"blend_backward": f"k_blend_bwd<{bpx},false,false>", "blend": f"k_blend_fwd<{fpx},false>",
+             "project_backward": f"k_project_bwd<{args.sh},true,{'true' if len(cams) > 1 else 'false'}>",
+             "project": f"k_project_fwd<{args.sh}>"}
+    tag = f"{args.workload}_{args.n // 1000}k_sh{args.sh}_{args.width}x{args.height}"
+    kernel_table = {}
+    for k, ms_k in per.items():
+        if k not in work:
+            continue
+        bound_k, bytes_k, flops_k = work[k]
+        d = ms_k * 1e-3
+        row = {"ms": round(ms_k, 4), "bound": bound_k, "alg_bytes": bytes_k,
+               "hbm_frac": round(bytes_k / d / (HBM_PEAK_GBS * 1e9), 4)}
+        if flops_k:
+            row["flops"] = flops_k
+            row["valu_frac"] = round(flops_k / d / (FP32_PEAK_TFLOPS * 1e12), 4)
+        t_k = recorded_traffic(names[k], tag) if k in names else None
+        if t_k is not None:
+            row["traffic_bytes"] = t_k
+            row["traffic_frac"] = round(t_k / d / (HBM_PEAK_GBS * 1e9), 4)
+        kernel_table[k] = row
     dom = max(per, key=lambda k: per[k])
-    bound, amount = work[dom]
+    bound, nbytes, nflops = work[dom]
     dur_s = per[dom] * 1e-3
     if bound == "hbm":
-        achieved, peak, unit = amount / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        achieved, peak, unit = nbytes / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
-        achieved, peak, unit = amount / dur_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
-    kernels = {"blend_backward": f"k_blend_bwd<{bpx},false,false>", "blend": f"k_blend_fwd<{fpx},false>",
-               "project_backward": f"k_project_bwd<{args.sh},true,{'true' if len(cams) > 1 else 'false'}>",
-               "project": f"k_project_fwd<{args.sh}>", "duplicate": "k_duplicate"}
-    tag = f"{args.workload}_{args.n // 1000}k_sh{args.sh}_{args.width}x{args.height}"
-    traffic = recorded_traffic(kernels[dom], tag) if dom in kernels else None
+        achieved, peak, unit = nflops / dur_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
+    traffic = recorded_traffic(names[dom], tag) if dom in names else None
     roof = dict(bound=bound, kernel=dom, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
                 traffic=traffic, avg_launch_ms=per[dom])
     if traffic is not None:
@@ -410,6 +439,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "repeats": args.repeats,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
@@ -425,6 +455,7 @@ def main():
         "roofline": roof,
         "eager_ms_per_step": ms_eager,
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
+        "kernels": kernel_table,
         "counts": {"visible_pairs": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total},
     }
 

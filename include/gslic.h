@@ -236,7 +236,9 @@ gs_status gs_set_fused_step(gs_map* map, int32_t enable);
  * gs_step with the same views has sized the workspace (capture never allocates; it fails
  * with GS_ERR_STATE otherwise). Every pointer passed is baked into the graph and must stay
  * valid while it is used; the map must not grow. Each gs_launch_step performs one more
- * step (the Adam step count lives on the device). */
+ * step (the Adam step count lives on the device). A step captured while the gradient
+ * planes were known to be zero skips reading them; gs_launch_step then returns
+ * GS_ERR_STATE if they may hold values again (gs_render_backward or gs_map_params since). */
 typedef struct gs_step_graph gs_step_graph;
 gs_status gs_capture_step(gs_map* map, int32_t n_views, const gs_view* views, const gs_frame* frames,
                           const float* const* targets, float lambda, float* const* exposure_states,
@@ -252,7 +254,9 @@ const char* gs_last_error(void);
 gs_status gs_map_info(const gs_map* map, int64_t* n, int64_t* capacity, int64_t* resident_bytes);
 
 /* Device pointers to plane 0 of the parameter, gradient and Adam m / v buffers, and the
- * plane stride (= capacity). Valid until the map grows or is destroyed. Any may be NULL. */
+ * plane stride (= capacity). Valid until the map grows or is destroyed. Any may be NULL.
+ * Asking for the gradient pointer tells the map its gradient planes may be written: the
+ * next fused step reads them (otherwise it skips that read while they are known zero). */
 gs_status gs_map_params(gs_map* map, float** params, float** grads, float** adam_m, float** adam_v,
                         int64_t* plane_stride);
 

@@ -83,11 +83,15 @@ struct gs_map {
   DevBuf rec, counts, offsets, scan_tmp, g2d, keys[2], vals[2], sort_tmp, ranges, pixT, pixN, loss_tmp;
   DevBuf dkey[2], dval[2];     // depth-sort keys / (view, Gaussian) ids, double-buffered
   DevBuf emit_g, inst_off;     // Gaussian of each emission index; first emission index per pair
+  DevBuf block_start, big_list;  // instance-parallel binning: first pair per block; large-rectangle pairs
   DevBuf inst_grad, exp_part;  // deterministic backward: per-instance gradients, per-tile exposure sums
   DevBuf dbg_g;                // Gaussian index per instance in blend order (inspection only)
   DevBuf gr_rgb, gr_T, gr_flags, gr_off, gr_tmp, gr_d2;  // map growth: render, selection, scan, sky
   bool deterministic = false;
   bool fused_step = true;      // gs_step applies Adam inside the projection backward
+  bool grads_dirty = false;    // gradient planes may hold non-zero values (a backward without Adam,
+                               // or their pointer was handed out)
+  bool step_assumed_clean = false;  // the last fused gs_step skipped reading the gradient planes
   int fwd_px = 1, bwd_px = 4;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
   uint32_t* d_nvn = nullptr;   // number of (view, Gaussian) pairs of the last render
   int64_t vn_cap = 0, inst_cap = 0, tiles_cap = 0, pix_cap = 0;
@@ -113,6 +117,7 @@ struct gs_map {
 
 struct gs_step_graph {
   gs_map* map = nullptr;
+  bool assumes_clean = false;  // captured with the gradient-plane read skipped
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -200,6 +205,7 @@ gs_status ensure_instances(gs_map* m, int64_t nc, int64_t vn, hipStream_t s) {
     GS_TRY(ensure(m, m->vals[b], (size_t)nc * 4, s));
   }
   GS_TRY(ensure(m, m->emit_g, (size_t)nc * 4, s));
+  GS_TRY(ensure(m, m->block_start, (size_t)block_start_elems(nc) * 4, s));
   if (m->deterministic) GS_TRY(ensure(m, m->inst_grad, (size_t)nc * 12 * 4, s));
   GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(std::max<int64_t>(nc, vn)) * 4, s));
   if (nc > m->inst_cap) m->inst_cap = nc;
@@ -389,6 +395,7 @@ gs_status gs_destroy_map(gs_map* m) {
   DevBuf* bufs[] = {&m->rec, &m->counts, &m->offsets, &m->scan_tmp, &m->g2d, &m->keys[0], &m->keys[1],
                     &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp,
                     &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
+                    &m->block_start, &m->big_list,
                     &m->inst_grad, &m->exp_part, &m->dbg_g, &m->gr_rgb, &m->gr_T, &m->gr_flags,
                     &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl};
   for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
@@ -544,6 +551,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     GS_TRY(ensure(m, m->dval[b], (size_t)std::max<int64_t>(vn, 1) * 4, s));
   }
   GS_TRY(ensure(m, m->inst_off, (size_t)std::max<int64_t>(vn, 1) * 4, s));
+  GS_TRY(ensure(m, m->big_list, (size_t)std::max<int64_t>(vn, 1) * 4, s));
   GS_TRY(ensure(m, m->exp_part, (size_t)std::max<int64_t>(tiles, 1) * 12 * 4, s));
   GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(std::max<int64_t>(std::max<int64_t>(vn, m->inst_cap), 1)) * 4,
                 s));
@@ -563,9 +571,12 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint32_t* offsets = (uint32_t*)m->offsets.ptr;
   uint32_t* dkey[2] = {(uint32_t*)m->dkey[0].ptr, (uint32_t*)m->dkey[1].ptr};
   uint32_t* dval[2] = {(uint32_t*)m->dval[0].ptr, (uint32_t*)m->dval[1].ptr};
+  uint32_t* big_n = m->d_ninst + 8;  // count of large-rectangle pairs (word 8 of the counter block)
   {
     StageTimer t(m, s, GS_STAGE_PROJECT);
-    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0], dval[0], s));
+    GS_HIP(fill_u32(big_n, 0u, 1, s));
+    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0], dval[0],
+                           (uint32_t*)m->big_list.ptr, big_n, s));
   }
   int dwhich = 0;
   {
@@ -595,8 +606,9 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint32_t* vals[2] = {(uint32_t*)m->vals[0].ptr, (uint32_t*)m->vals[1].ptr};
   {
     StageTimer t(m, s, GS_STAGE_DUPLICATE);
-    GS_HIP(duplicate_keys(rec, counts, order, offsets, N, va, keys[0], vals[0], (uint32_t*)m->emit_g.ptr,
-                          (uint32_t*)m->inst_off.ptr, m->inst_cap, m->d_overflow, s));
+    GS_HIP(duplicate_keys(rec, counts, order, offsets, m->d_ninst, (const uint32_t*)m->big_list.ptr, big_n, N, va,
+                          keys[0], vals[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr,
+                          (uint32_t*)m->block_start.ptr, m->inst_cap, m->d_overflow, s));
   }
   int which = 0;
   {
@@ -629,6 +641,7 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
 gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
                              const float* const* dL_dopacity, float* const* dL_dexposure, void* stream) {
   g_err.clear();
+  if (m) m->grads_dirty = true;
   return backward_impl(m, nv, dL_drgb, dL_ddepth, dL_dopacity, dL_dexposure, nullptr, (hipStream_t)stream);
 }
 
@@ -686,6 +699,7 @@ gs_status gs_adam_step(gs_map* m, int32_t ne, float* const* exposure_states, voi
   GS_HIP(adam_step(m->buf, m->cap, m->F, (int32_t)m->n, m->vis, lr, m->d_step, m->d_bc, d.beta1, d.beta2, d.eps,
                    ea, d.lr_exposure, s));
   if (m->n > 0) GS_HIP(fill_u32((uint32_t*)m->vis, 0u, (m->n + 3) / 4, s));
+  m->grads_dirty = false;  // every row with a gradient was visible and had it cleared
   m->h_step += 1;
   return GS_OK;
 }
@@ -914,7 +928,10 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   ad.beta1 = d.beta1;
   ad.beta2 = d.beta2;
   ad.eps = d.eps;
+  ad.grads_clean = m->grads_dirty ? 0 : 1;
+  m->step_assumed_clean = ad.grads_clean != 0;
   GS_TRY(backward_impl(m, nv, dl, nullptr, nullptr, eg, &ad, s));
+  m->grads_dirty = false;  // the fused update cleared every accumulated gradient it read
   ExpArg ea{};
   ea.n = nv;
   for (int v = 0; v < nv; ++v) ea.p[v] = exposure_states[v];
@@ -944,9 +961,13 @@ gs_status gs_capture_step(gs_map* m, int32_t nv, const gs_view* views, const gs_
   GS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   m->capturing = true;
   const int64_t step_before = m->h_step;
+  const bool dirty_before = m->grads_dirty;
+  m->step_assumed_clean = false;
   gs_status st = gs_step(m, nv, views, frames, targets, lambda, exposure_states, dl_drgb, loss_dev, stream);
   m->capturing = false;
-  m->h_step = step_before;
+  m->h_step = step_before;  // nothing ran yet
+  m->grads_dirty = dirty_before;
+  const bool assumes_clean = m->step_assumed_clean;
   std::string msg = g_err;
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);
@@ -970,14 +991,20 @@ gs_status gs_capture_step(gs_map* m, int32_t nv, const gs_view* views, const gs_
   g->map = m;
   g->graph = graph;
   g->exec = exec;
+  g->assumes_clean = assumes_clean;
   *out = g;
   return GS_OK;
 }
 
 gs_status gs_launch_step(gs_step_graph* g, void* stream) {
   if (!g) return fail(GS_ERR_INVALID, "graph is NULL");
+  if (g->assumes_clean && g->map->grads_dirty)
+    return fail(GS_ERR_STATE,
+                "the gradient planes may hold values (gs_render_backward or gs_map_params since the capture): "
+                "run gs_adam_step first, or capture again");
   GS_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   g->map->h_step += 1;
+  g->map->grads_dirty = false;
   return GS_OK;
 }
 
@@ -1001,7 +1028,10 @@ gs_status gs_map_params(gs_map* m, float** params, float** grads, float** am, fl
   if (!m) return fail(GS_ERR_INVALID, "map is NULL");
   const int64_t pl = (int64_t)m->F * m->cap;
   if (params) *params = m->buf;
-  if (grads) *grads = m->buf ? m->buf + pl : nullptr;
+  if (grads) {
+    *grads = m->buf ? m->buf + pl : nullptr;
+    m->grads_dirty = true;  // the caller may write them
+  }
   if (am) *am = m->buf ? m->buf + 2 * pl : nullptr;
   if (av) *av = m->buf ? m->buf + 3 * pl : nullptr;
   if (stride) *stride = m->cap;

@@ -258,109 +258,161 @@ hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* 
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------- duplicate
-// Thread k takes the k-th (view, Gaussian) pair in depth order and writes one instance per
-// tile its footprint reaches, at its scanned offset e: tiles_out[e] = global tile id,
-// vals_out[e] = e (the tile sort carries the emission index), emit_g[e] = Gaussian index;
-// inst_off[view * N + Gaussian] = first e of the pair. A block's pairs are consecutive, so
-// its instances form one contiguous range; it is assembled in LDS and written with
-// coalesced stores (direct stores if it is too long).
-constexpr int kDupLds = 4096;
+// Instances are emitted in depth order: pair k of the depth order ((view, Gaussian) id
+// order[k]) owns the instance range [offsets[k], offsets[k] + count). One lane per
+// instance, so the work does not depend on how unevenly the counts fall: block b covers
+// instances [256 b, 256 b + 256); it stages the offsets and ids of the (at most 256) pairs
+// from block_start[b] in LDS, finds its instance's pair by binary search and takes the
+// tile from the pair's 64-bit hit mask (its r-th set bit, row-major in the pair's tile
+// rectangle). Pairs whose rectangle has more than 64 tiles were listed by the projection;
+// one wave each evaluates the tile predicate over the rectangle and places the hits with
+// a ballot prefix sum. Instances past the capacity are not written; the overflow flag is
+// raised and the render is emptied downstream.
+constexpr int kLb = 256;
 
+// block_start[b] = the pair that owns instance 256 b.
 __global__ void __launch_bounds__(256)
-k_duplicate(const float4* __restrict__ rec, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ order,
-            const uint32_t* __restrict__ offsets, int32_t N, int64_t n_pairs, ViewsArg va,
-            uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ vals_out, uint32_t* __restrict__ emit_g,
-            uint32_t* __restrict__ inst_off, int64_t capacity, uint32_t* __restrict__ overflow) {
-  __shared__ uint32_t s_tile[kDupLds];
-  __shared__ uint32_t s_g[kDupLds];
-  __shared__ int64_t s_lo, s_hi;
-  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x;
-  const int64_t k = k0 + threadIdx.x;
-  uint32_t cnt = 0, vi = 0;
-  int64_t o = 0;
-  if (k < n_pairs) {
-    vi = order[k];
-    cnt = counts[vi];
-    o = offsets[k];
-    inst_off[vi] = (uint32_t)o;
+k_block_starts(const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ n_dev, int64_t n_pairs,
+               int64_t capacity, uint32_t* __restrict__ block_start) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  const int64_t total = n_dev[0];
+  const int64_t o = offsets[k];
+  const int64_t e = min(k + 1 < n_pairs ? (int64_t)offsets[k + 1] : total, min(total, capacity));
+  for (int64_t b = (o + kLb - 1) / kLb; b * kLb < e; ++b) block_start[b] = (uint32_t)k;
+}
+
+// position of the r-th set bit (r counted from 0) of a 32-bit word that has more than r
+__device__ __forceinline__ int nth_set_bit32(uint32_t w, uint32_t r) {
+  int pos = 0;
+#pragma unroll
+  for (int sh = 16; sh >= 1; sh >>= 1) {
+    const uint32_t c = (uint32_t)__popc(w & ((1u << sh) - 1u));
+    if (r >= c) {
+      r -= c;
+      w >>= sh;
+      pos += sh;
+    }
   }
-  if (threadIdx.x == 0) s_lo = o;
-  const int64_t klast = min(k0 + (int64_t)blockDim.x, n_pairs) - 1;
-  if (k == klast) s_hi = o + cnt;
+  return pos;
+}
+
+__global__ void __launch_bounds__(kLb)
+k_dup_lb(const float4* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ offsets,
+         const uint32_t* __restrict__ block_start, const uint32_t* __restrict__ n_dev, int64_t n_pairs, int32_t N,
+         ViewsArg va, int64_t capacity, uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ vals_out,
+         uint32_t* __restrict__ emit_g, uint32_t* __restrict__ inst_off, uint32_t* __restrict__ overflow) {
+  __shared__ uint32_t s_off[kLb + 1];
+  __shared__ uint32_t s_vi[kLb];
+  const int64_t total = n_dev[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && total > capacity) atomicOr(overflow, 1u);
+  const int64_t lim = min(total, capacity);
+  const int64_t slot0 = (int64_t)blockIdx.x * kLb;
+  if (slot0 >= lim) return;
+  const int64_t k0 = block_start[blockIdx.x];
+  {
+    const int64_t k = k0 + threadIdx.x;
+    s_off[threadIdx.x] = k < n_pairs ? offsets[k] : (uint32_t)total;
+    s_vi[threadIdx.x] = k < n_pairs ? order[k] : 0u;
+    if (threadIdx.x == 0) s_off[kLb] = k0 + kLb < n_pairs ? offsets[k0 + kLb] : (uint32_t)total;
+  }
   __syncthreads();
-  const int64_t lo = s_lo, hi = s_hi;
-  if (hi > capacity) {
-    if (threadIdx.x == 0) atomicOr(overflow, 1u);
-    return;
+  const int64_t slot = slot0 + threadIdx.x;
+  if (slot >= lim) return;
+  // the pairs k0 .. k0 + 255 cover this block (every pair before the unused ones has a
+  // tile): the last staged offset <= slot is the owner
+  int lo = 0, hi = kLb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)s_off[mid] <= slot) lo = mid;
+    else hi = mid - 1;
   }
-  const bool staged = hi - lo <= kDupLds;
-  if (cnt > 0) {
+  const uint32_t vi = s_vi[lo];
+  const uint32_t r = (uint32_t)(slot - (int64_t)s_off[lo]);
+  if (r == 0) inst_off[vi] = (uint32_t)slot;
+  const float4 r3 = rec[(size_t)vi * 4 + 3];
+  const uint32_t a = __float_as_uint(r3.x), b = __float_as_uint(r3.y);
+  const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
+  const int rw = x1 - x0 + 1;
+  if (rw * (y1 - y0 + 1) > 64) return;  // a listed pair: k_dup_big writes it
+  const uint32_t mlo = __float_as_uint(r3.z), mhi = __float_as_uint(r3.w);
+  const uint32_t clo = (uint32_t)__popc(mlo);
+  const int pos = r < clo ? nth_set_bit32(mlo, r) : 32 + nth_set_bit32(mhi, r - clo);
+  const int v = (int)(vi / (uint32_t)N);
+  const uint32_t g = vi - (uint32_t)v * (uint32_t)N;
+  const ViewDev& V = va.v[v];
+  tiles_out[slot] = (uint32_t)(V.tile_base + (y0 + pos / rw) * V.tiles_x + (x0 + pos % rw));
+  vals_out[slot] = (uint32_t)slot;
+  emit_g[slot] = g;
+}
+
+// One wave per listed pair (tile rectangle of more than 64 tiles).
+__global__ void __launch_bounds__(256)
+k_dup_big(const float4* __restrict__ rec, const uint32_t* __restrict__ big_list, const uint32_t* __restrict__ big_n,
+          const uint32_t* __restrict__ counts, const uint32_t* __restrict__ inst_off,
+          const uint32_t* __restrict__ n_dev, int32_t N, ViewsArg va, int64_t capacity,
+          uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ vals_out, uint32_t* __restrict__ emit_g) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  if ((int64_t)n_dev[0] > capacity) return;
+  const int64_t nb = big_n[0];
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
+  for (int64_t w = wave; w < nb; w += nwaves) {
+    const uint32_t vi = big_list[w];
     const int v = (int)(vi / (uint32_t)N);
     const uint32_t g = vi - (uint32_t)v * (uint32_t)N;
     const ViewDev& V = va.v[v];
-    const float4 r0 = rec[(size_t)vi * 4], r1 = rec[(size_t)vi * 4 + 1], r2 = rec[(size_t)vi * 4 + 2],
-                 r3 = rec[(size_t)vi * 4 + 3];
+    const float4* rp = rec + (size_t)vi * 4;
+    const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
     const uint32_t a = __float_as_uint(r3.x), b = __float_as_uint(r3.y);
     const int x0 = a & 0xffff, y0 = a >> 16, x1 = b & 0xffff, y1 = b >> 16;
-    const int rw = x1 - x0 + 1;
-    const int64_t end = o + cnt;
-    int64_t w = o;
-    auto put = [&](int tx, int ty) {
-      const uint32_t tile = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
-      if (staged) {
-        s_tile[w - lo] = tile;
-        s_g[w - lo] = g;
-      } else {
-        tiles_out[w] = tile;
-        vals_out[w] = (uint32_t)w;
-        emit_g[w] = g;
+    const int rw = x1 - x0 + 1, area = rw * (y1 - y0 + 1);
+    const int64_t o = inst_off[vi];
+    const uint32_t cnt = counts[vi];
+    uint32_t base = 0;
+    for (int t0 = 0; t0 < area; t0 += 64) {
+      const int t = t0 + lane;
+      int tx = 0, ty = 0;
+      bool hit = false;
+      if (t < area) {
+        tx = x0 + t % rw;
+        ty = y0 + t / rw;
+        hit = key_tile_hit(r0.x, r0.y, r0.z, r0.w, r1.x, r2.w, tx, ty);
       }
-      ++w;
-    };
-    if (rw * (y1 - y0 + 1) <= 64) {
-      // the count pass recorded which tiles passed
-      uint64_t hits = (uint64_t)__float_as_uint(r3.z) | ((uint64_t)__float_as_uint(r3.w) << 32);
-      while (hits && w < end) {
-        const int k = __ffsll((long long)hits) - 1;
-        hits &= hits - 1;
-        put(x0 + k % rw, y0 + k / rw);
+      const uint64_t m = __ballot(hit);
+      const uint32_t p = base + (uint32_t)__popcll(m & below);
+      if (hit && p < cnt) {
+        const int64_t slot = o + p;
+        tiles_out[slot] = (uint32_t)(V.tile_base + ty * V.tiles_x + tx);
+        vals_out[slot] = (uint32_t)slot;
+        emit_g[slot] = g;
       }
-    } else {
-      // same predicate as the count pass; writes never leave this pair's [o, o + cnt)
-      for (int ty = y0; ty <= y1 && w < end; ++ty)
-        for (int tx = x0; tx <= x1 && w < end; ++tx)
-          if (key_tile_hit(r0.x, r0.y, r0.z, r0.w, r1.x, r2.w, tx, ty)) put(tx, ty);
+      base += (uint32_t)__popcll(m);
     }
     // unreachable when both passes agree; the sentinel tile sorts after every real tile
-    for (; w < end; ++w) {
-      if (staged) {
-        s_tile[w - lo] = 0xffffffffu;
-        s_g[w - lo] = 0u;
-      } else {
-        tiles_out[w] = 0xffffffffu;
-        vals_out[w] = (uint32_t)w;
-        emit_g[w] = 0u;
-      }
-    }
-  }
-  if (staged) {
-    __syncthreads();
-    for (int64_t t = threadIdx.x; t < hi - lo; t += blockDim.x) {
-      tiles_out[lo + t] = s_tile[t];
-      vals_out[lo + t] = (uint32_t)(lo + t);
-      emit_g[lo + t] = s_g[t];
+    for (uint32_t p = base + lane; p < cnt; p += 64) {
+      tiles_out[o + p] = 0xffffffffu;
+      vals_out[o + p] = (uint32_t)(o + p);
+      emit_g[o + p] = 0u;
     }
   }
 }
 
+int64_t block_start_elems(int64_t capacity) { return capacity / kLb + 2; }
+
 hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
-                          int32_t N, const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g,
-                          uint32_t* inst_off, int64_t capacity, uint32_t* overflow, hipStream_t s) {
+                          const uint32_t* n_dev, const uint32_t* big_list, const uint32_t* big_n, int32_t N,
+                          const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g, uint32_t* inst_off,
+                          uint32_t* block_start, int64_t capacity, uint32_t* overflow, hipStream_t s) {
   const int64_t n = (int64_t)va.n * N;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rec, counts, order, offsets,
-                     N, n, va, tiles, vals, emit_g, inst_off, capacity, overflow);
+  if (n <= 0 || capacity <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_starts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, offsets, n_dev, n, capacity,
+                     block_start);
+  hipLaunchKernelGGL(k_dup_lb, dim3((unsigned)((capacity + kLb - 1) / kLb)), dim3(kLb), 0, s, rec, order, offsets,
+                     block_start, n_dev, n, N, va, capacity, tiles, vals, emit_g, inst_off, overflow);
+  hipLaunchKernelGGL(k_dup_big, dim3(512), dim3(256), 0, s, rec, big_list, big_n, counts, inst_off, n_dev, N, va,
+                     capacity, tiles, vals, emit_g);
   return hipGetLastError();
 }
 

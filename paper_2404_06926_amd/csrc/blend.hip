@@ -76,6 +76,42 @@ __device__ __forceinline__ float wave_sum_to_63(float x) {
   return x;
 }
 
+// Sums over the wave of eight values at once, transposing while reducing: each exchange
+// step halves the values a lane carries (the lane keeps one half, its partner the other),
+// so 8 values cost 4 + 2 + 1 exchanges instead of 8 per step. Steps: lane ^ 1 and lane ^ 2
+// (DPP quad_perm), lane ^ 4 (ds_swizzle), then the single value over lane bit 3 (DPP
+// row_shr:8, valid in lanes 8..15 of each row of 16) and lane bits 4, 5 (shuffles). On
+// return lane 8 + j of each row holds the wave total of v[rev3(j)], rev3 reversing the
+// three bits of j; other lanes hold partial sums.
+__device__ __forceinline__ float wave_sum8_transposed(const float (&v)[8], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  float w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float send = b0 ? v[k] : v[k + 4];
+    const float keep = b0 ? v[k + 4] : v[k];
+    w[k] = keep + dpp_f<0xB1, 0xf>(send);  // from lane ^ 1
+  }
+  float x[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float send = b1 ? w[k] : w[k + 2];
+    const float keep = b1 ? w[k + 2] : w[k];
+    x[k] = keep + dpp_f<0x4E, 0xf>(send);  // from lane ^ 2
+  }
+  const float send = b2 ? x[0] : x[1];
+  const float keep = b2 ? x[1] : x[0];
+  // ds_swizzle bit-mask mode: and 0x1f, or 0, xor 4 (from lane ^ 4 within 32 lanes)
+  float y = keep + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x101F));
+  y += dpp_f<0x118, 0xf>(y);  // row_shr:8: lanes 8..15 of a row add lanes 0..7
+  y += __shfl_xor(y, 16, 64);
+  y += __shfl_xor(y, 32, 64);
+  return y;
+}
+
+// index of the value whose total lane 8 + j (j = lane & 7) holds after wave_sum8_transposed
+__device__ __forceinline__ int rev3(int j) { return ((j & 1) << 2) | (j & 2) | ((j >> 2) & 1); }
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o, 64));
@@ -384,17 +420,27 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         }
       }
       if (!__any(any)) continue;
+      // terms 0..7 transposed (lanes 8..15 end with the totals), the rest by DPP rows
+      float g8[8];
 #pragma unroll
-      for (int f = 0; f < NG; ++f) gv[f] = wave_sum_to_63(gv[f]);
+      for (int f = 0; f < 8; ++f) g8[f] = gv[f];
+      const float tot = wave_sum8_transposed(g8, lane);
+#pragma unroll
+      for (int f = 8; f < NG; ++f) gv[f] = wave_sum_to_63(gv[f]);
+      if (lane >= 8 && lane < 16) {
+        const int f = rev3(lane & 7);
+        if (DET)
+          s_part[wid][j][f] = tot;
+        else if (tot != 0.0f)
+          unsafeAtomicAdd(vg + (size_t)s_g[j] * kGradFloats + f, tot);
+      }
       if (lane == 63) {
-        if (DET) {
 #pragma unroll
-          for (int f = 0; f < NG; ++f) s_part[wid][j][f] = gv[f];
-        } else {
-          float* dst = vg + (size_t)s_g[j] * kGradFloats;
-#pragma unroll
-          for (int f = 0; f < NG; ++f)
-            if (gv[f] != 0.0f) unsafeAtomicAdd(dst + f, gv[f]);
+        for (int f = 8; f < NG; ++f) {
+          if (DET)
+            s_part[wid][j][f] = gv[f];
+          else if (gv[f] != 0.0f)
+            unsafeAtomicAdd(vg + (size_t)s_g[j] * kGradFloats + f, gv[f]);
         }
       }
     }

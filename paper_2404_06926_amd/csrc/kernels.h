@@ -24,11 +24,14 @@ struct AdamArg {
   float* v;
   const float* bc;   // device bias corrections 1 - beta1^t, 1 - beta2^t
   float beta1, beta2, eps;
+  int32_t grads_clean;  // the gradient planes are known to be zero: do not read them
 };
 
 // projection (project.hip)
+// big_list / big_n (zeroed before): pairs whose tile rectangle exceeds 64 tiles.
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                           float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, hipStream_t s);
+                           float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, uint32_t* big_list,
+                           uint32_t* big_n, hipStream_t s);
 // With inst_grad != nullptr the 2D gradients are the sums, in emission order, of the
 // instance records [inst_off[vi], inst_off[vi] + counts[vi]); otherwise they come from g2d.
 // With adam != nullptr the Adam update of each row is applied in the same kernel (one step).
@@ -41,9 +44,13 @@ int64_t scan_temp_elems(int64_t n);
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s);
 hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* offsets, int64_t n,
                        uint32_t* temp, uint32_t* total, hipStream_t s);
+// Instances in depth order, one lane per instance (block_start: block_start_elems(capacity)
+// words); pairs listed in big_list (big_n of them) have more than 64 candidate tiles.
+int64_t block_start_elems(int64_t capacity);
 hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
-                          int32_t N, const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g,
-                          uint32_t* inst_off, int64_t capacity, uint32_t* overflow, hipStream_t s);
+                          const uint32_t* n_dev, const uint32_t* big_list, const uint32_t* big_n, int32_t N,
+                          const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g, uint32_t* inst_off,
+                          uint32_t* block_start, int64_t capacity, uint32_t* overflow, hipStream_t s);
 hipError_t gather_gaussians(const uint32_t* vals, const uint32_t* emit_g, const uint32_t* n_dev, int64_t cap,
                             uint32_t* out, hipStream_t s);
 int64_t sort_temp_elems(int64_t cap);

@@ -14,7 +14,7 @@ template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
               float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey,
-              uint32_t* __restrict__ dval) {
+              uint32_t* __restrict__ dval, uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -47,6 +47,8 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     dkey[vi] = cnt ? __float_as_uint(kp.zh) : 0xffffffffu;
     dval[vi] = (uint32_t)vi;
     if (cnt == 0) continue;
+    // rectangles past the 64-bit mask are binned by a wave each
+    if ((r[2] - r[0] + 1) * (r[3] - r[1] + 1) > 64) big_list[atomicAdd(big_n, 1u)] = (uint32_t)vi;
     // view-dependent colour: max(0, sum_k sh_k Y_k(dir) + 0.5)
     float dx = m0 - V.campos[0], dy = m1 - V.campos[1], dz = m2 - V.campos[2];
     const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -128,8 +130,9 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     if (!FUSED) {
       Gp[k] += g;
     } else {
-      const float acc = Gp[k];
-      const float gr = acc + g;  // what the separate path reads: 0 + gradient, plus earlier sums
+      // what the separate path reads: 0 + gradient, plus sums of earlier backward calls
+      const float acc = ad.grads_clean ? 0.0f : Gp[k];
+      const float gr = acc + g;
       if (acc != 0.0f) Gp[k] = 0.0f;
       float pp = P[k], mm = ad.m[k], vv = ad.v[k];
       adam_update(pp, mm, vv, gr, ad.lr.lr[f], ad.beta1, ad.beta2, ad.eps, ad.bc[0], ad.bc[1]);
@@ -347,9 +350,10 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
 
 template <int DEG>
 static hipError_t launch_fwd(const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                             float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, hipStream_t s) {
+                             float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, uint32_t* big_list,
+                             uint32_t* big_n, hipStream_t s) {
   hipLaunchKernelGGL(k_project_fwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, cap, N, va,
-                     near_z, rec, counts, dkey, dval);
+                     near_z, rec, counts, dkey, dval, big_list, big_n);
   return hipGetLastError();
 }
 
@@ -380,13 +384,13 @@ static hipError_t launch_bwd(float* P, float* G, int64_t cap, int32_t N, const V
 
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va,
                            float near_z, float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval,
-                           hipStream_t s) {
+                           uint32_t* big_list, uint32_t* big_n, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   switch (deg) {
-    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
-    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
-    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
-    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, dval, s);
+    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, dval, big_list, big_n, s);
+    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, dval, big_list, big_n, s);
+    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, dval, big_list, big_n, s);
+    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, dval, big_list, big_n, s);
   }
 }
 

@@ -436,3 +436,58 @@ def test_fused_step_equals_backward_then_adam():
             assert torch.equal(a, b)
         assert (maps[0].grads() == 0).all() and (maps[1].grads() == 0).all()
         assert (maps[0].visibility() == 0).all() and (maps[1].visibility() == 0).all()
+
+
+def test_fused_step_includes_gradients_of_an_earlier_backward():
+    # A render_backward without Adam leaves gradients in the planes; the next fused step
+    # must add them (it skips reading the planes only while they are known to be zero).
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    tg = [torch.tensor(scenes.smooth_image(5, c.height, c.width), device="cuda") for c in cams]
+    rng = np.random.default_rng(21)
+    extra = [torch.tensor(rng.normal(size=(3, c.height, c.width)), dtype=torch.float32, device="cuda") for c in cams]
+    out = []
+    for fused in (True, False):
+        m = gpu_map(params, deg)
+        m.set_deterministic(True)
+        m.set_fused_step(fused)
+        m.render(cams, exposures(cams))
+        m.render_backward(extra, None)
+        fr = [gslic.Frame(torch.empty(3, c.height, c.width, device="cuda"), torch.empty(c.height, c.width, device="cuda"),
+                          torch.empty(c.height, c.width, dtype=torch.int32, device="cuda")) for c in cams]
+        es = [gslic.identity_exposure_state() for _ in cams]
+        m.step(cams, fr, tg, es, [torch.empty(3, c.height, c.width, device="cuda") for c in cams],
+               torch.empty(len(cams), device="cuda"))
+        torch.cuda.synchronize()
+        out.append(m.params().clone())
+    assert torch.equal(out[0], out[1])
+
+
+def test_captured_clean_step_refuses_dirty_gradients():
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        m = gpu_map(params, deg)
+        tg = [torch.tensor(scenes.smooth_image(6, c.height, c.width), device="cuda") for c in cams]
+        fr = [gslic.Frame(torch.empty(3, c.height, c.width, device="cuda"), torch.empty(c.height, c.width, device="cuda"),
+                          torch.empty(c.height, c.width, dtype=torch.int32, device="cuda")) for c in cams]
+        es = [gslic.identity_exposure_state() for _ in cams]
+        gr = [torch.empty(3, c.height, c.width, device="cuda") for c in cams]
+        lo = torch.empty(len(cams), device="cuda")
+        m.step(cams, fr, tg, es, gr, lo)
+        torch.cuda.synchronize()
+        n_inst = m.debug_last_render()["n_inst"]
+        m.set_instance_policy(False, 2 * n_inst + 4096)
+        m.step(cams, fr, tg, es, gr, lo)
+        g = m.capture_step(cams, fr, tg, es, gr, lo)
+        g.launch()
+        m.render(cams, exposures(cams))
+        m.render_backward([torch.zeros(3, c.height, c.width, device="cuda") for c in cams], None)
+        with pytest.raises(gslic.GsError):
+            g.launch()
+        m.adam_step([])
+        g.launch()
+        torch.cuda.synchronize()
+        assert not m.check_overflow()
+        g.close()

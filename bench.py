@@ -291,8 +291,10 @@ def main():
     ap.add_argument("--lam", type=float, default=0.2)
     ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--blend-px", default="1,4",
+    ap.add_argument("--blend-px", default="1,2",
                     help="pixels per lane of the forward and backward blend kernels (1, 2 or 4)")
+    ap.add_argument("--bwd-mode", type=int, default=0,
+                    help="backward blend: 0 pixel order, 1 per Gaussian")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (a known-size kernel for counter scaling)")
     args = ap.parse_args()
@@ -335,6 +337,7 @@ def main():
     m.add_gaussians(torch.from_numpy(params).to(dev))
     fpx, bpx = (int(x) for x in args.blend_px.split(","))
     m.set_blend_config(fpx, bpx)
+    m.set_backward_mode(args.bwd_mode)
     B = StepBuffers(torch, gslic, cams, dev)
 
     def step():
@@ -385,6 +388,7 @@ def main():
     # algorithmic work per launch of each stage: bytes the method must move (all stages)
     # and FLOPs (blend kernels, bound by the vector ALU); per-unit figures in the design doc
     atomics = 36.0 * n_inst * (4 // bpx)   # one 9-float atomic add per wave and instance
+    # (the headline's adam stage is fused into project_backward: no separate pass)
     work = {
         "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + (64.0 + 12.0) * n_vis + 12.0 * V * args.n, 0),
         "depth_sort": ("hbm", 4 * 24.0 * V * args.n, 0),
@@ -395,10 +399,13 @@ def main():
         "blend": ("alu", 40.0 * n_inst + 20.0 * P, FWD_FLOPS_PER_PAIR * float(pairs)),
         "loss": ("hbm", 132.0 * P, 0),
         "blend_backward": ("alu", 40.0 * n_inst + 32.0 * P + atomics, BWD_FLOPS_PER_PAIR * float(pairs)),
-        "project_backward": ("hbm", 4.0 * F * n_vis * 3 + 96.0 * n_vis + 4.0 * V * args.n, 0),
-        "adam": ("hbm", 32.0 * F * n_vis, 0),
+        # fused with Adam: read and write parameters, m and v (3 x 4F B each way), read and
+        # clear the 48-B 2D-gradient record, read the tile counts
+        "project_backward": ("hbm", 24.0 * F * n_vis + 96.0 * n_vis + 4.0 * V * args.n, 0),
+        "adam": ("hbm", 2 * 4.0 * 48 * V, 0),   # exposures only: Gaussian rows update in project_backward
     }
-    names = {"blend_backward": f"k_blend_bwd<{bpx},false,false>", "blend": f"k_blend_fwd<{fpx},false>",
+    names = {"blend_backward": (f"k_blend_bwd<{bpx},false,false>" if args.bwd_mode == 0 else "k_blend_bwd_pg<false>"),
+             "blend": f"k_blend_fwd<{fpx},false>",
              "project_backward": f"k_project_bwd<{args.sh},true,{'true' if len(cams) > 1 else 'false'}>",
              "project": f"k_project_fwd<{args.sh}>"}
     tag = f"{args.workload}_{args.n // 1000}k_sh{args.sh}_{args.width}x{args.height}"
@@ -451,7 +458,8 @@ def main():
                                 + f" per step, loss 0.8 L1 + 0.2 D-SSIM, sparse Adam"),
                    "n_gaussians": args.n, "sh_degree": args.sh, "views_per_step": V,
                    "timing": "graph replay" if ms_graph is not None else "eager",
-                   "blend_px_per_lane": [fpx, bpx]},
+                   "blend_px_per_lane": [fpx, bpx],
+                   "backward_blend": "pixel order" if args.bwd_mode == 0 else "per Gaussian"},
         "roofline": roof,
         "eager_ms_per_step": ms_eager,
         "stages_ms": {k: round(v, 4) for k, v in per.items()},

@@ -322,8 +322,16 @@ gs_status gs_stage_times(gs_map* map, void* stream, double* ms, int64_t* count);
  * Default 0: wave-reduced float atomics. Takes effect from the next gs_render. */
 gs_status gs_set_deterministic(gs_map* map, int32_t enable);
 
+/* Parallelisation of the backward blend. mode 0 (default): pixel order, lanes own pixels
+ * and walk their lists back to front, per-Gaussian terms summed across the wave. mode 1:
+ * per Gaussian (Sec. III-D.1), lanes own a tile's list entries and walk its pixels, with
+ * prefix products and sums across lanes for the transmittance and the colour in front;
+ * the forward then keeps each pixel's pre-exposure colour (12 B per pixel). Gradients of
+ * the depth and opacity maps always use mode 0. Takes effect from the next gs_render. */
+gs_status gs_set_backward_mode(gs_map* map, int32_t mode);
+
 /* Launch configuration of the blend kernels: pixels per lane in the forward and backward
- * (1, 2 or 4; default 1 and 4). With p pixels per lane a tile is processed by 256 / p
+ * (1, 2 or 4; default 1 and 2). With p pixels per lane a tile is processed by 256 / p
  * lanes and each list entry's LDS reads and gradient reductions are shared by p pixels.
  * Results do not depend on it beyond FP32 summation order. */
 gs_status gs_set_blend_config(gs_map* map, int32_t fwd_px_per_lane, int32_t bwd_px_per_lane);

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgslic.so")
-SOURCES = ["api.hip", "project.hip", "binning.hip", "blend.hip", "loss.hip", "adam.hip", "growth.hip"]
+SOURCES = ["api.hip", "project.hip", "binning.hip", "blend.hip", "loss.hip", "adam.hip", "growth.hip", "blend_pg.hip"]
 # Packed FP32 instructions are disabled for device code; the host pass warns that it does
 # not know the feature, which is harmless.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -92,7 +92,10 @@ struct gs_map {
   bool grads_dirty = false;    // gradient planes may hold non-zero values (a backward without Adam,
                                // or their pointer was handed out)
   bool step_assumed_clean = false;  // the last fused gs_step skipped reading the gradient planes
-  int fwd_px = 1, bwd_px = 4;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
+  int fwd_px = 1, bwd_px = 2;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
+  int bwd_mode = 0;            // 0: pixel-order backward blend, 1: per-Gaussian (the forward keeps pre colour)
+  bool pre_saved = false;      // the last render kept the pre-exposure colour
+  DevBuf pixPre;               // 3 floats per pixel of the last render (per-Gaussian backward)
   uint32_t* d_nvn = nullptr;   // number of (view, Gaussian) pairs of the last render
   int64_t vn_cap = 0, inst_cap = 0, tiles_cap = 0, pix_cap = 0;
   bool sync_plan = true;
@@ -272,6 +275,7 @@ void fill_viewdev(ViewDev& d, const gs_view& v) {
   d.out_opac = nullptr;
   d.dl_ddepth = nullptr;
   d.dl_dopac = nullptr;
+  d.out_pre = nullptr;
 }
 
 // Records a start event for `stage` (when timing is on); stage_end records the stop.
@@ -397,7 +401,7 @@ gs_status gs_destroy_map(gs_map* m) {
                     &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
                     &m->block_start, &m->big_list,
                     &m->inst_grad, &m->exp_part, &m->dbg_g, &m->gr_rgb, &m->gr_T, &m->gr_flags,
-                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl};
+                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl, &m->pixPre};
   for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
   for (KeyframeSlot& k : m->kf) {
     dev_free(m, k.image, 3 * k.pix_bytes, s);
@@ -558,6 +562,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   GS_TRY(ensure(m, m->ranges, (size_t)tiles * 8, s));
   GS_TRY(ensure(m, m->pixT, (size_t)pix * 4, s));
   GS_TRY(ensure(m, m->pixN, (size_t)pix * 4, s));
+  if (m->bwd_mode == 1) GS_TRY(ensure(m, m->pixPre, (size_t)pix * 12, s));
   for (int v = 0; v < nv; ++v) {
     ViewDev& d = va.v[v];
     d.out_rgb = frames[v].rgb;
@@ -565,7 +570,9 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     d.out_nc = frames[v].n_contrib ? frames[v].n_contrib : (uint32_t*)m->pixN.ptr + d.pix_base;
     d.out_depth = frames[v].depth;
     d.out_opac = frames[v].opacity;
+    d.out_pre = m->bwd_mode == 1 ? (float*)m->pixPre.ptr + 3 * d.pix_base : nullptr;
   }
+  m->pre_saved = m->bwd_mode == 1;
   float4* rec = (float4*)m->rec.ptr;
   uint32_t* counts = (uint32_t*)m->counts.ptr;
   uint32_t* offsets = (uint32_t*)m->offsets.ptr;
@@ -665,11 +672,18 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
   const int32_t N = m->last_N;
   float4* rec = (float4*)m->rec.ptr;
   float* g2d = (float*)m->g2d.ptr;
+  bool maps = false;
+  for (int v = 0; v < nv; ++v) maps = maps || va.v[v].dl_ddepth || va.v[v].dl_dopac;
   {
     StageTimer t(m, s, GS_STAGE_BLEND_BACKWARD);
-    GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr,
-                          (const uint2*)m->ranges.ptr, g2d, m->deterministic ? (float*)m->inst_grad.ptr : nullptr,
-                          (float*)m->exp_part.ptr, m->bwd_px, s));
+    float* ig = m->deterministic ? (float*)m->inst_grad.ptr : nullptr;
+    if (m->bwd_mode == 1 && m->pre_saved && !maps)
+      GS_HIP(blend_backward_per_gaussian(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr,
+                                         (const uint32_t*)m->emit_g.ptr, (const uint2*)m->ranges.ptr, g2d, ig,
+                                         (float*)m->exp_part.ptr, s));
+    else
+      GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr,
+                            (const uint2*)m->ranges.ptr, g2d, ig, (float*)m->exp_part.ptr, m->bwd_px, s));
   }
   {
     StageTimer t(m, s, GS_STAGE_PROJECT_BACKWARD);
@@ -1124,6 +1138,15 @@ gs_status gs_set_deterministic(gs_map* m, int32_t enable) {
   if (!m) return fail(GS_ERR_INVALID, "map is NULL");
   m->deterministic = enable != 0;
   m->have_render = false;  // the next render sizes the per-instance buffers
+  return GS_OK;
+}
+
+gs_status gs_set_backward_mode(gs_map* m, int32_t mode) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (mode != 0 && mode != 1) return fail(GS_ERR_INVALID, "backward mode must be 0 (pixel order) or 1 (per Gaussian)");
+  if (m->capturing) return fail(GS_ERR_STATE, "cannot change the backward mode while capturing");
+  m->bwd_mode = mode;
+  m->have_render = false;  // the next render saves what the backward needs
   return GS_OK;
 }
 

@@ -250,6 +250,11 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     V.out_rgb[2 * P + p] = o2;
     V.out_T[p] = T[k];
     V.out_nc[p] = last[k];
+    if (V.out_pre) {
+      V.out_pre[p] = pre0;
+      V.out_pre[P + p] = pre1;
+      V.out_pre[2 * P + p] = pre2;
+    }
     if (DEPTH && V.out_depth) V.out_depth[p] = Dm[k];
     if (V.out_opac) V.out_opac[p] = 1.0f - T[k];  // Eq. 7 telescoped: sum a_i T_i = 1 - T_final
   }
@@ -549,6 +554,11 @@ static void launch_bwd(const ViewsArg& va, const float4* rec, int32_t N, const u
     launch_bwd_maps<PX, true>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s);
   else
     launch_bwd_maps<PX, false>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s);
+}
+
+hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_t s) {
+  hipLaunchKernelGGL(k_exposure_reduce, dim3(va.n), dim3(64), 0, s, va, exp_part);
+  return hipGetLastError();
 }
 
 hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,

@@ -1,0 +1,239 @@
+// Per-Gaussian backward of the blend (the parallelisation Sec. III-D.1 adopts for the
+// backward pass: lanes own Gaussians, not pixels).
+//
+// One wave per 16x16 tile. The tile's depth-sorted list is taken in chunks of 64 entries,
+// one entry per lane; for every pixel still open at the chunk (its last contributor lies
+// at or past the chunk start) the wave evaluates all 64 entries at that pixel and forms,
+// across lanes in depth order,
+//   T_i    = T_chunk * prod_{k < i} (1 - a_k)          (prefix product, DPP scan)
+//   acc_i  = C_chunk + sum_{k <= i} c_k a_k T_k         (prefix sum per channel)
+//   S_i    = pre - acc_i                                (colour behind entry i, incl. bg)
+//   dL/da_i = sum_ch G_ch (T_i c_i,ch - S_i,ch / (1 - a_i))
+// with pre the pixel's pre-exposure colour saved by the forward and G = A^T dL/dout. The
+// per-pixel state (T_chunk, C_chunk) moves to the next chunk through LDS. Each lane adds
+// its Gaussian's nine gradient terms over the tile's pixels in registers and writes them
+// once per instance: one atomic add per term, or, deterministic, the instance's record.
+// Contribution decisions follow the forward: entry i contributes at pixel p iff i is
+// before the pixel's saved list position and its alpha passes the cut-off.
+#include "gs_common.h"
+#include "kernels.h"
+
+namespace gs {
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_or(float v, float identity) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(identity), __float_as_int(v), CTRL, ROWS, 0xf,
+                                                    false));
+}
+
+// inclusive scans over the 64 lanes (lanes with no source take the identity)
+__device__ __forceinline__ float wave_scan_add(float x) {
+  x += dpp_or<0x111, 0xf>(x, 0.f);  // row_shr:1
+  x += dpp_or<0x112, 0xf>(x, 0.f);  // row_shr:2
+  x += dpp_or<0x114, 0xf>(x, 0.f);  // row_shr:4
+  x += dpp_or<0x118, 0xf>(x, 0.f);  // row_shr:8
+  x += dpp_or<0x142, 0xa>(x, 0.f);  // row_bcast:15 into rows 1 and 3
+  x += dpp_or<0x143, 0xc>(x, 0.f);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ float wave_scan_mul(float x) {
+  x *= dpp_or<0x111, 0xf>(x, 1.f);
+  x *= dpp_or<0x112, 0xf>(x, 1.f);
+  x *= dpp_or<0x114, 0xf>(x, 1.f);
+  x *= dpp_or<0x118, 0xf>(x, 1.f);
+  x *= dpp_or<0x142, 0xa>(x, 1.f);
+  x *= dpp_or<0x143, 0xc>(x, 1.f);
+  return x;
+}
+
+__device__ __forceinline__ float wave_sum_all(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <bool DET>
+__global__ void __launch_bounds__(64)
+k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
+               const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, float* __restrict__ g2d,
+               float* __restrict__ inst_grad, float* __restrict__ exp_part) {
+  __shared__ float s_T[256];          // transmittance in front of the current chunk
+  __shared__ float s_C[3][256];       // colour accumulated in front of the current chunk
+  __shared__ float s_P[3][256];       // pre-exposure colour of the pixel (incl. background)
+  __shared__ float s_G[3][256];       // dL/d(pre-exposure colour)
+  __shared__ uint32_t s_nc[256];      // list position after the pixel's last contributor
+  const int tile = blockIdx.x;
+  const int v = view_of_tile(va, tile);
+  const ViewDev& V = va.v[v];
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int lane = threadIdx.x;
+  const uint2 rg = ranges[tile];
+  const int n = (int)(rg.y - rg.x);
+  const float4* vrec = rec + (size_t)v * N * 4;
+  float* vg = g2d + (size_t)v * N * kGradFloats;
+  const int64_t P = (int64_t)V.W * V.H;
+
+  float e[12] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  uint32_t ncmax = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int p = lane + 64 * q;
+    const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f;
+    uint32_t nc = 0;
+    if (px < V.W && py < V.H) {
+      const int64_t o = (int64_t)py * V.W + px;
+      nc = V.out_nc[o];
+      g0 = V.dl_drgb[o];
+      g1 = V.dl_drgb[P + o];
+      g2 = V.dl_drgb[2 * P + o];
+      p0 = V.out_pre[o];
+      p1 = V.out_pre[P + o];
+      p2 = V.out_pre[2 * P + o];
+      e[0] += g0 * p0; e[1] += g0 * p1; e[2] += g0 * p2; e[3] += g0;
+      e[4] += g1 * p0; e[5] += g1 * p1; e[6] += g1 * p2; e[7] += g1;
+      e[8] += g2 * p0; e[9] += g2 * p1; e[10] += g2 * p2; e[11] += g2;
+    }
+    float G0 = g0, G1 = g1, G2 = g2;
+    if (V.exposure) {
+      const float* E = V.exposure;
+      G0 = E[0] * g0 + E[4] * g1 + E[8] * g2;
+      G1 = E[1] * g0 + E[5] * g1 + E[9] * g2;
+      G2 = E[2] * g0 + E[6] * g1 + E[10] * g2;
+    }
+    s_T[p] = 1.0f;
+    s_C[0][p] = s_C[1][p] = s_C[2][p] = 0.0f;
+    s_P[0][p] = p0;
+    s_P[1][p] = p1;
+    s_P[2][p] = p2;
+    s_G[0][p] = G0;
+    s_G[1][p] = G1;
+    s_G[2][p] = G2;
+    s_nc[p] = nc;
+    ncmax = max(ncmax, nc);
+  }
+  // one wave per block: LDS writes above are visible to every lane after the barrier
+  __syncthreads();
+  uint32_t nmax = ncmax;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, 64));
+  const int nlist = min((int)nmax, n);
+
+  for (int c0 = 0; c0 < nlist; c0 += 64) {
+    const int j = c0 + lane;
+    const bool live = j < nlist;
+    uint32_t e_idx = 0, g = 0;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+    float c2 = 0.f;
+    if (live) {
+      e_idx = vals[rg.x + j];
+      g = emit_g[e_idx];
+      const float4* r = vrec + (size_t)g * 4;
+      a = r[0];
+      b = r[1];
+      c2 = r[2].x;
+    }
+    float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int p = 0; p < 256; ++p) {
+      const uint32_t ncp = s_nc[p];
+      if ((int)ncp <= c0) continue;  // every contributor of this pixel lies before the chunk
+      const float pxc = (float)(tx * kTile + (p & 15)) + 0.5f, pyc = (float)(ty * kTile + (p >> 4)) + 0.5f;
+      float dx = 0.f, dy = 0.f, ex = 0.f, araw = 0.f, alpha = 0.f;
+      if (live && j < (int)ncp) {
+        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
+        if (power <= 0.0f) {
+          ex = __expf(power);
+          araw = b.y * ex;
+          alpha = fminf(kAlphaMax, araw);
+          if (alpha < kAlphaMin) alpha = 0.0f;
+        }
+      }
+      const float oma = 1.0f - alpha;
+      const float Tin = wave_scan_mul(oma);                 // prod_{k <= i} (1 - a_k)
+      const float T0 = s_T[p];
+      const float T = T0 * (Tin * __builtin_amdgcn_rcpf(oma));  // in front of entry i
+      const float w = alpha * T;
+      const float k0 = wave_scan_add(b.z * w), k1 = wave_scan_add(b.w * w), k2 = wave_scan_add(c2 * w);
+      const float C0 = s_C[0][p], C1 = s_C[1][p], C2 = s_C[2][p];
+      const float G0 = s_G[0][p], G1 = s_G[1][p], G2 = s_G[2][p];
+      if (alpha > 0.0f) {
+        const float iom = __builtin_amdgcn_rcpf(oma);
+        const float S0 = s_P[0][p] - (C0 + k0), S1 = s_P[1][p] - (C1 + k1), S2 = s_P[2][p] - (C2 + k2);
+        const float dalpha = G0 * (T * b.z - S0 * iom) + G1 * (T * b.w - S1 * iom) + G2 * (T * c2 - S2 * iom);
+        acc[6] += w * G0;
+        acc[7] += w * G1;
+        acc[8] += w * G2;
+        if (araw <= kAlphaMax) {
+          const float dpow = dalpha * alpha;
+          acc[0] += dpow * (a.z * dx + a.w * dy);
+          acc[1] += dpow * (a.w * dx + b.x * dy);
+          acc[2] += -0.5f * dpow * dx * dx;
+          acc[3] += -dpow * dx * dy;
+          acc[4] += -0.5f * dpow * dy * dy;
+          acc[5] += dalpha * ex;
+        }
+      }
+      // carry the pixel state to the next chunk (lane 63 holds the chunk totals)
+      if (lane == 63) {
+        s_T[p] = T0 * Tin;
+        s_C[0][p] = C0 + k0;
+        s_C[1][p] = C1 + k1;
+        s_C[2][p] = C2 + k2;
+      }
+    }
+    if (live) {
+      if (DET) {
+        float4* dst = (float4*)(inst_grad + (size_t)e_idx * 12);
+        dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        dst[2] = make_float4(acc[8], 0.f, 0.f, 0.f);
+      } else {
+        float* dst = vg + (size_t)g * kGradFloats;
+#pragma unroll
+        for (int f = 0; f < 9; ++f)
+          if (acc[f] != 0.0f) unsafeAtomicAdd(dst + f, acc[f]);
+      }
+    }
+  }
+  if (DET) {
+    // entries past every pixel's last contributor carry no gradient
+    for (int k = nlist + lane; k < n; k += 64) {
+      float4* dst = (float4*)(inst_grad + (size_t)vals[rg.x + k] * 12);
+      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+      dst[0] = z;
+      dst[1] = z;
+      dst[2] = z;
+    }
+  }
+  if (V.dl_dexp) {
+#pragma unroll
+    for (int f = 0; f < 12; ++f) e[f] = wave_sum_all(e[f]);
+    if (lane < 12) {
+      float s = 0.f;
+#pragma unroll
+      for (int f = 0; f < 12; ++f) s = lane == f ? e[f] : s;
+      if (DET)
+        exp_part[(size_t)tile * 12 + lane] = s;
+      else
+        unsafeAtomicAdd(V.dl_dexp + lane, s);
+    }
+  }
+}
+
+hipError_t blend_backward_per_gaussian(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                                       const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
+                                       float* exp_part, hipStream_t s) {
+  if (va.total_tiles <= 0) return hipSuccess;
+  if (inst_grad) {
+    hipLaunchKernelGGL(k_blend_bwd_pg<true>, dim3(va.total_tiles), dim3(64), 0, s, va, rec, N, vals, emit_g, ranges,
+                       g2d, inst_grad, exp_part);
+    return exposure_reduce(va, exp_part, s);
+  } else
+    hipLaunchKernelGGL(k_blend_bwd_pg<false>, dim3(va.total_tiles), dim3(64), 0, s, va, rec, N, vals, emit_g, ranges,
+                       g2d, inst_grad, exp_part);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -71,6 +71,14 @@ hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, cons
                           const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
                           float* exp_part, int px, hipStream_t s);
 
+// Per-Gaussian form of blend_backward (blend_pg.hip): needs the pre-exposure colour that
+// the forward saved in out_pre; colour and exposure gradients only (no depth / opacity maps).
+hipError_t blend_backward_per_gaussian(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
+                                       const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
+                                       float* exp_part, hipStream_t s);
+// fixed-order reduction of the per-tile exposure partials of the deterministic backward
+hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_t s);
+
 // loss (loss.hip)
 int64_t loss_temp_floats(int H, int W);
 hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,

@@ -10,13 +10,19 @@
 
 namespace gs {
 
+// Rectangles of up to this many candidate tiles are tested by their own lane.
+constexpr int kSerialTiles = 16;
+
 template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
               float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey,
               uint32_t* __restrict__ dval, uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  // lanes past the end stay (reading row N - 1) so that the whole wave takes part in the
+  // cooperative tile counting below; they write nothing
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i0 < N;
+  const int i = valid ? i0 : N - 1;
   constexpr int K = (DEG + 1) * (DEG + 1);
   const float m0 = P[i], m1 = P[cap + i], m2 = P[2 * cap + i];
   const KeyGeo G = key_geometry(P[3 * cap + i], P[4 * cap + i], P[5 * cap + i], P[6 * cap + i],
@@ -30,18 +36,45 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     const ViewDev& V = va.v[v];
     const size_t vi = (size_t)v * N + i;
     const KeyProj kp = key_project(V, G, m0, m1, m2, logit, near_z);
-    int r[4];
+    int r[4] = {0, 0, -1, -1};
     uint32_t cnt = 0;
     uint64_t hits = 0;  // passing tiles in row-major rectangle order (rectangles of <= 64 tiles)
-    if (kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) {
+    int area = 0;
+    if (valid && kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) area = (r[2] - r[0] + 1) * (r[3] - r[1] + 1);
+    if (area > 0 && area <= kSerialTiles) {
       int k = 0;
       for (int ty = r[1]; ty <= r[3]; ++ty)
         for (int tx = r[0]; tx <= r[2]; ++tx, ++k)
           if (key_tile_hit(kp.mx, kp.my, kp.A, kp.B, kp.C, kp.thr, tx, ty)) {
             ++cnt;
-            if (k < 64) hits |= 1ull << k;
+            hits |= 1ull << k;
           }
     }
+    // larger rectangles: the whole wave evaluates one lane's rectangle, 64 tiles per step,
+    // so no lane loops over hundreds of tiles while the others wait
+    uint64_t todo = __ballot(area > kSerialTiles);
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      const float mx = __shfl(kp.mx, src), my = __shfl(kp.my, src), A = __shfl(kp.A, src);
+      const float B = __shfl(kp.B, src), C = __shfl(kp.C, src), thr = __shfl(kp.thr, src);
+      const int x0 = __shfl(r[0], src), y0 = __shfl(r[1], src), rw = __shfl(r[2], src) - x0 + 1;
+      const int a_src = __shfl(area, src);
+      uint32_t c = 0;
+      uint64_t first = 0;
+      for (int t0 = 0; t0 < a_src; t0 += 64) {
+        const int t = t0 + (int)(threadIdx.x & 63);
+        const bool hit = t < a_src && key_tile_hit(mx, my, A, B, C, thr, x0 + t % rw, y0 + t / rw);
+        const uint64_t m = __ballot(hit);
+        if (t0 == 0) first = m;
+        c += (uint32_t)__popcll(m);
+      }
+      if ((int)(threadIdx.x & 63) == src) {
+        cnt = c;
+        hits = a_src <= 64 ? first : 0ull;
+      }
+    }
+    if (!valid) continue;
     counts[vi] = cnt;
     // depth-sort key of the pair: float bits of a positive depth, largest key when unused
     dkey[vi] = cnt ? __float_as_uint(kp.zh) : 0xffffffffu;

@@ -99,6 +99,7 @@ _SIGS = {
     "gs_set_instance_policy": (_I32, [_P, _I32, _I64]),
     "gs_check_overflow": (_I32, [_P, _P, ctypes.POINTER(_I32)]),
     "gs_set_blend_config": (_I32, [_P, _I32, _I32]),
+    "gs_set_backward_mode": (_I32, [_P, _I32]),
     "gs_set_stage_timing": (_I32, [_P, _I32]),
     "gs_set_deterministic": (_I32, [_P, _I32]),
     "gs_set_fused_step": (_I32, [_P, _I32]),
@@ -277,7 +278,10 @@ class GaussianMap:
         torch = _torch()
         p = [_P(), _P(), _P(), _P()]
         stride = _I64()
-        _check(lib().gs_map_params(self.handle, *[ctypes.byref(x) for x in p], ctypes.byref(stride)))
+        # ask only for the plane wanted: handing out the gradient pointer marks the
+        # gradient planes as possibly written
+        args = [ctypes.byref(x) if k == which else None for k, x in enumerate(p)]
+        _check(lib().gs_map_params(self.handle, *args, ctypes.byref(stride)))
         ptr = p[which].value
         cap = stride.value
         raw = self.allocator.view(ptr, self.F * cap * 4)
@@ -468,6 +472,10 @@ class GaussianMap:
 
     def set_deterministic(self, enable: bool):
         _check(lib().gs_set_deterministic(self.handle, 1 if enable else 0))
+
+    def set_backward_mode(self, mode: int):
+        """0: pixel-order backward blend; 1: per-Gaussian (lanes own list entries)."""
+        _check(lib().gs_set_backward_mode(self.handle, int(mode)))
 
     def set_blend_config(self, fwd_px_per_lane: int, bwd_px_per_lane: int):
         """Pixels per lane (1, 2 or 4) of the forward and backward blend kernels."""

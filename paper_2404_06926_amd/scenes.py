@@ -97,7 +97,7 @@ def random_quats(r: np.random.Generator, n: int) -> np.ndarray:
 
 def _assemble(means, log_scales, quats, logits, sh) -> np.ndarray:
     n = means.shape[0]
-    return np.concatenate([means, log_scales, quats, logits.reshape(n, 1), sh.reshape(n, -1)],
+    return np.concatenate([means, log_scales, quats, logits.reshape(n, 1), sh.reshape(n, sh.shape[1] * sh.shape[2])],
                           axis=1).astype(np.float32)
 
 

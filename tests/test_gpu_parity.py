@@ -94,10 +94,25 @@ def test_render_matches_oracle(name, px):
 
 @pytest.mark.parametrize("name,px,det", BWD)
 def test_backward_matches_oracle_adjoint(name, px, det):
+    _check_backward(name, px, det, mode=0)
+
+
+@pytest.mark.parametrize("name,det", [(n, False) for n in CASES] + [("c3a", True), ("multi", True)])
+def test_per_gaussian_backward_matches_oracle_adjoint(name, det):
+    # lanes own list entries and walk pixels (prefix products / sums across lanes)
+    _check_backward(name, 1, det, mode=1)
+
+
+def _check_backward(name, px, det, mode):
     torch = torch_mod()
     params, deg, cams = case(name)
-    print(f"case {name} px {px} deterministic {det}", flush=True)
-    m, frames = _run_gpu(params, deg, cams, px=px, det=det)
+    print(f"case {name} px {px} deterministic {det} mode {mode}", flush=True)
+    m = gpu_map(params, deg)
+    m.set_blend_config(px, px)
+    m.set_deterministic(det)
+    m.set_backward_mode(mode)
+    frames = m.render(cams, exposures(cams))
+    torch.cuda.synchronize()
     rng = np.random.default_rng(11)
     gouts = [rng.normal(size=(3, c.height, c.width)) for c in cams]
     gexp = [torch.zeros(12, device="cuda") for _ in cams]

@@ -351,13 +351,41 @@ def main():
         step()
     torch.cuda.synchronize()
 
+    # Every timed region starts from this state: the map's cost changes as Adam moves it
+    # (opacities and scales drift), so regions are made comparable by restoring parameters,
+    # Adam moments and exposure states before each (outside the timed regions).
+    snap = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in B.expo)]
+
+    def restore():
+        m.params().copy_(snap[0])
+        mm, vv = m.adam_moments()
+        mm.copy_(snap[1])
+        vv.copy_(snap[2])
+        for e, sv in zip(B.expo, snap[3:]):
+            e.copy_(sv)
+        torch.cuda.synchronize()
+
+    def work_counts():
+        dbg = m.debug_last_render()
+        return dict(n_inst=dbg["n_inst"], n_vis=int((dbg["counts"] > 0).sum().item()),
+                    pairs=sum(int(f.n_contrib.to(torch.int64).sum().item()) for f in B.frames),
+                    n_tiles=dbg["n_tiles"])
+
+    # work of the first step of a region (untimed), for the average with the last one
+    restore()
+    step()
+    torch.cuda.synchronize()
+    wc_first = work_counts()
+
     # eager timed region with per-stage HIP events
+    restore()
     m.set_stage_timing(True)
     m.stage_times()
     log(f"instances {n_inst0}; eager timed region ({args.steps} steps)")
     ms_eager = timed(torch, step, args.steps)
     stages = m.stage_times()
     m.set_stage_timing(False)
+    wc_last = work_counts()
 
     # captured step, replayed
     graph = None
@@ -367,19 +395,21 @@ def main():
         for _ in range(args.warmup):
             graph.launch()
         log(f"graph timed regions ({args.repeats} x {args.steps} steps)")
-        runs = [timed(torch, graph.launch, args.steps) for _ in range(max(args.repeats, 1))]
+        runs = []
+        for _ in range(max(args.repeats, 1)):
+            restore()
+            runs.append(timed(torch, graph.launch, args.steps))
         ms_graph = float(np.median(runs))
     if m.check_overflow():
         raise RuntimeError("instance buffer overflow during the timed steps")
     ms = ms_graph if ms_graph is not None else ms_eager
 
-    # work counts of the last step (outside the timed regions)
-    dbg = m.debug_last_render()
-    n_inst = dbg["n_inst"]
-    n_vis = int((dbg["counts"] > 0).sum().item())
-    pairs = sum(int(f.n_contrib.to(torch.int64).sum().item()) for f in B.frames)
+    # work per step: the mean of the first and last step of the eager region (the stage
+    # times are averages over that region; the work grows as the map moves)
+    avg = lambda k: (wc_first[k] + wc_last[k]) / 2.0
+    n_inst, n_vis, pairs = avg("n_inst"), avg("n_vis"), avg("pairs")
     F = 11 + 3 * (args.sh + 1) ** 2
-    T_total = dbg["n_tiles"]
+    T_total = wc_last["n_tiles"]
     P = sum(c.width * c.height for c in cams)
     tile_passes = (int(np.ceil(np.log2(T_total + 1))) + 7) // 8
     V = len(cams)
@@ -464,7 +494,8 @@ def main():
         "eager_ms_per_step": ms_eager,
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
         "kernels": kernel_table,
-        "counts": {"visible_pairs": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total},
+        "counts": {"visible_pairs": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total,
+                   "first_step": wc_first, "last_step": wc_last},
     }
 
     if args.workload == "batch8":
@@ -480,6 +511,7 @@ def main():
 
         for _ in range(args.warmup):
             plain()
+        restore()
         ms_plain = timed(torch, plain, args.steps)
         if m.check_overflow():
             raise RuntimeError("instance buffer overflow in the plain path")

@@ -174,18 +174,25 @@ k_radix_hist(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int
   hist[(int64_t)d * nblocks + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
 }
 
+// The block's keys are first placed in LDS in (digit, original order) order, then written
+// out by consecutive lanes, so each digit's run goes to consecutive global addresses.
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock)
 k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
                 uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
                 const uint32_t* __restrict__ hist_scan, int nblocks) {
-  __shared__ uint32_t s_cnt[kWaves][256];
-  __shared__ uint32_t s_base[kWaves][256];
+  __shared__ uint32_t s_cnt[kWaves][256];   // keys per (wave, digit), then the wave's offset
+  __shared__ uint32_t s_start[256];         // first LDS slot of each digit
+  __shared__ uint32_t s_gbase[256];         // global position of the block's first key of each digit
+  __shared__ uint32_t s_warp[kWaves];
+  __shared__ K s_key[kSortTile];
+  __shared__ uint32_t s_val[kSortTile];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int d = lane; d < 256; d += 64) s_cnt[wid][d] = 0;
   __syncthreads();
   const uint32_t n = sort_count(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wid * (64 * kSortItems);
+  const int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = blk0 + (int64_t)wid * (64 * kSortItems);
   K key[kSortItems];
   uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -208,25 +215,40 @@ k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* 
     rank[r] = prev + (uint32_t)__popcll(peers & lt);
   }
   __syncthreads();
-  // per-digit offsets of each wave inside the block, plus the block's global offset
+  // digit totals of the block, their exclusive scan (LDS start of each digit) and each
+  // wave's offset inside its digit run
   {
     const int d = threadIdx.x;
-    uint32_t run = hist_scan[(int64_t)d * nblocks + blockIdx.x];
+    uint32_t tot = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
-      s_base[w][d] = run;
-      run += s_cnt[w][d];
+      const uint32_t c = s_cnt[w][d];
+      s_cnt[w][d] = tot;
+      tot += c;
     }
+    uint32_t all;
+    const uint32_t start = block_exclusive_scan(tot, s_warp, all);
+    s_start[d] = start;
+    s_gbase[d] = hist_scan[(int64_t)d * nblocks + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t idx = base + r * 64 + lane;
     if (idx < n) {
-      const uint32_t pos = s_base[wid][dig[r]] + rank[r];
-      kout[pos] = key[r];
-      vout[pos] = val[r];
+      const uint32_t slot = s_start[dig[r]] + s_cnt[wid][dig[r]] + rank[r];
+      s_key[slot] = key[r];
+      s_val[slot] = val[r];
     }
+  }
+  __syncthreads();
+  const int64_t nblk = min((int64_t)kSortTile, (int64_t)n - blk0);
+  for (int t = threadIdx.x; t < nblk; t += kSortBlock) {
+    const K k = s_key[t];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t pos = s_gbase[d] + ((uint32_t)t - s_start[d]);
+    kout[pos] = k;
+    vout[pos] = s_val[t];
   }
 }
 

@@ -142,6 +142,59 @@ def timed(torch, fn, steps):
     return start.elapsed_time(stop) / steps
 
 
+def measure_outdoor(torch, gslic, args, dev):
+    """The outdoor-shaped single-view step (500k LiDAR-shaped Gaussians: ground, facades,
+    far points and a 20k sky shell; SH3; 1280x720; jittered-means target): graph replays
+    from a restored state, as for the headline."""
+    from paper_2404_06926_amd import scenes
+    params, cam = scenes.outdoor_scene(2000, deg=3)
+    target_params = scenes.jitter_means(params, 0.05, 2000)
+    cams = [cam]
+    tmap = gslic.GaussianMap(sh_degree=3, capacity=params.shape[0])
+    tmap.add_gaussians(torch.from_numpy(target_params).to(dev))
+    targets = [f.rgb.clone() for f in tmap.render(cams)]
+    tmap.close()
+    m = gslic.GaussianMap(sh_degree=3, capacity=params.shape[0])
+    m.add_gaussians(torch.from_numpy(params).to(dev))
+    fpx, bpx = (int(x) for x in args.blend_px.split(","))
+    m.set_blend_config(fpx, bpx)
+    B = StepBuffers(torch, gslic, cams, dev)
+    m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+    torch.cuda.synchronize()
+    n_inst = m.debug_last_render()["n_inst"]
+    m.set_instance_policy(False, int(n_inst * 1.5) + 65536)
+    for _ in range(args.warmup):
+        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+    torch.cuda.synchronize()
+    snap = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in B.expo)]
+    graph = m.capture_step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+    graph.launch()
+    m.params().copy_(snap[0])
+    mm, vv = m.adam_moments()
+    mm.copy_(snap[1])
+    vv.copy_(snap[2])
+    for e, sv in zip(B.expo, snap[3:]):
+        e.copy_(sv)
+    torch.cuda.synchronize()
+    ms = timed(torch, graph.launch, args.steps)
+    overflow = m.check_overflow()
+    graph.close()
+    # per-stage times of a few eager steps (HIP events around the stages)
+    m.set_stage_timing(True)
+    m.stage_times()
+    for _ in range(10):
+        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+    st = m.stage_times()
+    m.set_stage_timing(False)
+    pairs = int(B.frames[0].n_contrib.to(torch.int64).sum().item())
+    m.close()
+    if overflow:
+        raise RuntimeError("instance buffer overflow in the outdoor steps")
+    return {"workload": f"outdoor street, {params.shape[0]} Gaussians (LiDAR-shaped + 20k sky), SH3, 1280x720",
+            "iters_per_s": 1000.0 / ms, "ms_per_step": ms, "steps": args.steps, "instances": n_inst,
+            "pairs": pairs, "stages_ms": {k: round(v[0] / v[1], 4) for k, v in st.items() if v[1] > 0}}
+
+
 def _pinned(torch, a):
     t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
     t.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)))
@@ -291,6 +344,7 @@ def main():
     ap.add_argument("--lam", type=float, default=0.2)
     ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-outdoor", action="store_true", help="skip the outdoor single-view measurement")
     ap.add_argument("--blend-px", default="1,2",
                     help="pixels per lane of the forward and backward blend kernels (1, 2 or 4)")
     ap.add_argument("--bwd-mode", type=int, default=0,
@@ -522,6 +576,10 @@ def main():
 
     if graph is not None:
         graph.close()
+    if args.workload == "headline" and not args.no_outdoor:
+        m.close()
+        log("outdoor workload")
+        result["outdoor_single_view"] = measure_outdoor(torch, gslic, args, dev)
     if not args.no_cpu_baseline and args.workload == "headline":
         log("cpu baseline (oracle)")
         try:

@@ -128,8 +128,8 @@ hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* 
 // (digit-major), an exclusive scan of the histograms, then a stable scatter in which
 // every wave ranks its keys in order with ballot-based peer masks.
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 8;                       // keys per thread
-constexpr int kSortTile = kSortBlock * kSortItems;  // 2048 keys per block
+constexpr int kSortItems = 8;                       // keys per thread (16 measured slower: too few
+constexpr int kSortTile = kSortBlock * kSortItems;  // blocks for the 1M-key depth sort); 2048 per block
 constexpr int kWaves = kSortBlock / 64;
 
 // Elements to process: all of them when they fit, none after an overflow (the render is

@@ -167,11 +167,13 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
       const float acc = ad.grads_clean ? 0.0f : Gp[k];
       const float gr = acc + g;
       if (acc != 0.0f) Gp[k] = 0.0f;
-      float pp = P[k], mm = ad.m[k], vv = ad.v[k];
+      // each plane value is read and written once per step: stream it past the caches
+      float pp = __builtin_nontemporal_load(P + k), mm = __builtin_nontemporal_load(ad.m + k);
+      float vv = __builtin_nontemporal_load(ad.v + k);
       adam_update(pp, mm, vv, gr, ad.lr.lr[f], ad.beta1, ad.beta2, ad.eps, ad.bc[0], ad.bc[1]);
-      P[k] = pp;
-      ad.m[k] = mm;
-      ad.v[k] = vv;
+      __builtin_nontemporal_store(pp, P + k);
+      __builtin_nontemporal_store(mm, ad.m + k);
+      __builtin_nontemporal_store(vv, ad.v + k);
     }
   };
   bool any = false;

@@ -49,6 +49,11 @@ FWD_FLOPS_PER_PAIR = 22
 BWD_FLOPS_PER_PAIR = 56
 
 
+def split_config(args):
+    par, mn, bal = args.split.split(",")
+    return int(par), int(mn), float(bal)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -158,6 +163,7 @@ def measure_outdoor(torch, gslic, args, dev):
     m.add_gaussians(torch.from_numpy(params).to(dev))
     fpx, bpx = (int(x) for x in args.blend_px.split(","))
     m.set_blend_config(fpx, bpx)
+    m.set_tile_split(*split_config(args))
     B = StepBuffers(torch, gslic, cams, dev)
     m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
     torch.cuda.synchronize()
@@ -347,6 +353,8 @@ def main():
     ap.add_argument("--no-outdoor", action="store_true", help="skip the outdoor single-view measurement")
     ap.add_argument("--blend-px", default="1,2",
                     help="pixels per lane of the forward and backward blend kernels (1, 2 or 4)")
+    ap.add_argument("--split", default="4096,128,1.25",
+                    help="long-list split of the blend: parallel,min_chunk,balance (parallel 0: every tile whole)")
     ap.add_argument("--bwd-mode", type=int, default=0,
                     help="backward blend: 0 pixel order, 1 per Gaussian")
     ap.add_argument("--copy-probe", action="store_true",
@@ -392,6 +400,7 @@ def main():
     fpx, bpx = (int(x) for x in args.blend_px.split(","))
     m.set_blend_config(fpx, bpx)
     m.set_backward_mode(args.bwd_mode)
+    m.set_tile_split(*split_config(args))
     B = StepBuffers(torch, gslic, cams, dev)
 
     def step():
@@ -543,6 +552,7 @@ def main():
                    "n_gaussians": args.n, "sh_degree": args.sh, "views_per_step": V,
                    "timing": "graph replay" if ms_graph is not None else "eager",
                    "blend_px_per_lane": [fpx, bpx],
+                   "tile_split": list(split_config(args)),
                    "backward_blend": "pixel order" if args.bwd_mode == 0 else "per Gaussian"},
         "roofline": roof,
         "eager_ms_per_step": ms_eager,

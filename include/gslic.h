@@ -325,9 +325,9 @@ gs_status gs_set_deterministic(gs_map* map, int32_t enable);
 /* Parallelisation of the backward blend. mode 0 (default): pixel order, lanes own pixels
  * and walk their lists back to front, per-Gaussian terms summed across the wave. mode 1:
  * per Gaussian (Sec. III-D.1), lanes own a tile's list entries and walk its pixels, with
- * prefix products and sums across lanes for the transmittance and the colour in front;
- * the forward then keeps each pixel's pre-exposure colour (12 B per pixel). Gradients of
- * the depth and opacity maps always use mode 0. Takes effect from the next gs_render. */
+ * suffix products and sums across lanes for the transmittance in front of each entry and
+ * the colour behind it. Gradients of the depth and opacity maps always use mode 0. Takes
+ * effect from the next gs_render. */
 gs_status gs_set_backward_mode(gs_map* map, int32_t mode);
 
 /* Launch configuration of the blend kernels: pixels per lane in the forward and backward
@@ -335,6 +335,23 @@ gs_status gs_set_backward_mode(gs_map* map, int32_t mode);
  * lanes and each list entry's LDS reads and gradient reductions are shared by p pixels.
  * Results do not depend on it beyond FP32 summation order. */
 gs_status gs_set_blend_config(gs_map* map, int32_t fwd_px_per_lane, int32_t bwd_px_per_lane);
+
+/* Long tile lists (Sec. III-A: every tile blends its depth-sorted list front to back).
+ * A tile whose list holds more than `balance` times the mean list length and more than
+ * L = max(min_chunk, ceil(instances / parallel)) entries (L rounded up to a multiple of
+ * 64) is blended by ceil(n / L) workgroups, each over one of as many near-equal chunks
+ * of the list, and the chunks are composited in depth order; the backward walks the same
+ * chunks in parallel.
+ * With that L at most `parallel` tiles are split and the extra workgroups number at most
+ * `parallel`. parallel = 0 blends every tile in one workgroup; balance = 0 drops the
+ * comparison with the mean. Default: parallel 4096, min_chunk 128, balance 1.25. Results
+ * differ from the unsplit blend by FP32 summation order only (and, where a pixel's
+ * transmittance meets the stop threshold within rounding, by where it stops). Device
+ * memory: about 14 KiB per unit of `parallel`. The next gs_render_backward needs a
+ * gs_render after this call.
+ * Errors: GS_ERR_INVALID for parallel outside [0, 65536], min_chunk outside [1, 2^24] or
+ * balance outside [0, 1e6]; GS_ERR_STATE while capturing. */
+gs_status gs_set_tile_split(gs_map* map, int32_t parallel, int32_t min_chunk, float balance);
 
 #ifdef __cplusplus
 }

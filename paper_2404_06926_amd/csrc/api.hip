@@ -84,6 +84,7 @@ struct gs_map {
   DevBuf dkey[2], dval[2];     // depth-sort keys / (view, Gaussian) ids, double-buffered
   DevBuf emit_g, inst_off;     // Gaussian of each emission index; first emission index per pair
   DevBuf block_start, big_list;  // instance-parallel binning: first pair per block; large-rectangle pairs
+  DevBuf split_slot, split_extra, split_state;  // long lists cut into chunks (blend)
   DevBuf inst_grad, exp_part;  // deterministic backward: per-instance gradients, per-tile exposure sums
   DevBuf dbg_g;                // Gaussian index per instance in blend order (inspection only)
   DevBuf gr_rgb, gr_T, gr_flags, gr_off, gr_tmp, gr_d2;  // map growth: render, selection, scan, sky
@@ -93,9 +94,10 @@ struct gs_map {
                                // or their pointer was handed out)
   bool step_assumed_clean = false;  // the last fused gs_step skipped reading the gradient planes
   int fwd_px = 1, bwd_px = 2;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
+  int32_t split_par = 4096, split_min = 128;  // long-list split (SplitArg)
+  float split_balance = 1.25f;
+  SplitArg last_sp{};          // split of the last render, used by its backward
   int bwd_mode = 0;            // 0: pixel-order backward blend, 1: per-Gaussian (the forward keeps pre colour)
-  bool pre_saved = false;      // the last render kept the pre-exposure colour
-  DevBuf pixPre;               // 3 floats per pixel of the last render (per-Gaussian backward)
   uint32_t* d_nvn = nullptr;   // number of (view, Gaussian) pairs of the last render
   int64_t vn_cap = 0, inst_cap = 0, tiles_cap = 0, pix_cap = 0;
   bool sync_plan = true;
@@ -215,6 +217,19 @@ gs_status ensure_instances(gs_map* m, int64_t nc, int64_t vn, hipStream_t s) {
   return GS_OK;
 }
 
+SplitArg split_arg(gs_map* m, int64_t tiles) {
+  SplitArg sp{};
+  sp.par = m->split_par;
+  sp.min_len = m->split_min;
+  sp.balance = m->split_balance;
+  sp.tile_slot = (uint32_t*)m->split_slot.ptr;
+  sp.extra = (uint2*)m->split_extra.ptr;
+  sp.counts = (uint32_t*)m->ranges.ptr + 2 * tiles;
+  sp.n_inst = m->d_ninst;
+  sp.state = (float*)m->split_state.ptr;
+  return sp;
+}
+
 LrArg lr_table(const gs_map* m) {
   LrArg lr{};
   const gs_map_desc& d = m->desc;
@@ -275,7 +290,6 @@ void fill_viewdev(ViewDev& d, const gs_view& v) {
   d.out_opac = nullptr;
   d.dl_ddepth = nullptr;
   d.dl_dopac = nullptr;
-  d.out_pre = nullptr;
 }
 
 // Records a start event for `stage` (when timing is on); stage_end records the stop.
@@ -399,9 +413,9 @@ gs_status gs_destroy_map(gs_map* m) {
   DevBuf* bufs[] = {&m->rec, &m->counts, &m->offsets, &m->scan_tmp, &m->g2d, &m->keys[0], &m->keys[1],
                     &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp,
                     &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
-                    &m->block_start, &m->big_list,
+                    &m->block_start, &m->big_list, &m->split_slot, &m->split_extra, &m->split_state,
                     &m->inst_grad, &m->exp_part, &m->dbg_g, &m->gr_rgb, &m->gr_T, &m->gr_flags,
-                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl, &m->pixPre};
+                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl};
   for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
   for (KeyframeSlot& k : m->kf) {
     dev_free(m, k.image, 3 * k.pix_bytes, s);
@@ -559,10 +573,15 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   GS_TRY(ensure(m, m->exp_part, (size_t)std::max<int64_t>(tiles, 1) * 12 * 4, s));
   GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(std::max<int64_t>(std::max<int64_t>(vn, m->inst_cap), 1)) * 4,
                 s));
-  GS_TRY(ensure(m, m->ranges, (size_t)tiles * 8, s));
+  GS_TRY(ensure(m, m->ranges, (size_t)tiles * 8 + 16, s));  // + the split counters
+  if (m->split_par > 0) {
+    const size_t par = (size_t)m->split_par;
+    GS_TRY(ensure(m, m->split_slot, (size_t)std::max<int64_t>(tiles, 1) * 4, s));
+    GS_TRY(ensure(m, m->split_extra, par * 8, s));
+    GS_TRY(ensure(m, m->split_state, 2 * par * kSplitFields * kTile * kTile * 4, s));
+  }
   GS_TRY(ensure(m, m->pixT, (size_t)pix * 4, s));
   GS_TRY(ensure(m, m->pixN, (size_t)pix * 4, s));
-  if (m->bwd_mode == 1) GS_TRY(ensure(m, m->pixPre, (size_t)pix * 12, s));
   for (int v = 0; v < nv; ++v) {
     ViewDev& d = va.v[v];
     d.out_rgb = frames[v].rgb;
@@ -570,9 +589,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     d.out_nc = frames[v].n_contrib ? frames[v].n_contrib : (uint32_t*)m->pixN.ptr + d.pix_base;
     d.out_depth = frames[v].depth;
     d.out_opac = frames[v].opacity;
-    d.out_pre = m->bwd_mode == 1 ? (float*)m->pixPre.ptr + 3 * d.pix_base : nullptr;
   }
-  m->pre_saved = m->bwd_mode == 1;
   float4* rec = (float4*)m->rec.ptr;
   uint32_t* counts = (uint32_t*)m->counts.ptr;
   uint32_t* offsets = (uint32_t*)m->offsets.ptr;
@@ -627,12 +644,15 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint2* ranges = (uint2*)m->ranges.ptr;
   {
     StageTimer t(m, s, GS_STAGE_RANGES);
-    GS_HIP(fill_u32((uint32_t*)ranges, 0u, 2 * tiles, s));
+    GS_HIP(fill_u32((uint32_t*)ranges, 0u, 2 * tiles + 2, s));
     GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, s));
+    m->last_sp = split_arg(m, tiles);
+    GS_HIP(split_items(ranges, (int32_t)tiles, m->last_sp, s));
   }
   {
     StageTimer t(m, s, GS_STAGE_BLEND);
-    GS_HIP(blend_forward(va, rec, N, vals[which], (const uint32_t*)m->emit_g.ptr, ranges, m->fwd_px, s));
+    GS_HIP(blend_forward(va, rec, N, vals[which], (const uint32_t*)m->emit_g.ptr, ranges, m->last_sp, m->fwd_px,
+                         s));
   }
   m->have_render = true;
   m->last_va = va;
@@ -677,13 +697,14 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
   {
     StageTimer t(m, s, GS_STAGE_BLEND_BACKWARD);
     float* ig = m->deterministic ? (float*)m->inst_grad.ptr : nullptr;
-    if (m->bwd_mode == 1 && m->pre_saved && !maps)
+    if (m->bwd_mode == 1 && !maps)
       GS_HIP(blend_backward_per_gaussian(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr,
                                          (const uint32_t*)m->emit_g.ptr, (const uint2*)m->ranges.ptr, g2d, ig,
                                          (float*)m->exp_part.ptr, s));
     else
       GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr,
-                            (const uint2*)m->ranges.ptr, g2d, ig, (float*)m->exp_part.ptr, m->bwd_px, s));
+                            (const uint2*)m->ranges.ptr, g2d, ig, (float*)m->exp_part.ptr, m->last_sp,
+                            m->bwd_px, s));
   }
   {
     StageTimer t(m, s, GS_STAGE_PROJECT_BACKWARD);
@@ -1147,6 +1168,19 @@ gs_status gs_set_backward_mode(gs_map* m, int32_t mode) {
   if (m->capturing) return fail(GS_ERR_STATE, "cannot change the backward mode while capturing");
   m->bwd_mode = mode;
   m->have_render = false;  // the next render saves what the backward needs
+  return GS_OK;
+}
+
+gs_status gs_set_tile_split(gs_map* m, int32_t parallel, int32_t min_chunk, float balance) {
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (parallel < 0 || parallel > (1 << 16)) return fail(GS_ERR_INVALID, "parallel must be in [0, 65536]");
+  if (min_chunk < 1 || min_chunk > (1 << 24)) return fail(GS_ERR_INVALID, "min_chunk must be in [1, 2^24]");
+  if (!(balance >= 0.0f && balance <= 1e6f)) return fail(GS_ERR_INVALID, "balance must be in [0, 1e6]");
+  if (m->capturing) return fail(GS_ERR_STATE, "cannot change the tile split while capturing");
+  m->split_par = parallel;
+  m->split_min = min_chunk;
+  m->split_balance = balance;
+  m->have_render = false;  // a backward needs the split of its own render
   return GS_OK;
 }
 

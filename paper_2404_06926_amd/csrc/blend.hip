@@ -20,12 +20,35 @@
 // from that position down to 0, recovers T_i = T_{i+1} / (1 - alpha_i), keeps the colour
 // seen behind the current Gaussian, and reduces each Gaussian's nine gradient terms over
 // the 64 lanes of a wave with DPP row operations before one atomic add per wave and field.
+//
+// Long lists. A workgroup walks its tile's list serially per pixel, so a tile whose list
+// is much longer than the others (the horizon of a street scene gathers thousands of
+// pixel-sized Gaussians) sets the duration of the whole launch. Such lists are cut into
+// chunks (SplitArg, kernels.h) that separate workgroups blend:
+//   1. k_blend_trans: for every chunk but the last, each pixel's product of (1 - alpha)
+//      over the chunk's entries.
+//   2. k_blend_fwd: each chunk starts from the product of the earlier chunks' factors and
+//      blends its entries with the cut-offs of the serial walk (a pixel whose
+//      transmittance in front of the chunk is already below the stop threshold takes
+//      nothing from it), leaving its partial colour, depth, transmittance and last
+//      contributor per pixel.
+//   3. k_split_merge: adds the chunks up in depth order and writes the pixel outputs.
+//   4. k_blend_bwd: each chunk starts its reverse walk from its own transmittance and the
+//      colour, depth and opacity seen behind it (the later chunks and the background)
+//      instead of from the final transmittance and the background.
+// The passes are separate launches: the kernel boundary is what makes one workgroup's
+// writes visible to another, with no cache write-back per workgroup.
+// Front-to-back compositing is associative (C = C_front + T_front C_back, T = T_front
+// T_back), so the split changes results only by FP32 rounding order; a stop decision
+// within rounding of the threshold may fall one entry differently, as between any two
+// orders of evaluation.
 #include "gs_common.h"
 #include "kernels.h"
 
 namespace gs {
 
 constexpr int kBlendBlock = 256;
+#define NW_OF(PX) (kBlendBlock / (PX) / 64)
 
 // Minimum of q = A dx^2 + 2B dx dy + C dy^2 over [x0, x1] x [y0, y1] (offsets from the
 // mean) compared with thr: 0 inside; else the clamped 1-D minimum on the separating edges.
@@ -142,30 +165,306 @@ __device__ __forceinline__ int pixel_quadrant(int wid, int k) {
   return PX == 1 ? wid : (PX == 2 ? wid + 2 * k : k);
 }
 
+// quadrants covered by wave w
+template <int PX>
+__device__ __forceinline__ uint32_t wave_quadrants(int w) {
+  return PX == 1 ? (1u << w) : (PX == 2 ? ((1u << w) | (1u << (w + 2))) : 0xFu);
+}
+
+// Per-wave lists of the staged batch: the entries t < cnt whose quadrant mask meets wave
+// w's quadrants, in batch (depth) order, in s_list[w][0 .. s_len[w]). A wave then walks
+// only the entries that can reach its pixels: with pixel-sized footprints (long lists of
+// small Gaussians) most entries meet one quadrant. Called by every thread of the block.
+template <int PX, int NW, int NT>
+__device__ __forceinline__ void build_wave_lists(uint32_t m_own, int cnt, uint8_t (*s_list)[NT], int* s_len,
+                                                 uint32_t (*s_wc)[NW]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int t = threadIdx.x;
+  const uint32_t m = t < cnt ? m_own : 0u;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  bool hit[NW];
+  uint32_t rank[NW];
+#pragma unroll
+  for (int w2 = 0; w2 < NW; ++w2) {
+    hit[w2] = (m & wave_quadrants<PX>(w2)) != 0u;
+    const uint64_t b = __ballot(hit[w2]);
+    rank[w2] = (uint32_t)__popcll(b & lt);
+    if (lane == 0) s_wc[w2][wid] = (uint32_t)__popcll(b);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w2 = 0; w2 < NW; ++w2) {
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t c = s_wc[w2][w];
+      if (w < wid) off += c;
+      tot += c;
+    }
+    if (hit[w2]) s_list[w2][off + rank[w2]] = (uint8_t)t;
+    if (t == 0) s_len[w2] = (int)tot;
+  }
+  __syncthreads();
+}
+
+// ---- split lists -------------------------------------------------------------------
+// State of one chunk of a split tile, per pixel of the tile (field-major, 256 floats):
+//   0    the chunk's own transmittance factor (product of its entries' 1 - alpha)
+//   1-3  colour the chunk adds (sum of c a T, T the transmittance in front of the entry)
+//   4    depth the chunk adds
+//   5    transmittance after the chunk (where the pixel stopped, if it stopped in it)
+//   6    bits: list position after the chunk's last contributor | kStopped | kDead
+constexpr uint32_t kStopped = 1u << 31;   // the pixel's transmittance fell below kTMin here
+constexpr uint32_t kDead = 1u << 30;      // ... before the chunk: the chunk adds nothing
+constexpr uint32_t kPosMask = kDead - 1u;
+
+__device__ __forceinline__ float* split_field(const SplitArg& sp, uint32_t slot, int f) {
+  return sp.state + ((size_t)slot * kSplitFields + f) * (kTile * kTile);
+}
+
+// Chunk length for a render with n_inst instances (par > 0).
+__device__ __forceinline__ uint32_t chunk_len(uint32_t n_inst, int32_t par, int32_t min_len) {
+  const uint32_t L = max((n_inst + (uint32_t)par - 1u) / (uint32_t)par, (uint32_t)min_len);
+  return (L + 63u) & ~63u;
+}
+
+// Chunk c of a list of n entries cut into nch near-equal chunks: [begin, end).
+__device__ __forceinline__ void chunk_range(int n, int nch, int c, int& begin, int& end) {
+  begin = (int)((int64_t)c * n / nch);
+  end = (int)((int64_t)(c + 1) * n / nch);
+}
+
+struct BlendItem {
+  int tile, c, nch, begin, end;  // chunk c of nch covers list positions [begin, end)
+  uint32_t slot0;                // first state slot of the tile, kNoSlot if not split
+};
+
+// Work of block b: blocks [0, par) take the chunks >= 1 of split tiles (the long lists
+// start first), blocks [par, par + tiles) take tile b - par, whole or its chunk 0.
+// Returns false (uniformly over the block) for a block without work.
+__device__ __forceinline__ bool blend_item(const SplitArg& sp, const uint2* __restrict__ ranges, BlendItem& it) {
+  const int b = (int)blockIdx.x;
+  int tile = b - sp.par, c = 0;
+  if (b < sp.par) {
+    if ((uint32_t)b >= min(sp.counts[0], (uint32_t)sp.par)) return false;
+    const uint2 e = sp.extra[b];
+    if (e.x == kNoSlot) return false;
+    tile = (int)e.x;
+    c = (int)e.y;
+  }
+  const uint2 rg = ranges[tile];
+  const int n = (int)(rg.y - rg.x);
+  it.tile = tile;
+  it.c = c;
+  it.slot0 = sp.par > 0 ? sp.tile_slot[tile] : kNoSlot;
+  if (it.slot0 == kNoSlot) {
+    it.nch = 1;
+    it.begin = 0;
+    it.end = n;
+  } else {
+    const int L = (int)chunk_len(*sp.n_inst, sp.par, sp.min_len);
+    it.nch = (n + L - 1) / L;
+    chunk_range(n, it.nch, c, it.begin, it.end);
+  }
+  return true;
+}
+
+// One pixel's outputs from its pre-exposure colour (blended colour without background),
+// final transmittance, list position after the last contributor and depth.
+template <bool DEPTH>
+__device__ __forceinline__ void write_pixel(const ViewDev& V, int64_t p, float c0, float c1, float c2, float T,
+                                            uint32_t last, float D) {
+  const int64_t P = (int64_t)V.W * V.H;
+  const float pre0 = c0 + T * V.bg[0], pre1 = c1 + T * V.bg[1], pre2 = c2 + T * V.bg[2];
+  float o0 = pre0, o1 = pre1, o2 = pre2;
+  if (V.exposure) {
+    const float* E = V.exposure;
+    o0 = E[0] * pre0 + E[1] * pre1 + E[2] * pre2 + E[3];
+    o1 = E[4] * pre0 + E[5] * pre1 + E[6] * pre2 + E[7];
+    o2 = E[8] * pre0 + E[9] * pre1 + E[10] * pre2 + E[11];
+  }
+  V.out_rgb[p] = o0;
+  V.out_rgb[P + p] = o1;
+  V.out_rgb[2 * P + p] = o2;
+  V.out_T[p] = T;
+  V.out_nc[p] = last;
+  if (DEPTH && V.out_depth) V.out_depth[p] = D;
+  if (V.out_opac) V.out_opac[p] = 1.0f - T;  // Eq. 7 telescoped: sum a_i T_i = 1 - T_final
+}
+
+// Pass 3 of a split tile: block b merges the tile of extra item b when that item is the
+// tile's chunk 1 (one block per split tile); one pixel per lane. Per pixel the chunks are
+// taken in depth order up to the one the pixel stopped in.
+template <bool DEPTH>
+__global__ void __launch_bounds__(kTile * kTile)
+k_split_merge(ViewsArg va, const uint2* __restrict__ ranges, SplitArg sp) {
+  if (blockIdx.x >= min(sp.counts[0], (uint32_t)sp.par)) return;
+  const uint2 e = sp.extra[blockIdx.x];
+  if (e.x == kNoSlot || e.y != 1u) return;
+  const int tile = (int)e.x;
+  const uint32_t slot0 = sp.tile_slot[tile];
+  const uint2 rg = ranges[tile];
+  const int n = (int)(rg.y - rg.x);
+  const int L = (int)chunk_len(*sp.n_inst, sp.par, sp.min_len);
+  const int nch = (n + L - 1) / L;
+  const ViewDev& V = va.v[view_of_tile(va, tile)];
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int q = (int)threadIdx.x;
+  const int px = tx * kTile + (q & 15), py = ty * kTile + (q >> 4);
+  if (px >= V.W || py >= V.H) return;
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f, d = 0.f, T = 1.0f;
+  uint32_t last = 0;
+  for (int c = 0; c < nch; ++c) {
+    const uint32_t bits = __float_as_uint(split_field(sp, slot0 + c, 6)[q]);
+    if (bits & kDead) break;
+    c0 += split_field(sp, slot0 + c, 1)[q];
+    c1 += split_field(sp, slot0 + c, 2)[q];
+    c2 += split_field(sp, slot0 + c, 3)[q];
+    d += split_field(sp, slot0 + c, 4)[q];
+    T = split_field(sp, slot0 + c, 5)[q];
+    last = max(last, bits & kPosMask);
+    if (bits & kStopped) break;
+  }
+  write_pixel<DEPTH>(V, (int64_t)py * V.W + px, c0, c1, c2, T, last, d);
+}
+
+// Pass 1 of a split tile: block b takes chunk extra[b].y - 1 of tile extra[b].x (every
+// chunk but the last), one pixel per lane as k_blend_fwd with PX = 1.
+__global__ void __launch_bounds__(kBlendBlock)
+k_blend_trans(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
+              const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, SplitArg sp) {
+  constexpr int NT = kBlendBlock, NW = NT / 64;
+  __shared__ float4 s_a[NT];  // mx, my, A, B
+  __shared__ float2 s_b[NT];  // C, o
+  __shared__ uint8_t s_list[NW][NT];
+  __shared__ int s_len[NW];
+  __shared__ uint32_t s_wc[NW][NW];
+  if (blockIdx.x >= min(sp.counts[0], (uint32_t)sp.par)) return;
+  const uint2 e = sp.extra[blockIdx.x];
+  if (e.x == kNoSlot) return;
+  const int tile = (int)e.x, c = (int)e.y - 1;
+  const uint32_t slot0 = sp.tile_slot[tile];
+  const uint2 rg = ranges[tile];
+  const int n = (int)(rg.y - rg.x);
+  const int L = (int)chunk_len(*sp.n_inst, sp.par, sp.min_len);
+  int begin, end;
+  chunk_range(n, (n + L - 1) / L, c, begin, end);
+  const int v = view_of_tile(va, tile);
+  const ViewDev& V = va.v[v];
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const float4* vrec = rec + (size_t)v * N * 4;
+  int lx, ly;
+  lane_pixel<1>(wid, lane, 0, lx, ly);
+  const float pxc = (float)(tx * kTile + lx) + 0.5f, pyc = (float)(ty * kTile + ly) + 0.5f;
+  bool done = !(tx * kTile + lx < V.W && ty * kTile + ly < V.H);
+  float T = 1.0f;
+  for (int base = begin; base < end; base += NT) {
+    if (__syncthreads_count(done) == NT) break;
+    const int kk = base + (int)threadIdx.x;
+    uint32_t qm = 0;
+    if (kk < end) {
+      const uint32_t g = emit_g[vals[rg.x + kk]];
+      const float4* r = vrec + (size_t)g * 4;
+      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      s_a[threadIdx.x] = r0;
+      s_b[threadIdx.x] = make_float2(r1.x, r1.y);
+      qm = quadrant_mask(r0, r1, r2.w, tx, ty);
+    }
+    build_wave_lists<1, NW, NT>(qm, min(NT, end - base), s_list, s_len, s_wc);
+    if (!done) {
+      const int len = s_len[wid];
+      for (int jj = 0; jj < len; ++jj) {
+        const int j = s_list[wid][jj];
+        const float4 a = s_a[j];
+        const float2 b = s_b[j];
+        float dx, dy;
+        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
+        if (power > 0.0f) continue;
+        const float alpha = fminf(kAlphaMax, b.y * __expf(power));
+        if (alpha < kAlphaMin) continue;
+        T = T * (1.0f - alpha);
+        if (T < kTMin) {  // every later chunk is dead for this pixel whatever lies in front
+          done = true;
+          break;
+        }
+      }
+    }
+  }
+  split_field(sp, slot0 + c, 0)[ly * kTile + lx] = T;
+}
+
+// Items of a render: every tile longer than the chunk length and than `balance` times the
+// mean list takes ceil(n / L) state slots and lists its chunks >= 1 as extra items. counts[0..1]
+// are zero on entry.
+__global__ void k_split_items(const uint2* __restrict__ ranges, int32_t n_tiles, SplitArg sp) {
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= n_tiles) return;
+  const uint2 r = ranges[t];
+  const uint32_t n = r.y > r.x ? r.y - r.x : 0u;
+  const uint32_t n_inst = *sp.n_inst;
+  const uint32_t L = chunk_len(n_inst, sp.par, sp.min_len);
+  // lists within `balance` times the mean keep the launch balanced without a split
+  const float keep = sp.balance * (float)n_inst / (float)n_tiles;
+  uint32_t slot = kNoSlot;
+  if (n > L && (float)n > keep) {
+    const uint32_t nch = (n + L - 1u) / L;
+    const uint32_t s0 = atomicAdd(&sp.counts[1], nch);
+    const uint32_t e0 = atomicAdd(&sp.counts[0], nch - 1u);
+    const uint32_t par = (uint32_t)sp.par;
+    if (s0 + nch <= 2u * par && e0 + nch - 1u <= par) {
+      slot = s0;
+      for (uint32_t c = 1; c < nch; ++c) sp.extra[e0 + c - 1u] = make_uint2((uint32_t)t, c);
+    } else {
+      // cannot happen with L >= instances / par; kept consistent anyway: the tile is
+      // blended whole and its reserved items are marked empty
+      for (uint32_t c = 1; c < nch && e0 + c - 1u < par; ++c) sp.extra[e0 + c - 1u] = make_uint2(kNoSlot, 0u);
+    }
+  }
+  sp.tile_slot[t] = slot;
+}
+
+hipError_t split_items(const uint2* ranges, int32_t n_tiles, const SplitArg& sp, hipStream_t s) {
+  if (n_tiles <= 0 || sp.par <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_items, dim3((n_tiles + 255) / 256), dim3(256), 0, s, ranges, n_tiles, sp);
+  return hipGetLastError();
+}
+
 // DEPTH: also accumulate the depth map D = sum d_i a_i T_i (Eq. 6) for views that ask.
 template <int PX, bool DEPTH>
 __global__ void __launch_bounds__(kBlendBlock / PX)
 k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
-            const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges) {
+            const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, SplitArg sp) {
   constexpr int NT = kBlendBlock / PX;
   __shared__ float4 s_a[NT];   // mx, my, A, B
   __shared__ float4 s_b[NT];   // C, o, r, g
   __shared__ float s_c[NT];    // b
-  __shared__ float s_d[DEPTH ? NT : 1];  // camera-frame depth
+  __shared__ float s_d[NT];    // camera-frame depth
   __shared__ uint8_t s_m[NT];  // quadrant mask
-  const int tile = blockIdx.x;
+  __shared__ uint8_t s_list[NW_OF(PX)][NT];   // per-wave entry lists of the batch
+  __shared__ int s_len[NW_OF(PX)];
+  __shared__ uint32_t s_wc[NW_OF(PX)][NW_OF(PX)];
+  BlendItem it;
+  if (!blend_item(sp, ranges, it)) return;
+  const int tile = it.tile;
+  const bool split = it.slot0 != kNoSlot;
+  const uint32_t slot = it.slot0 + (uint32_t)it.c;
+  // a split tile always carries depth: a backward through the depth map needs the depth
+  // seen behind each chunk, whether or not this render outputs the map
+  const bool want_d = DEPTH || split;
   const int v = view_of_tile(va, tile);
   const ViewDev& V = va.v[v];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint2 rg = ranges[tile];
-  const int n = (int)(rg.y - rg.x);
   const float4* vrec = rec + (size_t)v * N * 4;
 
   float pxc[PX], pyc[PX], T[PX], C0[PX], C1[PX], C2[PX], Dm[PX];
   uint32_t last[PX];
-  bool done[PX];
+  bool done[PX], inside[PX], dead[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     int lx, ly;
@@ -173,8 +472,16 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     const int px = tx * kTile + lx, py = ty * kTile + ly;
     pxc[k] = (float)px + 0.5f;
     pyc[k] = (float)py + 0.5f;
-    done[k] = !(px < V.W && py < V.H);
+    inside[k] = px < V.W && py < V.H;
+    done[k] = !inside[k];
+    dead[k] = false;
     T[k] = 1.0f;
+    if (split && it.c > 0 && inside[k]) {
+      // transmittance in front of the chunk: the earlier chunks' factors
+      const int q = ly * kTile + lx;
+      for (int c = 0; c < it.c; ++c) T[k] *= split_field(sp, it.slot0 + c, 0)[q];
+      if (T[k] < kTMin) done[k] = dead[k] = true;  // stopped in an earlier chunk
+    }
     C0[k] = C1[k] = C2[k] = Dm[k] = 0.0f;
     last[k] = 0;
   }
@@ -185,23 +492,27 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     return d;
   };
   bool lane_done = all_done();
-  for (int base = 0; base < n; base += NT) {
+  for (int base = it.begin; base < it.end; base += NT) {
     if (__syncthreads_count(lane_done) == NT) break;
     const int kk = base + (int)threadIdx.x;
-    if (kk < n) {
+    uint32_t qm = 0;
+    if (kk < it.end) {
       const uint32_t g = emit_g[vals[rg.x + kk]];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
       s_a[threadIdx.x] = r0;
       s_b[threadIdx.x] = r1;
       s_c[threadIdx.x] = r2.x;
-      if (DEPTH) s_d[threadIdx.x] = r2.y;
-      s_m[threadIdx.x] = (uint8_t)quadrant_mask(r0, r1, r2.w, tx, ty);
+      if (want_d) s_d[threadIdx.x] = r2.y;
+      qm = quadrant_mask(r0, r1, r2.w, tx, ty);
+      s_m[threadIdx.x] = (uint8_t)qm;
     }
-    __syncthreads();
-    const int cnt = min(NT, n - base);
+    const int cnt = min(NT, it.end - base);
+    build_wave_lists<PX, NW_OF(PX), NT>(qm, cnt, s_list, s_len, s_wc);
     if (!lane_done) {
-      for (int j = 0; j < cnt; ++j) {
+      const int len = s_len[wid];
+      for (int jj = 0; jj < len; ++jj) {
+        const int j = s_list[wid][jj];
         const uint32_t m = s_m[j];
         const float4 a = s_a[j];
         const float4 b = s_b[j];
@@ -222,7 +533,7 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
           C0[k] += b.z * w;
           C1[k] += b.w * w;
           C2[k] += s_c[j] * w;
-          if (DEPTH) Dm[k] += s_d[j] * w;
+          if (want_d) Dm[k] += s_d[j] * w;
           T[k] = Tn;
           last[k] = (uint32_t)(base + j + 1);
         }
@@ -231,32 +542,27 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       }
     }
   }
-  const int64_t P = (int64_t)V.W * V.H;
+  if (!split) {
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      if (!inside[k]) continue;
+      const int64_t p = (int64_t)(int)pyc[k] * V.W + (int)pxc[k];
+      write_pixel<DEPTH>(V, p, C0[k], C1[k], C2[k], T[k], last[k], Dm[k]);
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
-    const int px = (int)pxc[k], py = (int)pyc[k];
-    if (px >= V.W || py >= V.H) continue;
-    const int64_t p = (int64_t)py * V.W + px;
-    const float pre0 = C0[k] + T[k] * V.bg[0], pre1 = C1[k] + T[k] * V.bg[1], pre2 = C2[k] + T[k] * V.bg[2];
-    float o0 = pre0, o1 = pre1, o2 = pre2;
-    if (V.exposure) {
-      const float* E = V.exposure;
-      o0 = E[0] * pre0 + E[1] * pre1 + E[2] * pre2 + E[3];
-      o1 = E[4] * pre0 + E[5] * pre1 + E[6] * pre2 + E[7];
-      o2 = E[8] * pre0 + E[9] * pre1 + E[10] * pre2 + E[11];
-    }
-    V.out_rgb[p] = o0;
-    V.out_rgb[P + p] = o1;
-    V.out_rgb[2 * P + p] = o2;
-    V.out_T[p] = T[k];
-    V.out_nc[p] = last[k];
-    if (V.out_pre) {
-      V.out_pre[p] = pre0;
-      V.out_pre[P + p] = pre1;
-      V.out_pre[2 * P + p] = pre2;
-    }
-    if (DEPTH && V.out_depth) V.out_depth[p] = Dm[k];
-    if (V.out_opac) V.out_opac[p] = 1.0f - T[k];  // Eq. 7 telescoped: sum a_i T_i = 1 - T_final
+    int lx, ly;
+    lane_pixel<PX>(wid, lane, k, lx, ly);
+    const int q = ly * kTile + lx;
+    const uint32_t bits = last[k] | (dead[k] ? kDead : (inside[k] && done[k] ? kStopped : 0u));
+    split_field(sp, slot, 1)[q] = C0[k];
+    split_field(sp, slot, 2)[q] = C1[k];
+    split_field(sp, slot, 3)[q] = C2[k];
+    split_field(sp, slot, 4)[q] = Dm[k];
+    split_field(sp, slot, 5)[q] = T[k];
+    split_field(sp, slot, 6)[q] = __uint_as_float(bits);
   }
 }
 
@@ -272,7 +578,7 @@ template <int PX, bool DET, bool MAPS>
 __global__ void __launch_bounds__(kBlendBlock / PX)
 k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
             const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, float* __restrict__ g2d,
-            float* __restrict__ inst_grad, float* __restrict__ exp_part) {
+            float* __restrict__ inst_grad, float* __restrict__ exp_part, SplitArg sp) {
   constexpr int NT = kBlendBlock / PX;
   constexpr int NW = NT / 64;
   constexpr int NG = MAPS ? 10 : 9;  // gradient terms per Gaussian
@@ -284,9 +590,16 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   __shared__ uint32_t s_e[DET ? NT : 1];
   __shared__ float s_part[DET ? NW : 1][DET ? NT : 1][NG];
   __shared__ uint8_t s_m[NT];
+  __shared__ uint8_t s_list[NW][NT];   // per-wave entry lists of the batch
+  __shared__ int s_len[NW];
+  __shared__ uint32_t s_wc[NW][NW];
   __shared__ float s_red[NW][12];
   __shared__ uint32_t s_wmax[NW];
-  const int tile = blockIdx.x;
+  BlendItem it;
+  if (!blend_item(sp, ranges, it)) return;
+  const int tile = it.tile;
+  const bool split = it.slot0 != kNoSlot;
+  const uint32_t slot = it.slot0 + (uint32_t)it.c;
   const int v = view_of_tile(va, tile);
   const ViewDev& V = va.v[v];
   const int lt = tile - V.tile_base;
@@ -341,6 +654,30 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     B0[k] = V.bg[0];
     B1[k] = V.bg[1];
     B2[k] = V.bg[2];
+    if (split && inside[k]) {
+      // start after this chunk: its own transmittance, and what the later chunks up to the
+      // one the pixel stopped in, then the background, add behind it (normalised)
+      const int q = ly * kTile + lx;
+      const float Tf = T[k];
+      float r0 = Tf * B0[k], r1 = Tf * B1[k], r2 = Tf * B2[k], rd = 0.f;
+      for (int c = it.c + 1; c < it.nch; ++c) {
+        const uint32_t bits = __float_as_uint(split_field(sp, it.slot0 + c, 6)[q]);
+        if (bits & kDead) break;
+        r0 += split_field(sp, it.slot0 + c, 1)[q];
+        r1 += split_field(sp, it.slot0 + c, 2)[q];
+        r2 += split_field(sp, it.slot0 + c, 3)[q];
+        rd += split_field(sp, it.slot0 + c, 4)[q];
+        if (bits & kStopped) break;
+      }
+      T[k] = split_field(sp, slot, 5)[q];
+      // a chunk past the pixel's stop has no contributor there; keep its state finite
+      const float inv = T[k] > 0.0f ? 1.0f / T[k] : 0.0f;
+      B0[k] = r0 * inv;
+      B1[k] = r1 * inv;
+      B2[k] = r2 * inv;
+      BD[k] = rd * inv;
+      BO[k] = 1.0f - Tf * inv;
+    }
     ncmax = max(ncmax, nc[k]);
   }
   const uint32_t wmax = wave_max_u32(ncmax);
@@ -350,10 +687,11 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
 #pragma unroll
   for (int w = 0; w < NW; ++w) nmax = max(nmax, (int)s_wmax[w]);
 
-  for (int end = nmax; end > 0; end -= NT) {
-    const int base = max(0, end - NT);
+  for (int end = min(nmax, it.end); end > it.begin; end -= NT) {
+    const int base = max(it.begin, end - NT);
     const int cnt = end - base;
     __syncthreads();
+    uint32_t qm = 0;
     if ((int)threadIdx.x < cnt) {
       const uint32_t e = vals[rg.x + base + threadIdx.x];
       const uint32_t g = emit_g[e];
@@ -364,7 +702,8 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       s_c[threadIdx.x] = r2.x;
       if (MAPS) s_d[threadIdx.x] = r2.y;
       s_g[threadIdx.x] = g;
-      s_m[threadIdx.x] = (uint8_t)quadrant_mask(r0, r1, r2.w, tx, ty);
+      qm = quadrant_mask(r0, r1, r2.w, tx, ty);
+      s_m[threadIdx.x] = (uint8_t)qm;
       if (DET) {
         s_e[threadIdx.x] = e;
 #pragma unroll
@@ -373,9 +712,11 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
           for (int f = 0; f < NG; ++f) s_part[w][threadIdx.x][f] = 0.f;
       }
     }
-    __syncthreads();
+    build_wave_lists<PX, NW, NT>(qm, cnt, s_list, s_len, s_wc);
     const int jtop = min(cnt, (int)wmax - base) - 1;  // entries at or past the wave's max are idle
-    for (int j = jtop; j >= 0; --j) {
+    for (int jj = s_len[wid] - 1; jj >= 0; --jj) {
+      const int j = s_list[wid][jj];
+      if (j > jtop) continue;
       const uint32_t m = s_m[j];
       const int pos = base + j;
       const float4 a = s_a[j];
@@ -468,8 +809,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   }
   if (DET) {
     // entries past every pixel's last contributor carry no gradient
-    const int n = (int)(rg.y - rg.x);
-    for (int k = nmax + (int)threadIdx.x; k < n; k += NT) {
+    for (int k = max(nmax, it.begin) + (int)threadIdx.x; k < it.end; k += NT) {
       float4* dst = (float4*)(inst_grad + (size_t)vals[rg.x + k] * 12);
       const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
       dst[0] = z;
@@ -477,8 +817,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       dst[2] = z;
     }
   }
-  // exposure gradient: dL/dA = sum g pre^T, dL/db = sum g (pre = B after the walk)
-  if (V.dl_dexp) {
+  // exposure gradient: dL/dA = sum g pre^T, dL/db = sum g (pre = B after the walk down to
+  // list position 0, so only the tile's first chunk has it)
+  if (V.dl_dexp && it.c == 0) {
     float e[12] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
@@ -517,43 +858,48 @@ __global__ void k_exposure_reduce(ViewsArg va, const float* __restrict__ exp_par
   V.dl_dexp[f] += s;
 }
 
+// blocks [0, par) for the chunks >= 1 of split tiles, then one per tile
+static dim3 item_grid(const ViewsArg& va, const SplitArg& sp) {
+  return dim3((unsigned)(va.total_tiles + (sp.par > 0 ? sp.par : 0)));
+}
+
 template <int PX>
 static void launch_fwd(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                       const uint32_t* emit_g, const uint2* ranges, hipStream_t s) {
+                       const uint32_t* emit_g, const uint2* ranges, const SplitArg& sp, hipStream_t s) {
   bool depth = false;
   for (int v = 0; v < va.n; ++v) depth = depth || va.v[v].out_depth != nullptr;
   if (depth)
-    hipLaunchKernelGGL((k_blend_fwd<PX, true>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec, N,
-                       vals, emit_g, ranges);
+    hipLaunchKernelGGL((k_blend_fwd<PX, true>), item_grid(va, sp), dim3(kBlendBlock / PX), 0, s, va, rec, N, vals,
+                       emit_g, ranges, sp);
   else
-    hipLaunchKernelGGL((k_blend_fwd<PX, false>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec, N,
-                       vals, emit_g, ranges);
+    hipLaunchKernelGGL((k_blend_fwd<PX, false>), item_grid(va, sp), dim3(kBlendBlock / PX), 0, s, va, rec, N, vals,
+                       emit_g, ranges, sp);
 }
 
 template <int PX, bool MAPS>
 static void launch_bwd_maps(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                             const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
-                            float* exp_part, hipStream_t s) {
+                            float* exp_part, const SplitArg& sp, hipStream_t s) {
   if (inst_grad) {
-    hipLaunchKernelGGL((k_blend_bwd<PX, true, MAPS>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec,
-                       N, vals, emit_g, ranges, g2d, inst_grad, exp_part);
+    hipLaunchKernelGGL((k_blend_bwd<PX, true, MAPS>), item_grid(va, sp), dim3(kBlendBlock / PX), 0, s, va, rec, N,
+                       vals, emit_g, ranges, g2d, inst_grad, exp_part, sp);
     hipLaunchKernelGGL(k_exposure_reduce, dim3(va.n), dim3(64), 0, s, va, exp_part);
   } else {
-    hipLaunchKernelGGL((k_blend_bwd<PX, false, MAPS>), dim3(va.total_tiles), dim3(kBlendBlock / PX), 0, s, va, rec,
-                       N, vals, emit_g, ranges, g2d, inst_grad, exp_part);
+    hipLaunchKernelGGL((k_blend_bwd<PX, false, MAPS>), item_grid(va, sp), dim3(kBlendBlock / PX), 0, s, va, rec, N,
+                       vals, emit_g, ranges, g2d, inst_grad, exp_part, sp);
   }
 }
 
 template <int PX>
 static void launch_bwd(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                        const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad, float* exp_part,
-                       hipStream_t s) {
+                       const SplitArg& sp, hipStream_t s) {
   bool maps = false;
   for (int v = 0; v < va.n; ++v) maps = maps || va.v[v].dl_ddepth != nullptr || va.v[v].dl_dopac != nullptr;
   if (maps)
-    launch_bwd_maps<PX, true>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s);
+    launch_bwd_maps<PX, true>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, sp, s);
   else
-    launch_bwd_maps<PX, false>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s);
+    launch_bwd_maps<PX, false>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, sp, s);
 }
 
 hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_t s) {
@@ -562,25 +908,37 @@ hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_
 }
 
 hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                         const uint32_t* emit_g, const uint2* ranges, int px, hipStream_t s) {
+                         const uint32_t* emit_g, const uint2* ranges, const SplitArg& sp, int px,
+                         hipStream_t s) {
   if (va.total_tiles <= 0) return hipSuccess;
+  if (px != 1 && px != 2 && px != 4) return hipErrorInvalidValue;
+  if (sp.par > 0)
+    hipLaunchKernelGGL(k_blend_trans, dim3((unsigned)sp.par), dim3(kBlendBlock), 0, s, va, rec, N, vals, emit_g,
+                       ranges, sp);
   switch (px) {
-    case 1: launch_fwd<1>(va, rec, N, vals, emit_g, ranges, s); break;
-    case 2: launch_fwd<2>(va, rec, N, vals, emit_g, ranges, s); break;
-    case 4: launch_fwd<4>(va, rec, N, vals, emit_g, ranges, s); break;
-    default: return hipErrorInvalidValue;
+    case 1: launch_fwd<1>(va, rec, N, vals, emit_g, ranges, sp, s); break;
+    case 2: launch_fwd<2>(va, rec, N, vals, emit_g, ranges, sp, s); break;
+    default: launch_fwd<4>(va, rec, N, vals, emit_g, ranges, sp, s); break;
+  }
+  if (sp.par > 0) {
+    bool depth = false;
+    for (int v = 0; v < va.n; ++v) depth = depth || va.v[v].out_depth != nullptr;
+    if (depth)
+      hipLaunchKernelGGL(k_split_merge<true>, dim3((unsigned)sp.par), dim3(kTile * kTile), 0, s, va, ranges, sp);
+    else
+      hipLaunchKernelGGL(k_split_merge<false>, dim3((unsigned)sp.par), dim3(kTile * kTile), 0, s, va, ranges, sp);
   }
   return hipGetLastError();
 }
 
 hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                           const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
-                          float* exp_part, int px, hipStream_t s) {
+                          float* exp_part, const SplitArg& sp, int px, hipStream_t s) {
   if (va.total_tiles <= 0) return hipSuccess;
   switch (px) {
-    case 1: launch_bwd<1>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s); break;
-    case 2: launch_bwd<2>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s); break;
-    case 4: launch_bwd<4>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, s); break;
+    case 1: launch_bwd<1>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, sp, s); break;
+    case 2: launch_bwd<2>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, sp, s); break;
+    case 4: launch_bwd<4>(va, rec, N, vals, emit_g, ranges, g2d, inst_grad, exp_part, sp, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

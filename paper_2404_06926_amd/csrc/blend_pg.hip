@@ -2,19 +2,24 @@
 // backward pass: lanes own Gaussians, not pixels).
 //
 // One wave per 16x16 tile. The tile's depth-sorted list is taken in chunks of 64 entries,
-// one entry per lane; for every pixel still open at the chunk (its last contributor lies
-// at or past the chunk start) the wave evaluates all 64 entries at that pixel and forms,
-// across lanes in depth order,
-//   T_i    = T_chunk * prod_{k < i} (1 - a_k)          (prefix product, DPP scan)
-//   acc_i  = C_chunk + sum_{k <= i} c_k a_k T_k         (prefix sum per channel)
-//   S_i    = pre - acc_i                                (colour behind entry i, incl. bg)
+// from the chunk holding the last contributor back to the first, one entry per lane with
+// the chunk's deepest entry in lane 0. For every pixel still open at the chunk (its last
+// contributor lies at or past the chunk start) the wave evaluates the 64 entries at that
+// pixel and forms, across lanes (inclusive or exclusive scans from the back of the chunk):
+//   Q_i    = prod_{k >= i} (1 - a_k)                    (suffix product, DPP scan)
+//   T_i    = T_after / Q_i                              (transmittance in front of i)
+//   S_i    = S_after + sum_{k > i} c_k a_k T_k          (colour behind i, incl. background)
 //   dL/da_i = sum_ch G_ch (T_i c_i,ch - S_i,ch / (1 - a_i))
-// with pre the pixel's pre-exposure colour saved by the forward and G = A^T dL/dout. The
-// per-pixel state (T_chunk, C_chunk) moves to the next chunk through LDS. Each lane adds
-// its Gaussian's nine gradient terms over the tile's pixels in registers and writes them
-// once per instance: one atomic add per term, or, deterministic, the instance's record.
-// Contribution decisions follow the forward: entry i contributes at pixel p iff i is
-// before the pixel's saved list position and its alpha passes the cut-off.
+// with G = A^T dL/dout, and (T_after, S_after) the transmittance after the chunk and the
+// colour behind it, which start at (T_final, T_final bg) and move to the previous chunk
+// through LDS. Every sum adds positive terms from the back, so the colour behind a deep
+// entry keeps its relative precision however small the transmittance has become. Each
+// lane adds its Gaussian's nine gradient terms over the tile's pixels in registers and
+// writes them once per instance: one atomic add per term, or, deterministic, the
+// instance's record. After the first chunk S_after is the pixel's pre-exposure colour,
+// which gives the exposure gradient. Contribution decisions follow the forward: entry i
+// contributes at pixel p iff i is before the pixel's saved list position and its alpha
+// passes the cut-off.
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -58,9 +63,8 @@ __global__ void __launch_bounds__(64)
 k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
                const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, float* __restrict__ g2d,
                float* __restrict__ inst_grad, float* __restrict__ exp_part) {
-  __shared__ float s_T[256];          // transmittance in front of the current chunk
-  __shared__ float s_C[3][256];       // colour accumulated in front of the current chunk
-  __shared__ float s_P[3][256];       // pre-exposure colour of the pixel (incl. background)
+  __shared__ float s_T[256];          // transmittance after the current chunk
+  __shared__ float s_S[3][256];       // colour behind the current chunk (incl. background)
   __shared__ float s_G[3][256];       // dL/d(pre-exposure colour)
   __shared__ uint32_t s_nc[256];      // list position after the pixel's last contributor
   const int tile = blockIdx.x;
@@ -75,27 +79,25 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
   float* vg = g2d + (size_t)v * N * kGradFloats;
   const int64_t P = (int64_t)V.W * V.H;
 
-  float e[12] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float gl[4][3];  // dL/dout of the lane's four pixels (exposure gradient)
   uint32_t ncmax = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int p = lane + 64 * q;
     const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, T = 1.0f;
     uint32_t nc = 0;
     if (px < V.W && py < V.H) {
       const int64_t o = (int64_t)py * V.W + px;
       nc = V.out_nc[o];
+      T = V.out_T[o];
       g0 = V.dl_drgb[o];
       g1 = V.dl_drgb[P + o];
       g2 = V.dl_drgb[2 * P + o];
-      p0 = V.out_pre[o];
-      p1 = V.out_pre[P + o];
-      p2 = V.out_pre[2 * P + o];
-      e[0] += g0 * p0; e[1] += g0 * p1; e[2] += g0 * p2; e[3] += g0;
-      e[4] += g1 * p0; e[5] += g1 * p1; e[6] += g1 * p2; e[7] += g1;
-      e[8] += g2 * p0; e[9] += g2 * p1; e[10] += g2 * p2; e[11] += g2;
     }
+    gl[q][0] = g0;
+    gl[q][1] = g1;
+    gl[q][2] = g2;
     float G0 = g0, G1 = g1, G2 = g2;
     if (V.exposure) {
       const float* E = V.exposure;
@@ -103,11 +105,10 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
       G1 = E[1] * g0 + E[5] * g1 + E[9] * g2;
       G2 = E[2] * g0 + E[6] * g1 + E[10] * g2;
     }
-    s_T[p] = 1.0f;
-    s_C[0][p] = s_C[1][p] = s_C[2][p] = 0.0f;
-    s_P[0][p] = p0;
-    s_P[1][p] = p1;
-    s_P[2][p] = p2;
+    s_T[p] = T;
+    s_S[0][p] = T * V.bg[0];
+    s_S[1][p] = T * V.bg[1];
+    s_S[2][p] = T * V.bg[2];
     s_G[0][p] = G0;
     s_G[1][p] = G1;
     s_G[2][p] = G2;
@@ -121,8 +122,8 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
   for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, o, 64));
   const int nlist = min((int)nmax, n);
 
-  for (int c0 = 0; c0 < nlist; c0 += 64) {
-    const int j = c0 + lane;
+  for (int c0 = ((nlist - 1) / 64) * 64; nlist > 0 && c0 >= 0; c0 -= 64) {
+    const int j = c0 + 63 - lane;  // lane 0 holds the deepest entry of the chunk
     const bool live = j < nlist;
     uint32_t e_idx = 0, g = 0;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -151,16 +152,18 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
         }
       }
       const float oma = 1.0f - alpha;
-      const float Tin = wave_scan_mul(oma);                 // prod_{k <= i} (1 - a_k)
-      const float T0 = s_T[p];
-      const float T = T0 * (Tin * __builtin_amdgcn_rcpf(oma));  // in front of entry i
+      const float Q = wave_scan_mul(oma);   // prod over this entry and the deeper ones
+      const float Ta = s_T[p];
+      const float T = Ta * __builtin_amdgcn_rcpf(Q);  // in front of this entry
       const float w = alpha * T;
-      const float k0 = wave_scan_add(b.z * w), k1 = wave_scan_add(b.w * w), k2 = wave_scan_add(c2 * w);
-      const float C0 = s_C[0][p], C1 = s_C[1][p], C2 = s_C[2][p];
-      const float G0 = s_G[0][p], G1 = s_G[1][p], G2 = s_G[2][p];
+      // colour the deeper entries of the chunk add (exclusive scan: the lane below's sum)
+      const float x0 = __shfl_up(b.z * w, 1, 64), x1 = __shfl_up(b.w * w, 1, 64), x2 = __shfl_up(c2 * w, 1, 64);
+      const float k0 = wave_scan_add(lane ? x0 : 0.f), k1 = wave_scan_add(lane ? x1 : 0.f);
+      const float k2 = wave_scan_add(lane ? x2 : 0.f);
+      const float S0 = s_S[0][p] + k0, S1 = s_S[1][p] + k1, S2 = s_S[2][p] + k2;
       if (alpha > 0.0f) {
+        const float G0 = s_G[0][p], G1 = s_G[1][p], G2 = s_G[2][p];
         const float iom = __builtin_amdgcn_rcpf(oma);
-        const float S0 = s_P[0][p] - (C0 + k0), S1 = s_P[1][p] - (C1 + k1), S2 = s_P[2][p] - (C2 + k2);
         const float dalpha = G0 * (T * b.z - S0 * iom) + G1 * (T * b.w - S1 * iom) + G2 * (T * c2 - S2 * iom);
         acc[6] += w * G0;
         acc[7] += w * G1;
@@ -175,12 +178,12 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
           acc[5] += dalpha * ex;
         }
       }
-      // carry the pixel state to the next chunk (lane 63 holds the chunk totals)
+      // carry the pixel state to the previous chunk (lane 63 holds the front entry)
       if (lane == 63) {
-        s_T[p] = T0 * Tin;
-        s_C[0][p] = C0 + k0;
-        s_C[1][p] = C1 + k1;
-        s_C[2][p] = C2 + k2;
+        s_T[p] = T;
+        s_S[0][p] = S0 + b.z * w;
+        s_S[1][p] = S1 + b.w * w;
+        s_S[2][p] = S2 + c2 * w;
       }
     }
     if (live) {
@@ -208,6 +211,23 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
     }
   }
   if (V.dl_dexp) {
+    // dL/dA = sum g pre^T, dL/db = sum g, with pre the colour behind the first chunk
+    __syncthreads();
+    float e[12];
+#pragma unroll
+    for (int f = 0; f < 12; ++f) e[f] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = lane + 64 * q;
+      const float p0 = s_S[0][p], p1 = s_S[1][p], p2 = s_S[2][p];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        e[4 * r + 0] += gl[q][r] * p0;
+        e[4 * r + 1] += gl[q][r] * p1;
+        e[4 * r + 2] += gl[q][r] * p2;
+        e[4 * r + 3] += gl[q][r];
+      }
+    }
 #pragma unroll
     for (int f = 0; f < 12; ++f) e[f] = wave_sum_all(e[f]);
     if (lane < 12) {

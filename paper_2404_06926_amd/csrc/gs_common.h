@@ -37,7 +37,6 @@ struct ViewDev {
   float* out_opac;          // H x W opacity map (Eq. 7) or nullptr
   const float* dl_ddepth;   // H x W (backward, may be nullptr)
   const float* dl_dopac;    // H x W (backward, may be nullptr)
-  float* out_pre;           // 3 x H x W pre-exposure colour (kept for the per-Gaussian backward) or nullptr
 };
 
 struct ViewsArg {

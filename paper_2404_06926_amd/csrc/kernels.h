@@ -60,19 +60,42 @@ hipError_t tile_ranges(const uint32_t* tiles, const uint32_t* n_dev, int64_t cap
                        hipStream_t s);
 
 // blending (blend.hip)
+// Long tile lists are split into chunks that separate workgroups blend: a tile whose list
+// is longer than `balance` times the mean list and than the chunk length L = max(min_len,
+// ceil(instances / par)) (rounded up to a multiple of 64) is cut into ceil(n / L) chunks
+// of near-equal length.
+// With that L at most par tiles split, the chunks after the first number at most par and
+// the chunks of all split tiles at most 2 par, which sizes every buffer below
+// independently of the scene.
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr int kSplitFields = 7;   // per chunk and pixel: see blend.hip
+struct SplitArg {
+  uint32_t* tile_slot;      // per tile: first state slot of a split tile, kNoSlot otherwise
+  uint2* extra;             // (tile, chunk) of every chunk >= 1 of a split tile, [0, counts[0])
+  uint32_t* counts;         // [0] extra chunks, [1] slots taken; zero before split_items
+  const uint32_t* n_inst;   // instance count of the render
+  float* state;             // kSplitFields x 256 floats per slot (2 par slots)
+  int32_t par;              // 0: no tile is split
+  int32_t min_len;
+  float balance;
+};
+hipError_t split_items(const uint2* ranges, int32_t n_tiles, const SplitArg& sp, hipStream_t s);
+
 // vals: emission index of each instance in blend order; emit_g: Gaussian of each emission index.
 // px: pixels per lane (1, 2 or 4), see blend.hip.
 hipError_t blend_forward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
-                         const uint32_t* emit_g, const uint2* ranges, int px, hipStream_t s);
+                         const uint32_t* emit_g, const uint2* ranges, const SplitArg& sp, int px,
+                         hipStream_t s);
 // Gradients of (mean2d, conic, opacity, colour, depth) per (view, Gaussian): with inst_grad == nullptr
 // they are added to g2d with wave-reduced atomics; otherwise every instance's gradient is
 // written to inst_grad[emission index] (12 floats, fixed-order reduction, deterministic).
+// sp: the split of the render whose lists and saved state this backward uses.
 hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                           const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
-                          float* exp_part, int px, hipStream_t s);
+                          float* exp_part, const SplitArg& sp, int px, hipStream_t s);
 
-// Per-Gaussian form of blend_backward (blend_pg.hip): needs the pre-exposure colour that
-// the forward saved in out_pre; colour and exposure gradients only (no depth / opacity maps).
+// Per-Gaussian form of blend_backward (blend_pg.hip): colour and exposure gradients only
+// (no depth / opacity maps).
 hipError_t blend_backward_per_gaussian(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                                        const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
                                        float* exp_part, hipStream_t s);

@@ -99,6 +99,7 @@ _SIGS = {
     "gs_set_instance_policy": (_I32, [_P, _I32, _I64]),
     "gs_check_overflow": (_I32, [_P, _P, ctypes.POINTER(_I32)]),
     "gs_set_blend_config": (_I32, [_P, _I32, _I32]),
+    "gs_set_tile_split": (_I32, [_P, _I32, _I32, _F]),
     "gs_set_backward_mode": (_I32, [_P, _I32]),
     "gs_set_stage_timing": (_I32, [_P, _I32]),
     "gs_set_deterministic": (_I32, [_P, _I32]),
@@ -480,6 +481,12 @@ class GaussianMap:
     def set_blend_config(self, fwd_px_per_lane: int, bwd_px_per_lane: int):
         """Pixels per lane (1, 2 or 4) of the forward and backward blend kernels."""
         _check(lib().gs_set_blend_config(self.handle, int(fwd_px_per_lane), int(bwd_px_per_lane)))
+
+    def set_tile_split(self, parallel: int = 4096, min_chunk: int = 128, balance: float = 1.25):
+        """Blend tiles whose lists exceed `balance` times the mean list and max(min_chunk,
+        instances / parallel) entries in chunks on separate workgroups; parallel = 0
+        keeps every tile in one workgroup."""
+        _check(lib().gs_set_tile_split(self.handle, int(parallel), int(min_chunk), float(balance)))
 
     def set_stage_timing(self, enable: bool):
         _check(lib().gs_set_stage_timing(self.handle, 1 if enable else 0))

@@ -57,6 +57,13 @@ def case(name):
         cams[1].exposure = scenes.random_exposure(9)
         cams[2].t = np.array([-0.3, 0.0, -0.5], np.float32)
         return params, 2, cams
+    if name == "dense":    # long lists of opaque Gaussians: most pixels stop (T < 1e-4) mid-list
+        cam = scenes.pinhole(64, 48, 50.0)
+        cam.exposure = scenes.random_exposure(4242)
+        cam.bg = np.array([0.2, 0.1, 0.3], np.float32)
+        params = scenes.frustum_gaussians(8000, 1, cam, seed=4242, log_scale_mean=-2.0)
+        params[:, 10] += 2.0
+        return params, 1, [cam]
     raise KeyError(name)
 
 

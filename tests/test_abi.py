@@ -56,6 +56,7 @@ def test_defaults_and_validation_without_gpu(L):
     assert L.gs_render_backward(None, 1, None, None, None, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_adam_step(None, 0, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_loss(None, None, None, 4, 4, 0.2, None, None, None) == gslic.GS_ERR_INVALID
+    assert L.gs_set_tile_split(None, 4096, 128, 2.0) == gslic.GS_ERR_INVALID
     assert L.gs_destroy_map(None) == gslic.GS_OK
 
 

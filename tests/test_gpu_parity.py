@@ -10,13 +10,18 @@ from gpu_common import (IMG_TOL, TIE_ALPHA, TIE_T, case, exposures, gpu_map, gra
 from paper_2404_06926_amd import gslic, scenes
 
 pytestmark = pytest.mark.gpu
-CASES = ["c1", "c3a", "ragged", "multi"]
+CASES = ["c1", "c3a", "ragged", "multi", "dense"]
+# long-list split (parallel, min_chunk, balance): None keeps the default, (0, ...) blends
+# every tile whole, (65536, 64, 0) cuts every list longer than 64 entries into chunks of 64
+SPLITS = [None, (0, 256, 2.0), (65536, 64, 0.0)]
 
 
-def _run_gpu(params, deg, cams, px=1, det=False):
+def _run_gpu(params, deg, cams, px=1, det=False, split=None):
     m = gpu_map(params, deg)
     m.set_blend_config(px, px)
     m.set_deterministic(det)
+    if split is not None:
+        m.set_tile_split(*split)
     frames = m.render(cams, exposures(cams))  # the map keeps the exposures of its last render
     torch_mod().cuda.synchronize()
     return m, frames
@@ -77,9 +82,20 @@ def test_projection_keys_and_sort_bit_exact(name):
 @pytest.mark.parametrize("px", [1, 2, 4])
 @pytest.mark.parametrize("name", CASES)
 def test_render_matches_oracle(name, px):
+    _check_render(name, px, None)
+
+
+@pytest.mark.parametrize("split", SPLITS[1:])
+@pytest.mark.parametrize("name,px", [(n, 1) for n in CASES] + [("dense", 2), ("multi", 4)])
+def test_split_render_matches_oracle(name, px, split):
+    # chunks of a long list blended by separate workgroups and composited in depth order
+    _check_render(name, px, split)
+
+
+def _check_render(name, px, split):
     params, deg, cams = case(name)
-    print(f"case {name} px {px}", flush=True)
-    m, frames = _run_gpu(params, deg, cams, px=px)
+    print(f"case {name} px {px} split {split}", flush=True)
+    m, frames = _run_gpu(params, deg, cams, px=px, split=split)
     views, projs, bins, rend = _oracle(name)
     for f, r in zip(frames, rend):
         ok = r["tie"] == 0
@@ -97,20 +113,35 @@ def test_backward_matches_oracle_adjoint(name, px, det):
     _check_backward(name, px, det, mode=0)
 
 
+@pytest.mark.parametrize("split", SPLITS[1:])
+@pytest.mark.parametrize("name,px,det", [(n, 2, False) for n in CASES] + [("dense", 1, True), ("multi", 4, True),
+                                                                          ("dense", 4, False)])
+def test_split_backward_matches_oracle_adjoint(name, px, det, split):
+    # every chunk walks its entries in reverse from the state the forward left after it
+    _check_backward(name, px, det, mode=0, split=split)
+
+
 @pytest.mark.parametrize("name,det", [(n, False) for n in CASES] + [("c3a", True), ("multi", True)])
 def test_per_gaussian_backward_matches_oracle_adjoint(name, det):
     # lanes own list entries and walk pixels (prefix products / sums across lanes)
     _check_backward(name, 1, det, mode=1)
 
 
-def _check_backward(name, px, det, mode):
+def test_per_gaussian_backward_after_a_split_render():
+    # the per-Gaussian backward reads only the pixel outputs, which the split blend writes
+    _check_backward("dense", 1, False, mode=1, split=(65536, 64, 0.0))
+
+
+def _check_backward(name, px, det, mode, split=None):
     torch = torch_mod()
     params, deg, cams = case(name)
-    print(f"case {name} px {px} deterministic {det} mode {mode}", flush=True)
+    print(f"case {name} px {px} deterministic {det} mode {mode} split {split}", flush=True)
     m = gpu_map(params, deg)
     m.set_blend_config(px, px)
     m.set_deterministic(det)
     m.set_backward_mode(mode)
+    if split is not None:
+        m.set_tile_split(*split)
     frames = m.render(cams, exposures(cams))
     torch.cuda.synchronize()
     rng = np.random.default_rng(11)
@@ -160,17 +191,25 @@ def test_depth_and_opacity_maps_match_oracle(name, px):
         assert torch_mod().equal(f.rgb, fp.rgb)
 
 
-@pytest.mark.parametrize("name,px,det", [("c3a", 1, False), ("multi", 2, False), ("ragged", 4, False),
-                                         ("c3a", 2, True), ("multi", 4, True)])
-def test_backward_with_map_gradients_matches_oracle(name, px, det):
+FORCED = (65536, 64, 0.0)
+
+
+@pytest.mark.parametrize("name,px,det,split", [("c3a", 1, False, None), ("multi", 2, False, None),
+                                               ("ragged", 4, False, None), ("c3a", 2, True, None),
+                                               ("multi", 4, True, None), ("dense", 2, False, None),
+                                               ("dense", 2, False, FORCED), ("multi", 1, True, FORCED),
+                                               ("dense", 4, True, FORCED)])
+def test_backward_with_map_gradients_matches_oracle(name, px, det, split):
     # dL/dD and dL/dO (Eq. 6-7) on top of dL/dout: parameter gradients against the oracle's
     # adjoint, to the same bar as the colour-only backward.
     torch = torch_mod()
     params, deg, cams = case(name)
-    print(f"case {name} px {px} deterministic {det}", flush=True)
+    print(f"case {name} px {px} deterministic {det} split {split}", flush=True)
     m = gpu_map(params, deg)
     m.set_blend_config(px, px)
     m.set_deterministic(det)
+    if split is not None:
+        m.set_tile_split(*split)
     m.render(cams, exposures(cams), depth=True, opacity=True)
     rng = np.random.default_rng(12)
     gouts = [rng.normal(size=(3, c.height, c.width)) for c in cams]
@@ -255,6 +294,9 @@ def test_batched_equals_per_view_launches():
     torch = torch_mod()
     params, deg, cams = case("multi")
     m = gpu_map(params, deg)
+    # the long-list split depends on the batch's mean list length: keep every tile whole so
+    # that the same lists are blended in the same order
+    m.set_tile_split(0, 256, 2.0)
     ex = exposures(cams)
     batched = m.render(cams, ex)
     rng = np.random.default_rng(5)

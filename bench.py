@@ -339,7 +339,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--repeats", type=int, default=1, help="timed regions of --steps steps; the median is reported")
-    ap.add_argument("--workload", choices=["headline", "batch8", "stream", "multi"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "outdoor", "batch8", "stream", "multi"], default="headline")
     ap.add_argument("--duration", type=float, default=None,
                     help="serving workloads: seconds of keyframe arrivals (stream 5, multi 2)")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="multi: HBM admission budget")
@@ -384,6 +384,12 @@ def main():
     if args.workload == "batch8":
         args.sh = 0
         cams, params, target_params = batch_workload(args.n)
+    elif args.workload == "outdoor":
+        from paper_2404_06926_amd import scenes
+        params, cam = scenes.outdoor_scene(2000, deg=3)
+        target_params = scenes.jitter_means(params, 0.05, 2000)
+        cams = [cam]
+        args.n, args.sh = params.shape[0], 3
     else:
         cams, params, target_params = headline_workload(args.n, args.sh, args.width, args.height)
     log(f"workload {args.workload}: n={args.n} sh={args.sh} views={[(c.width, c.height) for c in cams]}")
@@ -546,7 +552,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"{args.n} Gaussians, SH{args.sh}, "
+        "config": {"workload": (("outdoor street (LiDAR-shaped + 20k sky), " if args.workload == "outdoor" else "")
+                                + f"{args.n} Gaussians, SH{args.sh}, "
                                 + ", ".join(f"{c.width}x{c.height}" for c in cams)
                                 + f" per step, loss 0.8 L1 + 0.2 D-SSIM, sparse Adam"),
                    "n_gaussians": args.n, "sh_degree": args.sh, "views_per_step": V,
@@ -583,6 +590,8 @@ def main():
         result["batched_over_plain"] = ms_plain / ms
         result["batched_eager_over_plain"] = ms_plain / ms_eager
         result["metric"] = "mapping iters/s, 8 uneven keyframes per step (batched vs one view per launch)"
+    if args.workload == "outdoor":
+        result["metric"] = "mapping iters/s (fwd+bwd+Adam), outdoor single view, 500k Gaussians 1280x720"
 
     if graph is not None:
         graph.close()

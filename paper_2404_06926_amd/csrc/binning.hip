@@ -46,97 +46,132 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   return wbase + incl - x;
 }
 
-// Pass 1: per-block local exclusive scan and block sums; element k is in[idx[k]] when idx
-// is given (a gather in another order), else in[k].
+// Exclusive scan over a fixed grid of at most kScanGrid blocks, each owning a contiguous
+// run of 2048-element tiles (every block at least one): the up pass sums each block's run,
+// the down pass takes the sum of the earlier blocks' runs as its start and scans its tiles
+// in order. Element k is in[idx[k]] when idx is given (a gather in another order), else
+// in[k]; in may equal out.
+constexpr int kScanGrid = 1024;
+
+static int scan_grid(int64_t n) {
+  return (int)std::min<int64_t>(kScanGrid, std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile));
+}
+
+__device__ __forceinline__ void scan_share(int64_t n, int G, int64_t& t0, int64_t& t1) {
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  t0 = (int64_t)blockIdx.x * nt / G;
+  t1 = (int64_t)(blockIdx.x + 1) * nt / G;
+}
+
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_local(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, uint32_t* __restrict__ out,
-             uint32_t* __restrict__ sums, int64_t n) {
+k_scan_up(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, int64_t n, uint32_t* __restrict__ sums,
+          int G) {
   __shared__ uint32_t s_warp[kScanBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
+  int64_t t0, t1;
+  scan_share(n, G, t0, t1);
   uint32_t tsum = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = 0u;
-    if (base + k < n) v[k] = idx ? in[idx[base + k]] : in[base + k];
-    tsum += v[k];
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < n) tsum += idx ? in[idx[base + k]] : in[base + k];
   }
   uint32_t total;
-  uint32_t run = block_exclusive_scan(tsum, s_warp, total);
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
-  }
+  block_exclusive_scan(tsum, s_warp, total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// Pass 3: add the scanned block sums.
+// total (optional): the sum of all elements, written by the last block.
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ sums, int64_t n) {
-  const uint32_t add = sums[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  for (int k = threadIdx.x; k < kScanTile; k += kScanBlock)
-    if (base + k < n) out[base + k] += add;
-}
-
-// total = last offset + last count
-__global__ void k_scan_total(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx,
-                             const uint32_t* __restrict__ out, int64_t n, uint32_t* __restrict__ total) {
-  total[0] = n > 0 ? out[n - 1] + (idx ? in[idx[n - 1]] : in[n - 1]) : 0u;
-}
-
-int64_t scan_temp_elems(int64_t n) {
-  int64_t t = 0;
-  while (n > 1) {
-    n = (n + kScanTile - 1) / kScanTile;
-    t += n;
+k_scan_down(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, uint32_t* __restrict__ out, int64_t n,
+            const uint32_t* __restrict__ sums, int G, uint32_t* __restrict__ total_out) {
+  __shared__ uint32_t s_warp[kScanBlock / 64];
+  // start of this block's run: the sums of the blocks before it (G <= 1024: 4 per thread)
+  uint32_t before = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = (int)threadIdx.x * 4 + k;
+    if (b < (int)blockIdx.x) before += sums[b];
   }
-  return t + 1;
+  uint32_t carry;
+  block_exclusive_scan(before, s_warp, carry);
+  int64_t t0, t1;
+  scan_share(n, G, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = 0u;
+      if (base + k < n) v[k] = idx ? in[idx[base + k]] : in[base + k];
+      tsum += v[k];
+    }
+    uint32_t tile_total;
+    uint32_t run = carry + block_exclusive_scan(tsum, s_warp, tile_total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+    carry += tile_total;
+  }
+  if (total_out && blockIdx.x == (unsigned)(G - 1) && threadIdx.x == 0) total_out[0] = carry;
 }
+
+int64_t scan_temp_elems(int64_t n) { return scan_grid(n) + 1; }
 
 static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* temp,
-                            hipStream_t s) {
+                            uint32_t* total, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  uint32_t* sums = temp;
-  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, idx, out, sums, n);
-  if (nb > 1) {
-    hipError_t e = scan_impl(sums, nullptr, sums, nb, temp + nb, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanBlock), 0, s, out, sums, n);
-  }
+  const int G = scan_grid(n);
+  hipLaunchKernelGGL(k_scan_up, dim3(G), dim3(kScanBlock), 0, s, in, idx, n, temp, G);
+  hipLaunchKernelGGL(k_scan_down, dim3(G), dim3(kScanBlock), 0, s, in, idx, out, n, temp, G, total);
   return hipGetLastError();
 }
 
 // Exclusive scan of n u32 values (in may equal out); temp holds scan_temp_elems(n).
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s) {
-  return scan_impl(in, nullptr, out, n, temp, s);
+  return scan_impl(in, nullptr, out, n, temp, nullptr, s);
 }
 
 // offsets[k] = sum of counts[order[j]] for j < k; total = sum of all.
 hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* offsets, int64_t n,
                        uint32_t* temp, uint32_t* total, hipStream_t s) {
-  hipError_t e = scan_impl(counts, order, offsets, n, temp, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, counts, order, offsets, n, total);
-  return hipGetLastError();
+  return scan_impl(counts, order, offsets, n, temp, total, s);
 }
 
 // ------------------------------------------------------------------ radix sort
-// Stable LSD sort with 8-bit digits. Each pass: per-block digit histograms
-// (digit-major), an exclusive scan of the histograms, then a stable scatter in which
-// every wave ranks its keys in order with ballot-based peer masks.
+// Stable LSD sort with 8-bit digits over a fixed grid of G blocks (even share: block g
+// owns a contiguous run of 2048-key tiles, whatever the key count). Each pass:
+//   up:      per-block digit counts (digit-major, counts[d * G + g]);
+//   rowscan: one block per digit scans its row over the G blocks and writes the digit
+//            total;
+//   down:    each block takes the exclusive scan of the 256 digit totals plus its row
+//            prefix as the global start of each digit, then walks its tiles in order:
+//            every wave ranks its keys with ballot-based peer masks, the tile is placed
+//            in LDS in (digit, original order) order and written out by consecutive lanes
+//            (each digit's run goes to consecutive addresses), and the digit starts
+//            advance by the tile's counts.
+// Three launches per pass and a count matrix of 256 x G entries, independent of n.
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 8;                       // keys per thread (16 measured slower: too few
-constexpr int kSortTile = kSortBlock * kSortItems;  // blocks for the 1M-key depth sort); 2048 per block
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 2048 keys per tile
 constexpr int kWaves = kSortBlock / 64;
+constexpr int kSortGrid = 1024;                     // blocks of the up and down sweeps
 
 // Elements to process: all of them when they fit, none after an overflow (the render is
 // then empty and the overflow flag tells the host to re-plan).
 __device__ __forceinline__ uint32_t sort_count(const uint32_t* n_dev, int64_t cap) {
   const uint32_t n = n_dev[0];
   return (int64_t)n <= cap ? n : 0u;
+}
+
+// Tiles [t0, t1) of block g among G for n keys.
+__device__ __forceinline__ void sort_share(uint32_t n, int G, int64_t& t0, int64_t& t1) {
+  const int64_t nt = ((int64_t)n + kSortTile - 1) / kSortTile;
+  t0 = (int64_t)blockIdx.x * nt / G;
+  t1 = (int64_t)(blockIdx.x + 1) * nt / G;
 }
 
 // Lanes of the wave whose digit equals this lane's (8 ballots), restricted to `ok` lanes.
@@ -152,110 +187,149 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool ok) {
 
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock)
-k_radix_hist(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
-             uint32_t* __restrict__ hist, int nblocks) {
+k_radix_up(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
+           uint32_t mask, uint32_t* __restrict__ counts, int G) {
   __shared__ uint32_t s_h[kWaves][256];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int d = lane; d < 256; d += 64) s_h[wid][d] = 0;
   __syncthreads();
   const uint32_t n = sort_count(n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wid * (64 * kSortItems);
+  int64_t t0, t1;
+  sort_share(n, G, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * kSortTile + (int64_t)wid * (64 * kSortItems);
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    const int64_t idx = base + r * 64 + lane;
-    const bool ok = idx < n;
-    const uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
-    // one LDS add per distinct digit of the wave
-    const uint64_t peers = digit_peers(d, ok);
-    if (ok && lane == __ffsll((long long)peers) - 1) s_h[wid][d] += (uint32_t)__popcll(peers);
+    for (int r = 0; r < kSortItems; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      const bool ok = idx < n;
+      const uint32_t d = ok ? (uint32_t)(keys[idx] >> shift) & mask : 0u;
+      // one LDS add per distinct digit of the wave
+      const uint64_t peers = digit_peers(d, ok);
+      if (ok && lane == __ffsll((long long)peers) - 1) s_h[wid][d] += (uint32_t)__popcll(peers);
+    }
   }
   __syncthreads();
   const int d = threadIdx.x;
-  hist[(int64_t)d * nblocks + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
+  counts[(int64_t)d * G + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
 }
 
-// The block's keys are first placed in LDS in (digit, original order) order, then written
-// out by consecutive lanes, so each digit's run goes to consecutive global addresses.
+// Block d: exclusive scan of row d (G <= 1024 entries) in place, its total to totals[d].
+__global__ void __launch_bounds__(256)
+k_radix_rowscan(uint32_t* __restrict__ counts, int G, uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_warp[4];
+  uint32_t* row = counts + (int64_t)blockIdx.x * G;
+  uint32_t v[4], sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = (int)threadIdx.x * 4 + k;
+    v[k] = i < G ? row[i] : 0u;
+    sum += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(sum, s_warp, total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = (int)threadIdx.x * 4 + k;
+    if (i < G) row[i] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock)
-k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-                uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t cap, int shift,
-                const uint32_t* __restrict__ hist_scan, int nblocks) {
+k_radix_down(const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
+             uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t cap, int shift, uint32_t mask,
+             const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, int G) {
   __shared__ uint32_t s_cnt[kWaves][256];   // keys per (wave, digit), then the wave's offset
-  __shared__ uint32_t s_start[256];         // first LDS slot of each digit
-  __shared__ uint32_t s_gbase[256];         // global position of the block's first key of each digit
+  __shared__ uint32_t s_start[256];         // first LDS slot of each digit in the tile
+  __shared__ uint32_t s_tot[256];           // keys of each digit in the tile
+  __shared__ uint32_t s_base[256];          // global position of the block's next key of each digit
   __shared__ uint32_t s_warp[kWaves];
   __shared__ K s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int d = lane; d < 256; d += 64) s_cnt[wid][d] = 0;
-  __syncthreads();
   const uint32_t n = sort_count(n_dev, cap);
-  const int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
-  const int64_t base = blk0 + (int64_t)wid * (64 * kSortItems);
-  K key[kSortItems];
-  uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    const int64_t idx = base + r * 64 + lane;
-    const bool ok = idx < n;
-    key[r] = ok ? kin[idx] : (K)0;
-    val[r] = ok ? vin[idx] : 0u;
-    const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-    dig[r] = d;
-    const uint64_t peers = digit_peers(d, ok);
-    uint32_t prev = 0;
-    const int leader = peers ? (__ffsll((long long)peers) - 1) : 0;
-    if (ok && lane == leader) {
-      prev = s_cnt[wid][d];
-      s_cnt[wid][d] = prev + (uint32_t)__popcll(peers);
-    }
-    prev = __shfl(prev, leader, 64);
-    rank[r] = prev + (uint32_t)__popcll(peers & lt);
-  }
-  __syncthreads();
-  // digit totals of the block, their exclusive scan (LDS start of each digit) and each
-  // wave's offset inside its digit run
+  int64_t t0, t1;
+  sort_share(n, G, t0, t1);
+  if (t0 >= t1) return;
   {
     const int d = threadIdx.x;
-    uint32_t tot = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = s_cnt[w][d];
-      s_cnt[w][d] = tot;
-      tot += c;
-    }
     uint32_t all;
-    const uint32_t start = block_exclusive_scan(tot, s_warp, all);
-    s_start[d] = start;
-    s_gbase[d] = hist_scan[(int64_t)d * nblocks + blockIdx.x];
+    const uint32_t start = block_exclusive_scan(totals[d], s_warp, all);
+    s_base[d] = start + counts[(int64_t)d * G + blockIdx.x];
   }
-  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t t = t0; t < t1; ++t) {
+    for (int d = lane; d < 256; d += 64) s_cnt[wid][d] = 0;
+    __syncthreads();
+    const int64_t blk0 = t * kSortTile;
+    const int64_t base = blk0 + (int64_t)wid * (64 * kSortItems);
+    K key[kSortItems];
+    uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
-    const int64_t idx = base + r * 64 + lane;
-    if (idx < n) {
-      const uint32_t slot = s_start[dig[r]] + s_cnt[wid][dig[r]] + rank[r];
-      s_key[slot] = key[r];
-      s_val[slot] = val[r];
+    for (int r = 0; r < kSortItems; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      const bool ok = idx < n;
+      key[r] = ok ? kin[idx] : (K)0;
+      val[r] = ok ? vin[idx] : 0u;
+      const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+      dig[r] = d;
+      const uint64_t peers = digit_peers(d, ok);
+      uint32_t prev = 0;
+      const int leader = peers ? (__ffsll((long long)peers) - 1) : 0;
+      if (ok && lane == leader) {
+        prev = s_cnt[wid][d];
+        s_cnt[wid][d] = prev + (uint32_t)__popcll(peers);
+      }
+      prev = __shfl(prev, leader, 64);
+      rank[r] = prev + (uint32_t)__popcll(peers & lt);
     }
-  }
-  __syncthreads();
-  const int64_t nblk = min((int64_t)kSortTile, (int64_t)n - blk0);
-  for (int t = threadIdx.x; t < nblk; t += kSortBlock) {
-    const K k = s_key[t];
-    const uint32_t d = (uint32_t)(k >> shift) & 255u;
-    const uint32_t pos = s_gbase[d] + ((uint32_t)t - s_start[d]);
-    kout[pos] = k;
-    vout[pos] = s_val[t];
+    __syncthreads();
+    // digit totals of the tile, their exclusive scan (LDS start of each digit) and each
+    // wave's offset inside its digit run
+    {
+      const int d = threadIdx.x;
+      uint32_t tot = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = s_cnt[w][d];
+        s_cnt[w][d] = tot;
+        tot += c;
+      }
+      uint32_t all;
+      s_start[d] = block_exclusive_scan(tot, s_warp, all);
+      s_tot[d] = tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const int64_t idx = base + r * 64 + lane;
+      if (idx < n) {
+        const uint32_t slot = s_start[dig[r]] + s_cnt[wid][dig[r]] + rank[r];
+        s_key[slot] = key[r];
+        s_val[slot] = val[r];
+      }
+    }
+    __syncthreads();
+    const int64_t nblk = min((int64_t)kSortTile, (int64_t)n - blk0);
+    for (int i = threadIdx.x; i < nblk; i += kSortBlock) {
+      const K k = s_key[i];
+      const uint32_t d = (uint32_t)(k >> shift) & mask;
+      const uint32_t pos = s_base[d] + ((uint32_t)i - s_start[d]);
+      kout[pos] = k;
+      vout[pos] = s_val[i];
+    }
+    __syncthreads();
+    s_base[threadIdx.x] += s_tot[threadIdx.x];
   }
 }
 
-int64_t sort_temp_elems(int64_t cap) {
-  const int64_t nb = (cap + kSortTile - 1) / kSortTile;
-  return 256 * nb + scan_temp_elems(256 * nb);
+static int sort_grid(int64_t cap) {
+  return (int)std::min<int64_t>(kSortGrid, std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile));
 }
+
+int64_t sort_temp_elems(int64_t cap) { return 256 * (int64_t)sort_grid(cap) + 256; }
 
 // Sorts (keys[0], vals[0]) on bits [0, nbits) using (keys[1], vals[1]) as the double buffer;
 // *which receives the index of the buffer that holds the result.
@@ -263,17 +337,23 @@ hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* 
                           uint32_t* temp, int* which, hipStream_t s) {
   *which = 0;
   if (cap <= 0) return hipSuccess;
-  const int nb = (int)((cap + kSortTile - 1) / kSortTile);
-  uint32_t* hist = temp;
-  uint32_t* stemp = temp + (int64_t)256 * nb;
+  const int G = sort_grid(cap);
+  uint32_t* counts = temp;
+  uint32_t* totals = temp + (int64_t)256 * G;
+  // as many passes as 8-bit digits need, the bits spread evenly over them: fewer digit
+  // values per pass give longer runs of equal digits in each tile, so the scatter writes
+  // longer contiguous pieces (12-bit tile ids: two 6-bit passes rather than 8 + 4)
+  const int passes = (nbits + 7) / 8;
+  const int width = passes ? (nbits + passes - 1) / passes : 8;
   int cur = 0;
-  for (int shift = 0; shift < nbits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist<uint32_t>, dim3(nb), dim3(kSortBlock), 0, s, keys[cur], n_dev, cap, shift,
-                       hist, nb);
-    hipError_t e = exclusive_scan(hist, hist, (int64_t)256 * nb, stemp, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter<uint32_t>, dim3(nb), dim3(kSortBlock), 0, s, keys[cur], vals[cur],
-                       keys[cur ^ 1], vals[cur ^ 1], n_dev, cap, shift, hist, nb);
+  for (int shift = 0; shift < nbits; shift += width) {
+    const int w = std::min(width, nbits - shift);
+    const uint32_t mask = (w >= 32) ? 0xFFFFFFFFu : ((1u << w) - 1u);
+    hipLaunchKernelGGL(k_radix_up<uint32_t>, dim3(G), dim3(kSortBlock), 0, s, keys[cur], n_dev, cap, shift, mask,
+                       counts, G);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, counts, G, totals);
+    hipLaunchKernelGGL(k_radix_down<uint32_t>, dim3(G), dim3(kSortBlock), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+                       vals[cur ^ 1], n_dev, cap, shift, mask, counts, totals, G);
     cur ^= 1;
   }
   *which = cur;

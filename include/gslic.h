@@ -46,7 +46,7 @@ enum {
   GS_ERR_INVALID = -1,       /* bad argument; nothing enqueued */
   GS_ERR_OOM = -2,           /* an allocation failed; map unchanged */
   GS_ERR_HIP = -3,           /* a HIP runtime call failed */
-  GS_ERR_CAPACITY = -4,      /* a fixed capacity (views per call, instances) is exceeded */
+  GS_ERR_CAPACITY = -4,      /* a fixed capacity (views per call, instances, 2^30 Gaussians) is exceeded */
   GS_ERR_STATE = -6,         /* call order violated (e.g. backward without a render) */
   GS_ERR_UNIMPLEMENTED = -7
 };
@@ -120,7 +120,7 @@ gs_status gs_destroy_map(gs_map* map);
  * Inputs are device arrays in rows: means n x 3, log_scales n x 3, quats n x 4 (w,x,y,z),
  * opacity_logits n, sh n x K x 3 (K = (deg+1)^2, coefficient-major). Gradients and Adam
  * moments of the new rows start at zero. Capacity doubles as needed (device copy on
- * `stream`). n = 0 is a no-op. */
+ * `stream`), up to 2^30 Gaussians (GS_ERR_CAPACITY beyond). n = 0 is a no-op. */
 gs_status gs_add_gaussians(gs_map* map, int64_t n, const float* means, const float* log_scales,
                            const float* quats, const float* opacity_logits, const float* sh,
                            void* stream);

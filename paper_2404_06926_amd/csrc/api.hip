@@ -176,7 +176,10 @@ float* grads_of(gs_map* m) { return m->buf + (int64_t)m->F * m->cap; }
 
 gs_status grow_capacity(gs_map* m, int64_t need, hipStream_t s) {
   if (need <= m->cap) return GS_OK;
-  int64_t nc = std::max<int64_t>(need, std::max<int64_t>(1024, 2 * m->cap));
+  // kernels address a row of a parameter plane with a 32-bit byte offset
+  constexpr int64_t kMaxCapacity = int64_t(1) << 30;
+  if (need > kMaxCapacity) return fail(GS_ERR_CAPACITY, "more than 2^30 Gaussians in one map");
+  int64_t nc = std::min<int64_t>(kMaxCapacity, std::max<int64_t>(need, std::max<int64_t>(1024, 2 * m->cap)));
   const size_t fbytes = (size_t)4 * m->F * nc * sizeof(float);
   const size_t vbytes = (size_t)((nc + 3) / 4) * 4;
   float* nb = (float*)dev_alloc(m, fbytes, s);

@@ -148,8 +148,59 @@ __device__ __forceinline__ void pair_grad(size_t vi, const uint32_t* __restrict_
   }
 }
 
+// Element of one parameter plane at the row's 32-bit byte offset (capacity < 2^30 rows).
+__device__ __forceinline__ float& plane_at(float* plane, uint32_t byte_off) {
+  return *(float*)((char*)plane + byte_off);
+}
+
+// One Adam update of NB planes f0 + stride j of row i, parameter values p[j] already
+// loaded: the moments (and any accumulated gradient) of all NB planes are loaded before
+// any store, so a lane keeps 2 NB loads in flight; each value is read and written once per
+// step and streamed past the caches.
+template <int NB>
+__device__ __forceinline__ void adam_rows(float* __restrict__ P, float* __restrict__ Mp, float* __restrict__ Vp,
+                                          float* __restrict__ Gp, int64_t cap, uint32_t lo, int f0, int stride,
+                                          const float* p, const float* g, const float* lr, const AdamArg& ad,
+                                          float bc1, float bc2) {
+  float m[NB], v[NB], acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int64_t f = (int64_t)(f0 + stride * j) * cap;
+    m[j] = __builtin_nontemporal_load(&plane_at(Mp + f, lo));
+    v[j] = __builtin_nontemporal_load(&plane_at(Vp + f, lo));
+    // what the separate path reads: 0 + gradient, plus sums of earlier backward calls
+    acc[j] = ad.grads_clean ? 0.0f : plane_at(Gp + f, lo);
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int64_t f = (int64_t)(f0 + stride * j) * cap;
+    float pp = p[j];
+    adam_update(pp, m[j], v[j], acc[j] + g[j], lr[j], ad.beta1, ad.beta2, ad.eps, bc1, bc2);
+    __builtin_nontemporal_store(pp, &plane_at(P + f, lo));
+    __builtin_nontemporal_store(m[j], &plane_at(Mp + f, lo));
+    __builtin_nontemporal_store(v[j], &plane_at(Vp + f, lo));
+    if (acc[j] != 0.0f) plane_at(Gp + f, lo) = 0.0f;
+  }
+}
+
+// The K planes f0 + 3 k of one SH channel in batches of at most kAdamBatch (bounded
+// registers).
+constexpr int kAdamBatch = 4;
+template <int K>
+__device__ __forceinline__ void adam_sh(float* __restrict__ P, float* __restrict__ Mp, float* __restrict__ Vp,
+                                        float* __restrict__ Gp, int64_t cap, uint32_t lo, int f0, const float* p,
+                                        const float* g, const float* lr, const AdamArg& ad, float bc1, float bc2) {
+  if constexpr (K <= kAdamBatch) {
+    adam_rows<K>(P, Mp, Vp, Gp, cap, lo, f0, 3, p, g, lr, ad, bc1, bc2);
+  } else {
+    adam_rows<kAdamBatch>(P, Mp, Vp, Gp, cap, lo, f0, 3, p, g, lr, ad, bc1, bc2);
+    adam_sh<K - kAdamBatch>(P, Mp, Vp, Gp, cap, lo, f0 + 3 * kAdamBatch, p + kAdamBatch, g + kAdamBatch,
+                            lr + kAdamBatch, ad, bc1, bc2);
+  }
+}
+
 template <int DEG, bool FUSED, bool MULTI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256)
 k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg va, float near_z,
               const uint32_t* __restrict__ counts, float4* __restrict__ g2d, const float4* __restrict__ inst_grad,
               const uint32_t* __restrict__ inst_off, uint8_t* __restrict__ vis, AdamArg ad) {
@@ -157,30 +208,23 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   __shared__ float s_gsh[MULTI ? 3 * K : 1][MULTI ? 256 : 1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  // gradient g of plane f: added to the gradient planes, or one Adam update of the row
-  auto emit = [&](int f, float g) {
-    const int64_t k = (int64_t)f * cap + i;
-    if (!FUSED) {
-      Gp[k] += g;
-    } else {
-      // what the separate path reads: 0 + gradient, plus sums of earlier backward calls
-      const float acc = ad.grads_clean ? 0.0f : Gp[k];
-      const float gr = acc + g;
-      if (acc != 0.0f) Gp[k] = 0.0f;
-      // each plane value is read and written once per step: stream it past the caches
-      float pp = __builtin_nontemporal_load(P + k), mm = __builtin_nontemporal_load(ad.m + k);
-      float vv = __builtin_nontemporal_load(ad.v + k);
-      adam_update(pp, mm, vv, gr, ad.lr.lr[f], ad.beta1, ad.beta2, ad.eps, ad.bc[0], ad.bc[1]);
-      __builtin_nontemporal_store(pp, P + k);
-      __builtin_nontemporal_store(mm, ad.m + k);
-      __builtin_nontemporal_store(vv, ad.v + k);
-    }
-  };
+  // non-fused: gradient g of plane f added to the gradient planes
+  const uint32_t lo = (uint32_t)i * 4u;  // byte offset of the row in every plane (cap < 2^30)
+  auto emit = [&](int f, float g) { plane_at(Gp + (int64_t)f * cap, lo) += g; };
+  auto ldp = [&](int f) { return plane_at(P + (int64_t)f * cap, lo); };
+  float* __restrict__ Mp = ad.m;
+  float* __restrict__ Vp = ad.v;
+  const float bc1 = FUSED ? ad.bc[0] : 1.0f, bc2 = FUSED ? ad.bc[1] : 1.0f;
+  // learning rates by plane (constant indices: a runtime index into the by-value table
+  // would place it in scratch memory)
+  float lr_sh[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) lr_sh[k] = ad.lr.lr[k == 0 ? 11 : 14];
   bool any = false;
   for (int v = 0; v < va.n; ++v) any |= counts[(size_t)v * N + i] > 0;
   if (!any && !(FUSED && vis[i])) return;
 
-  const float mu0 = P[i], mu1 = P[cap + i], mu2 = P[2 * cap + i];
+  const float mu0 = ldp(0), mu1 = ldp(1), mu2 = ldp(2);
   float gmu[3] = {0.f, 0.f, 0.f};
 
   // ---- phase 1: colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = normalised (mu - campos)
@@ -208,17 +252,24 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
       float raw = 0.5f;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        shc[k] = P[(int64_t)(11 + 3 * k + ch) * cap + i];
+        shc[k] = ldp(11 + 3 * k + ch);
         raw += shc[k] * Y[k];
       }
       const float gcol = raw < 0.0f ? 0.0f : g_col[ch];  // clamped channel: no gradient
-#pragma unroll 4
+      float gk[K];
+#pragma unroll
       for (int k = 0; k < K; ++k) {
         wsum[k] += gcol * shc[k];
-        if (MULTI)
-          s_gsh[3 * k + ch][threadIdx.x] += gcol * Y[k];
-        else
-          emit(11 + 3 * k + ch, gcol * Y[k]);
+        gk[k] = gcol * Y[k];
+      }
+      if (MULTI) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s_gsh[3 * k + ch][threadIdx.x] += gk[k];
+      } else if (FUSED) {
+        adam_sh<K>(P, Mp, Vp, Gp, cap, lo, 11 + ch, shc, gk, lr_sh, ad, bc1, bc2);
+      } else {
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) emit(11 + 3 * k + ch, gk[k]);
       }
     }
     if (!MULTI) sh_done = true;
@@ -231,22 +282,36 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
       gmu[2] += (gdz - dot * d2) * inv;
     }
   }
-  if (MULTI) {
-    for (int f = 0; f < 3 * K; ++f) emit(11 + f, s_gsh[f][threadIdx.x]);
-  } else if (!sh_done) {
-    // single view without a tile in this batch (fused path, marked earlier): zero local part
-    for (int f = 0; f < 3 * K; ++f) emit(11 + f, 0.0f);
+  if (MULTI || !sh_done) {
+    // several views: the summed SH gradients; a single view without a tile in this batch
+    // (fused path, row marked by an earlier backward): zero local part
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ++ch) {
+      float gk[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) gk[k] = MULTI ? s_gsh[3 * k + ch][threadIdx.x] : 0.0f;
+      if (FUSED) {
+        float pk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) pk[k] = ldp(11 + 3 * k + ch);
+        adam_sh<K>(P, Mp, Vp, Gp, cap, lo, 11 + ch, pk, gk, lr_sh, ad, bc1, bc2);
+      } else {
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) emit(11 + 3 * k + ch, gk[k]);
+      }
+    }
   }
 
   // ---- phase 2: geometry. Normalised quaternion, rotation, scales, M = R S, Sigma = M M^T
-  const float q0 = P[6 * cap + i], q1 = P[7 * cap + i], q2 = P[8 * cap + i], q3 = P[9 * cap + i];
+  const float q0 = ldp(6), q1 = ldp(7), q2 = ldp(8), q3 = ldp(9);
   const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
   const float iqn = qn > 0.f ? 1.0f / qn : 0.f;
   const float w = q0 * iqn, x = q1 * iqn, y = q2 * iqn, z = q3 * iqn;
   const float Rq[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
                        2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
                        2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
-  const float s[3] = {__expf(P[3 * cap + i]), __expf(P[4 * cap + i]), __expf(P[5 * cap + i])};
+  const float ls0 = ldp(3), ls1 = ldp(4), ls2 = ldp(5);
+  const float s[3] = {__expf(ls0), __expf(ls1), __expf(ls2)};
   float M[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -259,7 +324,8 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   Sg[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
   Sg[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
   Sg[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
-  const float op = 1.0f / (1.0f + __expf(-P[10 * cap + i]));
+  const float logit = ldp(10);
+  const float op = 1.0f / (1.0f + __expf(-logit));
   float gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   float glogit = 0.0f;
 
@@ -372,14 +438,21 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   gq[3] = 2.f * (-2.f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.f * z * gR[4] + y * gR[5] + x * gR[6] + y * gR[7]);
   const float qd = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
   const float unit[4] = {w, x, y, z};
-  emit(0, gmu[0]);
-  emit(1, gmu[1]);
-  emit(2, gmu[2]);
+  const float gg[11] = {gmu[0], gmu[1], gmu[2], gls[0], gls[1], gls[2], (gq[0] - qd * unit[0]) * iqn,
+                        (gq[1] - qd * unit[1]) * iqn, (gq[2] - qd * unit[2]) * iqn, (gq[3] - qd * unit[3]) * iqn,
+                        glogit};
+  if (FUSED) {
+    const float pg[11] = {mu0, mu1, mu2, ls0, ls1, ls2, q0, q1, q2, q3, logit};
+    float lr_geo[11];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) emit(3 + k, gls[k]);
+    for (int f = 0; f < 11; ++f) lr_geo[f] = ad.lr.lr[f];
+    adam_rows<4>(P, Mp, Vp, Gp, cap, lo, 0, 1, pg, gg, lr_geo, ad, bc1, bc2);
+    adam_rows<4>(P, Mp, Vp, Gp, cap, lo, 4, 1, pg + 4, gg + 4, lr_geo + 4, ad, bc1, bc2);
+    adam_rows<3>(P, Mp, Vp, Gp, cap, lo, 8, 1, pg + 8, gg + 8, lr_geo + 8, ad, bc1, bc2);
+  } else {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) emit(6 + k, (gq[k] - qd * unit[k]) * iqn);
-  emit(10, glogit);
+    for (int f = 0; f < 11; ++f) emit(f, gg[f]);
+  }
   vis[i] = FUSED ? 0 : 1;
 }
 

@@ -49,9 +49,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
 // Exclusive scan over a fixed grid of at most kScanGrid blocks, each owning a contiguous
 // run of 2048-element tiles (every block at least one): the up pass sums each block's run,
 // the down pass takes the sum of the earlier blocks' runs as its start and scans its tiles
-// in order. Element k is in[idx[k]] when idx is given (a gather in another order), else
-// in[k]; in may equal out.
-constexpr int kScanGrid = 1024;
+// in order. Element k is in[idx[k]] when idx is given (a gather in another order; the up
+// pass stores the gathered values in order so that the down pass reads them contiguously),
+// else in[k]; in may equal out.
+constexpr int kScanGrid = 4096;
 
 static int scan_grid(int64_t n) {
   return (int)std::min<int64_t>(kScanGrid, std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile));
@@ -65,16 +66,22 @@ __device__ __forceinline__ void scan_share(int64_t n, int G, int64_t& t0, int64_
 
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_up(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, int64_t n, uint32_t* __restrict__ sums,
-          int G) {
+          int G, uint32_t* __restrict__ gathered) {
   __shared__ uint32_t s_warp[kScanBlock / 64];
   int64_t t0, t1;
   scan_share(n, G, t0, t1);
   uint32_t tsum = 0;
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = t * kScanTile + (int64_t)threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-      if (base + k < n) tsum += idx ? in[idx[base + k]] : in[base + k];
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t e = base + (int64_t)k * kScanBlock;  // coalesced over the lanes
+      if (e < n) {
+        const uint32_t v = idx ? in[idx[e]] : in[e];
+        if (idx) gathered[e] = v;
+        tsum += v;
+      }
+    }
   }
   uint32_t total;
   block_exclusive_scan(tsum, s_warp, total);
@@ -86,11 +93,11 @@ __global__ void __launch_bounds__(kScanBlock)
 k_scan_down(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, uint32_t* __restrict__ out, int64_t n,
             const uint32_t* __restrict__ sums, int G, uint32_t* __restrict__ total_out) {
   __shared__ uint32_t s_warp[kScanBlock / 64];
-  // start of this block's run: the sums of the blocks before it (G <= 1024: 4 per thread)
+  // start of this block's run: the sums of the blocks before it (G <= 4096: 16 per thread)
   uint32_t before = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int b = (int)threadIdx.x * 4 + k;
+  for (int k = 0; k < kScanGrid / kScanBlock; ++k) {
+    const int b = (int)threadIdx.x + k * kScanBlock;
     if (b < (int)blockIdx.x) before += sums[b];
   }
   uint32_t carry;
@@ -99,34 +106,55 @@ k_scan_down(const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, u
   scan_share(n, G, t0, t1);
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const bool full = base + kScanItems <= n;  // the lane's 8 elements as two 16-B accesses
     uint32_t v[kScanItems];
     uint32_t tsum = 0;
+    if (full && !idx) {
+      const uint4 a = *(const uint4*)(in + base), b = *(const uint4*)(in + base + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      v[k] = 0u;
-      if (base + k < n) v[k] = idx ? in[idx[base + k]] : in[base + k];
-      tsum += v[k];
+      for (int k = 0; k < kScanItems; ++k) {
+        v[k] = 0u;
+        if (base + k < n) v[k] = idx ? in[idx[base + k]] : in[base + k];
+      }
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) tsum += v[k];
     uint32_t tile_total;
     uint32_t run = carry + block_exclusive_scan(tsum, s_warp, tile_total);
+    uint32_t o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-      if (base + k < n) out[base + k] = run;
+      o[k] = run;
       run += v[k];
+    }
+    if (full) {
+      *(uint4*)(out + base) = make_uint4(o[0], o[1], o[2], o[3]);
+      *(uint4*)(out + base + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) out[base + k] = o[k];
     }
     carry += tile_total;
   }
   if (total_out && blockIdx.x == (unsigned)(G - 1) && threadIdx.x == 0) total_out[0] = carry;
 }
 
-int64_t scan_temp_elems(int64_t n) { return scan_grid(n) + 1; }
+// block sums, then room for n gathered values
+int64_t scan_temp_elems(int64_t n) { return kScanGrid + n + 1; }
 
 static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* temp,
                             uint32_t* total, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int G = scan_grid(n);
-  hipLaunchKernelGGL(k_scan_up, dim3(G), dim3(kScanBlock), 0, s, in, idx, n, temp, G);
-  hipLaunchKernelGGL(k_scan_down, dim3(G), dim3(kScanBlock), 0, s, in, idx, out, n, temp, G, total);
+  uint32_t* gathered = temp + kScanGrid;
+  hipLaunchKernelGGL(k_scan_up, dim3(G), dim3(kScanBlock), 0, s, in, idx, n, temp, G, gathered);
+  if (idx)
+    hipLaunchKernelGGL(k_scan_down, dim3(G), dim3(kScanBlock), 0, s, gathered, nullptr, out, n, temp, G, total);
+  else
+    hipLaunchKernelGGL(k_scan_down, dim3(G), dim3(kScanBlock), 0, s, in, nullptr, out, n, temp, G, total);
   return hipGetLastError();
 }
 
@@ -213,23 +241,24 @@ k_radix_up(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64
   counts[(int64_t)d * G + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
 }
 
-// Block d: exclusive scan of row d (G <= 1024 entries) in place, its total to totals[d].
+// Block d: exclusive scan of row d (G <= kSortGrid entries) in place, its total to totals[d].
 __global__ void __launch_bounds__(256)
 k_radix_rowscan(uint32_t* __restrict__ counts, int G, uint32_t* __restrict__ totals) {
+  constexpr int kPer = kSortGrid / 256;
   __shared__ uint32_t s_warp[4];
   uint32_t* row = counts + (int64_t)blockIdx.x * G;
-  uint32_t v[4], sum = 0;
+  uint32_t v[kPer], sum = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int i = (int)threadIdx.x * 4 + k;
+  for (int k = 0; k < kPer; ++k) {
+    const int i = (int)threadIdx.x * kPer + k;
     v[k] = i < G ? row[i] : 0u;
     sum += v[k];
   }
   uint32_t total;
   uint32_t run = block_exclusive_scan(sum, s_warp, total);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int i = (int)threadIdx.x * 4 + k;
+  for (int k = 0; k < kPer; ++k) {
+    const int i = (int)threadIdx.x * kPer + k;
     if (i < G) row[i] = run;
     run += v[k];
   }

@@ -330,15 +330,16 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const f
 }
 
 // One Adam update of a parameter (Sec. III-D.2 sparse Adam, Sec. IV-A.1 rates). Shared by
-// the Adam kernels so that every path takes the same rounding steps.
+// the Adam kernels; every operation is an explicitly rounded one (no contraction, IEEE
+// division and square root), so that every path and kernel takes the same rounding steps.
 __device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, float lr, float beta1,
                                             float beta2, float eps, float bc1, float bc2) {
-#pragma clang fp contract(off)
-  const float mm = beta1 * m + (1.0f - beta1) * g;
-  const float vv = beta2 * v + (1.0f - beta2) * (g * g);
+  const float mm = __fadd_rn(__fmul_rn(beta1, m), __fmul_rn(__fsub_rn(1.0f, beta1), g));
+  const float vv = __fadd_rn(__fmul_rn(beta2, v), __fmul_rn(__fsub_rn(1.0f, beta2), __fmul_rn(g, g)));
   m = mm;
   v = vv;
-  p = p - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+  const float den = __fadd_rn(__fsqrt_rn(__fdiv_rn(vv, bc2)), eps);
+  p = __fsub_rn(p, __fdiv_rn(__fmul_rn(lr, __fdiv_rn(mm, bc1)), den));
 }
 
 __device__ __forceinline__ float wave_sum(float x) {

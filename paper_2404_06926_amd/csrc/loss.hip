@@ -2,14 +2,20 @@
 // gradient. SSIM per channel with an 11x11 Gaussian window (sigma 1.5, separable),
 // C1 = 0.01^2, C2 = 0.03^2, zero padding outside the image.
 //
-// Pass 1 (per 16x16 pixel block, per channel): out and gt with a 5-pixel halo go to LDS,
-// a horizontal then a vertical window pass forms the five local moments, and the pass
-// writes the partial derivatives of SSIM with respect to mu_x, E[x^2] and E[xy] (already
-// scaled by dL/dSSIM) plus per-block sums of SSIM and |out - gt|.
-// Pass 2: the same separable window applied to those partial maps (the window is
-// symmetric, so the adjoint of the zero-padded correlation is the same correlation)
-// gives dL/dout = blur(d_mu) + 2 x blur(d_xx) + y blur(d_xy) + L1 term.
-// Pass 3: one block adds the per-block sums in a fixed order.
+// One fused pass per 32x16 output tile (k_ssim_tile), channel by channel:
+//   1. out and gt over the tile with a 10-pixel margin go to LDS (each lane loads the next
+//      channel's share into registers while the current channel is processed);
+//   2. the five local moments (mu_x, mu_y, E[x^2], E[y^2], E[xy]) over the tile with a
+//      5-pixel margin: a horizontal then a vertical window pass, each lane producing a run
+//      of outputs from values it holds in registers;
+//   3. at those pixels (inside the image; zero outside) the partial derivatives of SSIM
+//      with respect to mu_x, E[x^2] and E[xy], scaled by dL/dSSIM;
+//   4. the same separable window applied to those three maps (the window is symmetric, so
+//      the adjoint of the zero-padded correlation is the same correlation) gives
+//      dL/dout = blur(d_mu) + 2 x blur(d_xx) + y blur(d_xy) + the L1 term on the tile.
+// The moments of the 5-pixel margin are recomputed by the neighbouring tiles instead of
+// going through HBM. A second launch adds the per-tile sums of SSIM and |out - gt| in a
+// fixed order.
 #include <cmath>
 
 #include "gs_common.h"
@@ -17,11 +23,18 @@
 
 namespace gs {
 
-constexpr int kLB = 16;          // output block edge
-constexpr int kHalo = 5;
-constexpr int kLE = kLB + 2 * kHalo;  // 26
+constexpr int kR = 5;                  // window radius
+constexpr int kTW = 32, kTH = 16;      // output tile
+constexpr int kBW = kTW + 2 * kR;      // 42: moments / derivative maps
+constexpr int kBH = kTH + 2 * kR;      // 26
+constexpr int kAW = kTW + 4 * kR;      // 52: inputs
+constexpr int kAH = kTH + 4 * kR;      // 36
+constexpr int kHRun = 6;               // horizontal moment pass: outputs per lane (42 = 7 x 6)
+constexpr int kVRun = 7;               // vertical moment pass: rows per lane (26 = 3 x 7 + 5)
+constexpr int kDRun = 8;               // horizontal derivative pass: outputs per lane (32 = 4 x 8)
+constexpr int kGRun = 2;               // vertical derivative pass: rows per lane (16 = 8 x 2)
 
-// Normalised 1-D Gaussian window (sigma 1.5), passed by value to the kernels.
+// Normalised 1-D Gaussian window (sigma 1.5), passed by value to the kernel.
 struct Win {
   float w[11];
 };
@@ -37,138 +50,203 @@ static Win make_window() {
   return W;
 }
 
-template <int NQ>
-__device__ __forceinline__ void sep_blur(const Win& c_win, float (*src)[kLE][kLE], float (*hbuf)[kLE][kLB],
-                                         float* outv) {
-  // horizontal: rows 0..25, output columns 0..15
-  for (int t = threadIdx.x; t < kLE * kLB; t += 256) {
-    const int r = t / kLB, c = t % kLB;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      float acc = 0.f;
-#pragma unroll
-      for (int j = 0; j < 11; ++j) acc += c_win.w[j] * src[q][r][c + j];
-      hbuf[q][r][c] = acc;
-    }
-  }
-  __syncthreads();
-  const int ly = threadIdx.x / kLB, lx = threadIdx.x % kLB;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    float acc = 0.f;
-#pragma unroll
-    for (int i = 0; i < 11; ++i) acc += c_win.w[i] * hbuf[q][ly + i][lx];
-    outv[q] = acc;
-  }
-}
+struct SsimLds {
+  float x[kAH][kAW + 1];
+  float y[kAH][kAW + 1];
+  union {
+    float h[5][kAH][kBW];       // horizontal pass of the five moment maps
+    float hd[3][kBH][kTW + 1];  // horizontal pass of the three derivative maps
+  };
+  float d[3][kBH][kBW + 1];     // derivative maps
+  float red[2][4];
+};
 
 __global__ void __launch_bounds__(256)
-k_ssim_fwd(Win win, const float* __restrict__ x, const float* __restrict__ y, int H, int W, float lambda,
-           float* __restrict__ dmu, float* __restrict__ dxx, float* __restrict__ dxy,
-           float* __restrict__ part) {
-  __shared__ float s_src[5][kLE][kLE];
-  __shared__ float s_h[5][kLE][kLB];
-  __shared__ float s_red[2][4];
-  const int bx = blockIdx.x * kLB, by = blockIdx.y * kLB;
-  const int ly = threadIdx.x / kLB, lx = threadIdx.x % kLB;
-  const int px = bx + lx, py = by + ly;
-  const bool inside = px < W && py < H;
+k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, int H, int W, float lambda,
+            float* __restrict__ gout, float* __restrict__ part) {
+  __shared__ SsimLds L;
+  const int bx = blockIdx.x * kTW, by = blockIdx.y * kTH;
+  const int tid = threadIdx.x;
   const int64_t P = (int64_t)H * W;
   const float n = 3.0f * (float)P;
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
+  const float s_ssim = -lambda / n;                    // dL/dSSIM per pixel and channel
+  const float l1w = (1.0f - lambda) / n;
   float ssum = 0.f, l1 = 0.f;
-  for (int ch = 0; ch < 3; ++ch) {
-    const float* xc = x + ch * P;
-    const float* yc = y + ch * P;
-    __syncthreads();
-    for (int t = threadIdx.x; t < kLE * kLE; t += 256) {
-      const int r = t / kLE, c = t % kLE;
-      const int gy = by + r - kHalo, gx = bx + c - kHalo;
-      float a = 0.f, b = 0.f;
-      if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-        a = xc[(int64_t)gy * W + gx];
-        b = yc[(int64_t)gy * W + gx];
+  constexpr int kLoadPer = (kAH * kAW + 255) / 256;
+  float pa[kLoadPer], pb[kLoadPer];
+  auto fetch = [&](int ch) {
+#pragma unroll
+    for (int j = 0; j < kLoadPer; ++j) {
+      const int t = tid + 256 * j;
+      const int r = t / kAW, c = t % kAW;
+      const int gy = by - 2 * kR + r, gx = bx - 2 * kR + c;
+      pa[j] = pb[j] = 0.f;
+      if (t < kAH * kAW && gx >= 0 && gx < W && gy >= 0 && gy < H) {
+        pa[j] = x[ch * P + (int64_t)gy * W + gx];
+        pb[j] = y[ch * P + (int64_t)gy * W + gx];
       }
-      s_src[0][r][c] = a;
-      s_src[1][r][c] = b;
-      s_src[2][r][c] = a * a;
-      s_src[3][r][c] = b * b;
-      s_src[4][r][c] = a * b;
+    }
+  };
+  fetch(0);
+  for (int ch = 0; ch < 3; ++ch) {
+    __syncthreads();
+    // 1. inputs with a 10-pixel margin (zero outside the image); the next channel's are
+    // loaded into registers while this one is processed
+#pragma unroll
+    for (int j = 0; j < kLoadPer; ++j) {
+      const int t = tid + 256 * j;
+      if (t < kAH * kAW) {
+        L.x[t / kAW][t % kAW] = pa[j];
+        L.y[t / kAW][t % kAW] = pb[j];
+      }
+    }
+    if (ch < 2) fetch(ch + 1);
+    __syncthreads();
+    // 2a. horizontal window pass of the five moments: rows of the input block, columns of
+    // the moment block; lane = (row, run of kHRun columns)
+    if (tid < kAH * (kBW / kHRun)) {
+      const int r = tid / (kBW / kHRun), c0 = (tid % (kBW / kHRun)) * kHRun;
+      float xv[kHRun + 10], yv[kHRun + 10];
+#pragma unroll
+      for (int j = 0; j < kHRun + 10; ++j) {
+        xv[j] = L.x[r][c0 + j];
+        yv[j] = L.y[r][c0 + j];
+      }
+#pragma unroll
+      for (int o = 0; o < kHRun; ++o) {
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 11; ++j) {
+          const float a = xv[o + j], b = yv[o + j], w = win.w[j];
+          m0 += w * a;
+          m1 += w * b;
+          m2 += w * (a * a);
+          m3 += w * (b * b);
+          m4 += w * (a * b);
+        }
+        L.h[0][r][c0 + o] = m0;
+        L.h[1][r][c0 + o] = m1;
+        L.h[2][r][c0 + o] = m2;
+        L.h[3][r][c0 + o] = m3;
+        L.h[4][r][c0 + o] = m4;
+      }
     }
     __syncthreads();
-    float m[5];
-    sep_blur<5>(win, s_src, s_h, m);
-    if (inside) {
-      const float mx = m[0], my = m[1];
-      const float A1 = 2.f * mx * my + C1, A2 = 2.f * (m[4] - mx * my) + C2;
-      const float B1 = mx * mx + my * my + C1, B2 = (m[2] - mx * mx) + (m[3] - my * my) + C2;
-      const float num = A1 * A2, den = B1 * B2;
-      const float S = num / den;
-      ssum += S;
-      const float s = -lambda / n;
-      const float dnum = 2.f * my * A2 - 2.f * my * A1;
-      const float dden = 2.f * mx * B2 - 2.f * mx * B1;
-      const int64_t q = ch * P + (int64_t)py * W + px;
-      dmu[q] = s * (dnum * den - num * dden) / (den * den);
-      dxx[q] = s * (-num * B1 / (den * den));
-      dxy[q] = s * (2.f * A1 / den);
-      l1 += fabsf(s_src[0][ly + kHalo][lx + kHalo] - s_src[1][ly + kHalo][lx + kHalo]);
+    // 2b. vertical pass and 3. the derivative maps; lane = (column, run of kVRun rows)
+    constexpr int kVRuns = (kBH + kVRun - 1) / kVRun;
+    if (tid < kBW * kVRuns) {
+      const int c = tid % kBW, r0 = (tid / kBW) * kVRun;
+      const int nr = min(kVRun, kBH - r0);
+      float acc[5][kVRun];
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int o = 0; o < kVRun; ++o) acc[k][o] = 0.f;
+#pragma unroll
+      for (int i = 0; i < kVRun + 10; ++i) {
+        if (r0 + i >= kAH) break;
+        float hv[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) hv[k] = L.h[k][r0 + i][c];
+#pragma unroll
+        for (int o = 0; o < kVRun; ++o) {
+          const int j = i - o;  // tap index of input row r0 + i for output row r0 + o
+          if (j < 0 || j > 10) continue;
+          const float w = win.w[j];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) acc[k][o] += w * hv[k];
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < kVRun; ++o) {
+        if (o >= nr) break;
+        const int rb = r0 + o;
+        const int gy = by - kR + rb, gx = bx - kR + c;
+        float dmu = 0.f, dxx = 0.f, dxy = 0.f;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+          const float mx = acc[0][o], my = acc[1][o];
+          const float A1 = 2.f * mx * my + C1, A2 = 2.f * (acc[4][o] - mx * my) + C2;
+          const float B1 = mx * mx + my * my + C1, B2 = (acc[2][o] - mx * mx) + (acc[3][o] - my * my) + C2;
+          const float num = A1 * A2, den = B1 * B2;
+          const float dnum = 2.f * my * A2 - 2.f * my * A1;
+          const float dden = 2.f * mx * B2 - 2.f * mx * B1;
+          dmu = s_ssim * (dnum * den - num * dden) / (den * den);
+          dxx = s_ssim * (-num * B1 / (den * den));
+          dxy = s_ssim * (2.f * A1 / den);
+          // SSIM of the tile's own pixels (the margins belong to the neighbours)
+          if (rb >= kR && rb < kR + kTH && c >= kR && c < kR + kTW) ssum += num / den;
+        }
+        L.d[0][rb][c] = dmu;
+        L.d[1][rb][c] = dxx;
+        L.d[2][rb][c] = dxy;
+      }
+    }
+    __syncthreads();
+    // 4a. horizontal window pass of the derivative maps; lane = (row, run of kDRun columns)
+    if (tid < kBH * (kTW / kDRun)) {
+      const int r = tid / (kTW / kDRun), c0 = (tid % (kTW / kDRun)) * kDRun;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float dv[kDRun + 10];
+#pragma unroll
+        for (int j = 0; j < kDRun + 10; ++j) dv[j] = L.d[k][r][c0 + j];
+#pragma unroll
+        for (int o = 0; o < kDRun; ++o) {
+          float a = 0.f;
+#pragma unroll
+          for (int j = 0; j < 11; ++j) a += win.w[j] * dv[o + j];
+          L.hd[k][r][c0 + o] = a;
+        }
+      }
+    }
+    __syncthreads();
+    // 4b. vertical pass and dL/dout on the tile; lane = (column, run of kGRun rows)
+    {
+      const int c = tid % kTW, r0 = (tid / kTW) * kGRun;
+      float g[3][kGRun];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int o = 0; o < kGRun; ++o) g[k][o] = 0.f;
+#pragma unroll
+      for (int i = 0; i < kGRun + 10; ++i) {
+        float hv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) hv[k] = L.hd[k][r0 + i][c];
+#pragma unroll
+        for (int o = 0; o < kGRun; ++o) {
+          const int j = i - o;
+          if (j < 0 || j > 10) continue;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) g[k][o] += win.w[j] * hv[k];
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < kGRun; ++o) {
+        const int py = by + r0 + o, px = bx + c;
+        if (px >= W || py >= H) continue;
+        const float xv = L.x[r0 + o + 2 * kR][c + 2 * kR], yv = L.y[r0 + o + 2 * kR][c + 2 * kR];
+        const float d = xv - yv;
+        const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        gout[ch * P + (int64_t)py * W + px] = g[0][o] + 2.f * xv * g[1][o] + yv * g[2][o] + l1w * sg;
+        l1 += fabsf(d);
+      }
     }
   }
   ssum = wave_sum(ssum);
   l1 = wave_sum(l1);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = tid & 63, wid = tid >> 6;
   __syncthreads();
   if (lane == 0) {
-    s_red[0][wid] = ssum;
-    s_red[1][wid] = l1;
+    L.red[0][wid] = ssum;
+    L.red[1][wid] = l1;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    part[2 * b] = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
-    part[2 * b + 1] = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
-  }
-}
-
-__global__ void __launch_bounds__(256)
-k_ssim_bwd(Win win, const float* __restrict__ x, const float* __restrict__ y, int H, int W, float lambda,
-           const float* __restrict__ dmu, const float* __restrict__ dxx, const float* __restrict__ dxy,
-           float* __restrict__ gout) {
-  __shared__ float s_src[3][kLE][kLE];
-  __shared__ float s_h[3][kLE][kLB];
-  const int bx = blockIdx.x * kLB, by = blockIdx.y * kLB;
-  const int ly = threadIdx.x / kLB, lx = threadIdx.x % kLB;
-  const int px = bx + lx, py = by + ly;
-  const bool inside = px < W && py < H;
-  const int64_t P = (int64_t)H * W;
-  const float l1w = (1.0f - lambda) / (3.0f * (float)P);
-  for (int ch = 0; ch < 3; ++ch) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < kLE * kLE; t += 256) {
-      const int r = t / kLE, c = t % kLE;
-      const int gy = by + r - kHalo, gx = bx + c - kHalo;
-      float a = 0.f, b = 0.f, d = 0.f;
-      if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-        const int64_t q = ch * P + (int64_t)gy * W + gx;
-        a = dmu[q];
-        b = dxx[q];
-        d = dxy[q];
-      }
-      s_src[0][r][c] = a;
-      s_src[1][r][c] = b;
-      s_src[2][r][c] = d;
-    }
-    __syncthreads();
-    float m[3];
-    sep_blur<3>(win, s_src, s_h, m);
-    if (inside) {
-      const int64_t q = ch * P + (int64_t)py * W + px;
-      const float xv = x[q], yv = y[q];
-      const float d = xv - yv;
-      const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-      gout[q] = m[0] + 2.f * xv * m[1] + yv * m[2] + l1w * sg;
-    }
+    part[2 * b] = L.red[0][0] + L.red[0][1] + L.red[0][2] + L.red[0][3];
+    part[2 * b + 1] = L.red[1][0] + L.red[1][1] + L.red[1][2] + L.red[1][3];
   }
 }
 
@@ -197,23 +275,18 @@ k_loss_reduce(const float* __restrict__ part, int64_t nb, int64_t P, float lambd
 }
 
 int64_t loss_temp_floats(int H, int W) {
-  const int64_t P = (int64_t)H * W;
-  const int64_t nb = (int64_t)((W + kLB - 1) / kLB) * ((H + kLB - 1) / kLB);
-  return 9 * P + 2 * nb + 64;
+  const int64_t nb = (int64_t)((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
+  return 2 * nb + 64;
 }
 
 hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,
                      float* gout, hipStream_t s) {
   const Win win = make_window();
   const int64_t P = (int64_t)H * W;
-  float* dmu = temp;
-  float* dxx = temp + 3 * P;
-  float* dxy = temp + 6 * P;
-  float* part = temp + 9 * P;
-  const dim3 grid((W + kLB - 1) / kLB, (H + kLB - 1) / kLB);
+  float* part = temp;
+  const dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH);
   const int64_t nb = (int64_t)grid.x * grid.y;
-  hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, win, out, gt, H, W, lambda, dmu, dxx, dxy, part);
-  hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, win, out, gt, H, W, lambda, dmu, dxx, dxy, gout);
+  hipLaunchKernelGGL(k_ssim_tile, grid, dim3(256), 0, s, win, out, gt, H, W, lambda, gout, part);
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, part, nb, P, lambda, loss);
   return hipGetLastError();
 }

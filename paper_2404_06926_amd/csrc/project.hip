@@ -5,6 +5,12 @@
 // are read once and the view-independent covariance is formed once. Parameter planes
 // are read coalesced; the per-(view, Gaussian) records are 64 B and written by the lane
 // that owns them.
+//
+// No multiply-add contraction anywhere in this file (the pragma precedes the includes):
+// the adjoint's kernels, fused with Adam or not, then round every gradient term the same
+// way, and a step with the fused update gives bit for bit the parameters of a backward
+// followed by the separate Adam kernel. These kernels are bound by memory traffic.
+#pragma clang fp contract(off)
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -175,7 +181,8 @@ __device__ __forceinline__ void adam_rows(float* __restrict__ P, float* __restri
   for (int j = 0; j < NB; ++j) {
     const int64_t f = (int64_t)(f0 + stride * j) * cap;
     float pp = p[j];
-    adam_update(pp, m[j], v[j], acc[j] + g[j], lr[j], ad.beta1, ad.beta2, ad.eps, bc1, bc2);
+    // rounded sum (no contraction), as the separate path's += then load
+    adam_update(pp, m[j], v[j], __fadd_rn(acc[j], g[j]), lr[j], ad.beta1, ad.beta2, ad.eps, bc1, bc2);
     __builtin_nontemporal_store(pp, &plane_at(P + f, lo));
     __builtin_nontemporal_store(m[j], &plane_at(Mp + f, lo));
     __builtin_nontemporal_store(v[j], &plane_at(Vp + f, lo));
@@ -210,7 +217,10 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   if (i >= N) return;
   // non-fused: gradient g of plane f added to the gradient planes
   const uint32_t lo = (uint32_t)i * 4u;  // byte offset of the row in every plane (cap < 2^30)
-  auto emit = [&](int f, float g) { plane_at(Gp + (int64_t)f * cap, lo) += g; };
+  auto emit = [&](int f, float g) {
+    float& d = plane_at(Gp + (int64_t)f * cap, lo);
+    d = __fadd_rn(d, g);
+  };
   auto ldp = [&](int f) { return plane_at(P + (int64_t)f * cap, lo); };
   float* __restrict__ Mp = ad.m;
   float* __restrict__ Vp = ad.v;
@@ -260,7 +270,7 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         wsum[k] += gcol * shc[k];
-        gk[k] = gcol * Y[k];
+        gk[k] = __fmul_rn(gcol, Y[k]);  // rounded: both paths add exactly this value
       }
       if (MULTI) {
 #pragma unroll

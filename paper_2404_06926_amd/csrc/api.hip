@@ -602,14 +602,14 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   {
     StageTimer t(m, s, GS_STAGE_PROJECT);
     GS_HIP(fill_u32(big_n, 0u, 1, s));
-    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0], dval[0],
+    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0],
                            (uint32_t*)m->big_list.ptr, big_n, s));
   }
   int dwhich = 0;
   {
     StageTimer t(m, s, GS_STAGE_DEPTH_SORT);
     GS_HIP(fill_u32(m->d_nvn, (uint32_t)vn, 1, s));
-    GS_HIP(radix_sort_u32(dkey, dval, m->d_nvn, vn, 32, (uint32_t*)m->sort_tmp.ptr, &dwhich, s));
+    GS_HIP(radix_sort_u32(dkey, dval, m->d_nvn, vn, 32, (uint32_t*)m->sort_tmp.ptr, &dwhich, s, true));
   }
   const uint32_t* order = dval[dwhich];
   {
@@ -634,7 +634,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   {
     StageTimer t(m, s, GS_STAGE_DUPLICATE);
     GS_HIP(duplicate_keys(rec, counts, order, offsets, m->d_ninst, (const uint32_t*)m->big_list.ptr, big_n, N, va,
-                          keys[0], vals[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr,
+                          keys[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr,
                           (uint32_t*)m->block_start.ptr, m->inst_cap, m->d_overflow, s));
   }
   int which = 0;
@@ -642,7 +642,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     // stable sort by tile id; one extra bit keeps the sentinel id above every real tile
     StageTimer t(m, s, GS_STAGE_SORT);
     GS_HIP(radix_sort_u32(keys, vals, m->d_ninst, m->inst_cap, bits_for(tiles + 1), (uint32_t*)m->sort_tmp.ptr,
-                          &which, s));
+                          &which, s, true));
   }
   uint2* ranges = (uint2*)m->ranges.ptr;
   {

@@ -30,7 +30,7 @@ struct AdamArg {
 // projection (project.hip)
 // big_list / big_n (zeroed before): pairs whose tile rectangle exceeds 64 tiles.
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                           float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* dval, uint32_t* big_list,
+                           float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* big_list,
                            uint32_t* big_n, hipStream_t s);
 // With inst_grad != nullptr the 2D gradients are the sums, in emission order, of the
 // instance records [inst_off[vi], inst_off[vi] + counts[vi]); otherwise they come from g2d.
@@ -49,13 +49,14 @@ hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* 
 int64_t block_start_elems(int64_t capacity);
 hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
                           const uint32_t* n_dev, const uint32_t* big_list, const uint32_t* big_n, int32_t N,
-                          const ViewsArg& va, uint32_t* tiles, uint32_t* vals, uint32_t* emit_g, uint32_t* inst_off,
+                          const ViewsArg& va, uint32_t* tiles, uint32_t* emit_g, uint32_t* inst_off,
                           uint32_t* block_start, int64_t capacity, uint32_t* overflow, hipStream_t s);
 hipError_t gather_gaussians(const uint32_t* vals, const uint32_t* emit_g, const uint32_t* n_dev, int64_t cap,
                             uint32_t* out, hipStream_t s);
 int64_t sort_temp_elems(int64_t cap);
+// vals_iota: the values are 0, 1, 2, ... and vals[0] is not read.
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
-                          uint32_t* temp, int* which, hipStream_t s);
+                          uint32_t* temp, int* which, hipStream_t s, bool vals_iota);
 hipError_t tile_ranges(const uint32_t* tiles, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
                        hipStream_t s);
 

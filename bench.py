@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-outdoor", action="store_true", help="skip the outdoor single-view measurement")
-    ap.add_argument("--blend-px", default="1,2",
+    ap.add_argument("--blend-px", default="1,1",
                     help="pixels per lane of the forward and backward blend kernels (1, 2 or 4)")
     ap.add_argument("--split", default="4096,128,1.25",
                     help="long-list split of the blend: parallel,min_chunk,balance (parallel 0: every tile whole)")
@@ -489,14 +489,15 @@ def main():
     atomics = 36.0 * n_inst * (4 // bpx)   # one 9-float atomic add per wave and instance
     # (the headline's adam stage is fused into project_backward: no separate pass)
     work = {
-        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + (64.0 + 12.0) * n_vis + 12.0 * V * args.n, 0),
-        "depth_sort": ("hbm", 4 * 24.0 * V * args.n, 0),
+        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + 64.0 * n_vis + 8.0 * V * args.n, 0),
+        # 20 B per key and pass (4 read up, 8 read + 8 written down); the first pass reads no values
+        "depth_sort": ("hbm", (4 * 20.0 - 4.0) * V * args.n, 0),
         "scan": ("hbm", 12.0 * V * args.n, 0),
-        "duplicate": ("hbm", 24.0 * n_vis + 12.0 * n_inst, 0),
-        "sort": ("hbm", tile_passes * 20.0 * n_inst, 0),
+        "duplicate": ("hbm", 24.0 * n_vis + 8.0 * n_inst, 0),
+        "sort": ("hbm", (tile_passes * 20.0 - 4.0) * n_inst, 0),
         "ranges": ("hbm", 4.0 * n_inst + 8.0 * T_total, 0),
         "blend": ("alu", 40.0 * n_inst + 20.0 * P, FWD_FLOPS_PER_PAIR * float(pairs)),
-        "loss": ("hbm", 132.0 * P, 0),
+        "loss": ("hbm", 36.0 * P, 0),   # read out and gt, write dL/dout (3 channels)
         "blend_backward": ("alu", 40.0 * n_inst + 32.0 * P + atomics, BWD_FLOPS_PER_PAIR * float(pairs)),
         # fused with Adam: read and write parameters, m and v (3 x 4F B each way), read and
         # clear the 48-B 2D-gradient record, read the tile counts

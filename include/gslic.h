@@ -331,7 +331,7 @@ gs_status gs_set_deterministic(gs_map* map, int32_t enable);
 gs_status gs_set_backward_mode(gs_map* map, int32_t mode);
 
 /* Launch configuration of the blend kernels: pixels per lane in the forward and backward
- * (1, 2 or 4; default 1 and 2). With p pixels per lane a tile is processed by 256 / p
+ * (1, 2 or 4; default 1 and 1). With p pixels per lane a tile is processed by 256 / p
  * lanes and each list entry's LDS reads and gradient reductions are shared by p pixels.
  * Results do not depend on it beyond FP32 summation order. */
 gs_status gs_set_blend_config(gs_map* map, int32_t fwd_px_per_lane, int32_t bwd_px_per_lane);

@@ -93,7 +93,7 @@ struct gs_map {
   bool grads_dirty = false;    // gradient planes may hold non-zero values (a backward without Adam,
                                // or their pointer was handed out)
   bool step_assumed_clean = false;  // the last fused gs_step skipped reading the gradient planes
-  int fwd_px = 1, bwd_px = 2;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
+  int fwd_px = 1, bwd_px = 1;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
   int32_t split_par = 4096, split_min = 128;  // long-list split (SplitArg)
   float split_balance = 1.25f;
   SplitArg last_sp{};          // split of the last render, used by its backward

@@ -46,7 +46,7 @@ def _oracle(name):
 def _gpu(name):
     params, deg, cams, *_ = _oracle(name)
     m = gpu_map(params, deg)
-    m.set_blend_config(1, 2)            # bench.py's default launch configuration
+    m.set_blend_config(1, 1)            # bench.py's default launch configuration
     return m
 
 

@@ -415,15 +415,21 @@ def _clone_state(src, dst):
     torch.cuda.synchronize()
 
 
-def test_step_graph_replays_match_eager_steps():
+@pytest.mark.parametrize("split", [None, (65536, 64, 0.0)])
+def test_step_graph_replays_match_eager_steps(split):
     # Map B replays a captured step; before each replay map A takes B's state and runs the
     # same step eagerly. Renders and losses are deterministic, so they must agree bit for
     # bit; parameters after Adam agree up to the order of the backward's float atomics.
+    # The split lists' counters and state live in the graph's buffers and are reset by
+    # kernels, so replays see the same split as an eager step.
     torch = torch_mod()
     params, deg, cams = case("multi")
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         mA, mB = gpu_map(params, deg), gpu_map(params, deg)
+        if split is not None:
+            mA.set_tile_split(*split)
+            mB.set_tile_split(*split)
         tg = [torch.tensor(scenes.smooth_image(k, c.height, c.width), device="cuda") for k, c in enumerate(cams)]
 
         def bufs():

@@ -403,8 +403,23 @@ def test_invalid_arguments_leave_map_unchanged():
     with pytest.raises(gslic.GsError) as e:
         m.render([cam] * 17)
     assert e.value.code == gslic.GS_ERR_CAPACITY
+    for args in [(-1, 128, 1.0), (1 << 17, 128, 1.0), (4096, 0, 1.0), (4096, 128, -1.0), (4096, 128, float("nan"))]:
+        with pytest.raises(gslic.GsError) as e:
+            m.set_tile_split(*args)
+        assert e.value.code == gslic.GS_ERR_INVALID, args
+    for fwd, bwd in [(7, 1), (0, 1), (1, 3), (1, 8)]:
+        with pytest.raises(gslic.GsError) as e:
+            m.set_blend_config(fwd, bwd)
+        assert e.value.code == gslic.GS_ERR_INVALID, (fwd, bwd)
     np.testing.assert_array_equal(m.params().cpu().numpy().T, p)
     assert m.n == 300
+    # a split setting takes effect from the next render; a backward after the change alone
+    # has no render of its own
+    m.render([cam])
+    m.set_tile_split(4096, 64, 0.0)
+    with pytest.raises(gslic.GsError) as e:
+        m.render_backward([torch.zeros(3, 48, 64, device="cuda")])
+    assert e.value.code == gslic.GS_ERR_STATE
 
 
 def _clone_state(src, dst):

@@ -79,6 +79,31 @@ def recorded_traffic(kernel, workload_tag):
     return None
 
 
+def recorded_valu(kernel, workload_tag):
+    """VALU wave-instructions per launch of `kernel` from the committed SQ counter summary
+    (profiles/sq_counters_<tag>.md), or None (no summary, or the source changed since)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload_tag}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("kernel="):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split())
+        if f["kernel"] != kernel:
+            continue
+        src = os.path.join(ROOT, f["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != f["sha256"]:
+            return None
+        return float(f["valu_insts"])
+    return None
+
+
+# wave64 VALU instructions the device can issue per second: 256 CUs x 4 SIMDs, one every
+# 4 cycles, 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+
+
 def headline_workload(n, deg, W, H, seed=2024):
     from paper_2404_06926_amd import scenes
     cam = scenes.pinhole(W, H, 1000.0 * W / 1280.0)
@@ -535,6 +560,11 @@ def main():
     traffic = recorded_traffic(names[dom], tag) if dom in names else None
     roof = dict(bound=bound, kernel=dom, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
                 traffic=traffic, avg_launch_ms=per[dom])
+    valu = recorded_valu(names[dom], tag) if dom in names else None
+    if valu is not None:
+        # instruction side of an ALU-bound kernel: VALU wave-instructions per launch (SQ
+        # counters) over what the device issues in the launch's duration
+        roof["valu_issue_frac"] = valu / (dur_s * VALU_ISSUE_PER_S)
     if traffic is not None:
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)"
         roof["traffic_GBs"] = traffic / dur_s / 1e9

@@ -380,6 +380,8 @@ def main():
                     help="pixels per lane of the forward and backward blend kernels (1, 2 or 4)")
     ap.add_argument("--split", default="4096,128,1.25",
                     help="long-list split of the blend: parallel,min_chunk,balance (parallel 0: every tile whole)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the blend launch shapes by timing runs of mapping steps of every candidate on this map")
     ap.add_argument("--bwd-mode", type=int, default=0,
                     help="backward blend: 0 pixel order, 1 per Gaussian")
     ap.add_argument("--copy-probe", action="store_true",
@@ -441,6 +443,18 @@ def main():
     torch.cuda.synchronize()
     n_inst0 = m.debug_last_render()["n_inst"]
     m.set_instance_policy(False, int(n_inst0 * 1.5) + 65536)
+    tuned = None
+    if args.autotune:
+        from paper_2404_06926_amd import tune
+        best, times = tune.autotune_step(m, cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam,
+                                         steps=min(args.steps, 50))
+        fpx, bpx, args.bwd_mode, sp = best
+        args.split = ",".join(str(x) for x in sp)
+        tuned = {"chosen": {"blend_px_per_lane": [fpx, bpx], "backward_mode": args.bwd_mode, "tile_split": list(sp)},
+                 "configs_tried": len(times), "ms_best": times[best],
+                 "ms_defaults": times.get((1, 1, 0, (4096, 128, 1.25)))}
+        log(f"autotune: {tuned}")
+        log("autotune times: " + "; ".join(f"{k}: {v:.3f}" for k, v in sorted(times.items(), key=lambda kv: kv[1])))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -591,6 +605,7 @@ def main():
                    "timing": "graph replay" if ms_graph is not None else "eager",
                    "blend_px_per_lane": [fpx, bpx],
                    "tile_split": list(split_config(args)),
+                   "autotuned": tuned,
                    "backward_blend": "pixel order" if args.bwd_mode == 0 else "per Gaussian"},
         "roofline": roof,
         "eager_ms_per_step": ms_eager,

@@ -266,6 +266,11 @@ gs_status gs_map_visibility(gs_map* map, uint8_t** vis);
 /* Number of Adam steps taken (host mirror of the device counter). */
 gs_status gs_map_step_count(const gs_map* map, int64_t* t);
 
+/* Sets the Adam step counter t (Sec. III-D.2: the bias corrections 1 - beta^t of the next
+ * step use t + 1), on `stream`, as a checkpoint restore of parameters and moments needs.
+ * t < 0 or a NULL map: GS_ERR_INVALID. Ordered on `stream` like the steps around it. */
+gs_status gs_map_set_step_count(gs_map* map, int64_t t, void* stream);
+
 /* Device views of the last gs_render's intermediate results, valid until the next render:
  *   tiles     uint32[n_inst]  global tile id of each instance, in blend order (tile, then
  *                             depth, then Gaussian index); the sort key of instance k is

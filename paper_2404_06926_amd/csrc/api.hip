@@ -1088,6 +1088,18 @@ gs_status gs_map_step_count(const gs_map* m, int64_t* t) {
   return GS_OK;
 }
 
+gs_status gs_map_set_step_count(gs_map* m, int64_t t, void* stream) {
+  g_err.clear();
+  if (!m) return fail(GS_ERR_INVALID, "map is NULL");
+  if (t < 0) return fail(GS_ERR_INVALID, "step count must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t u = (uint64_t)t;
+  GS_HIP(fill_u32((uint32_t*)m->d_step, (uint32_t)u, 1, s));
+  GS_HIP(fill_u32((uint32_t*)m->d_step + 1, (uint32_t)(u >> 32), 1, s));
+  m->h_step = t;
+  return GS_OK;
+}
+
 gs_status gs_debug_last_render(gs_map* m, void* stream, const uint32_t** keys, const uint32_t** vals,
                                int64_t* n_inst, const uint32_t** ranges, int64_t* n_tiles, const float** proj,
                                const uint32_t** counts) {

@@ -93,6 +93,7 @@ _SIGS = {
                              ctypes.POINTER(_I64)]),
     "gs_map_visibility": (_I32, [_P, ctypes.POINTER(_P)]),
     "gs_map_step_count": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "gs_map_set_step_count": (_I32, [_P, _I64, _P]),
     "gs_debug_last_render": (_I32, [_P, _P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                     ctypes.POINTER(_P), ctypes.POINTER(_I64), ctypes.POINTER(_P),
                                     ctypes.POINTER(_P)]),
@@ -274,6 +275,10 @@ class GaussianMap:
         t = _I64()
         _check(lib().gs_map_step_count(self.handle, ctypes.byref(t)))
         return t.value
+
+    def set_step_count(self, t: int, stream=None):
+        """Restores the Adam step counter (with the parameters and moments of a checkpoint)."""
+        _check(lib().gs_map_set_step_count(self.handle, int(t), _stream(stream)))
 
     def _planes(self, which):
         torch = _torch()

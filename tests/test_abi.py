@@ -57,6 +57,7 @@ def test_defaults_and_validation_without_gpu(L):
     assert L.gs_adam_step(None, 0, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_loss(None, None, None, 4, 4, 0.2, None, None, None) == gslic.GS_ERR_INVALID
     assert L.gs_set_tile_split(None, 4096, 128, 2.0) == gslic.GS_ERR_INVALID
+    assert L.gs_map_set_step_count(None, 0, None) == gslic.GS_ERR_INVALID
     assert L.gs_destroy_map(None) == gslic.GS_OK
 
 
@@ -74,3 +75,16 @@ def test_struct_layouts_match_header():
     want = [ctypes.sizeof(gslic.GsMapDesc), ctypes.sizeof(gslic.GsView), ctypes.sizeof(gslic.GsFrame),
             ctypes.sizeof(gslic.GsAllocator), gslic.GsView.exposure.offset]
     assert got == want
+
+
+def test_autotune_candidates():
+    """Every candidate is a valid setting of the three setters; the per-Gaussian backward
+    (fixed shape) appears with one backward px only."""
+    from paper_2404_06926_amd import tune
+    c = tune.candidates()
+    assert len(c) == len(set(c)) == 3 * 3 * 3 + 3 * 3
+    for fpx, bpx, mode, (par, min_len, bal) in c:
+        assert fpx in (1, 2, 4) and bpx in (1, 2, 4) and mode in (0, 1)
+        assert par >= 0 and min_len >= 64 and bal >= 0.0
+        assert mode == 0 or bpx == 1
+    assert (1, 1, 0, (4096, 128, 1.25)) in c

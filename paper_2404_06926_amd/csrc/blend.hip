@@ -727,43 +727,49 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
 #pragma unroll
       for (int f = 0; f < NG; ++f) gv[f] = 0.f;
       bool any = false;
+      // Branch-free: a pixel that does not take this entry (outside the Gaussian's quadrant
+      // mask, past its last contributor, power > 0 or alpha below the cut-off) runs the same
+      // arithmetic with alpha = 0, which leaves its T and colour behind unchanged exactly
+      // (T is selected, B = 0 * c + 1 * B) and adds exact zeros to the sums.
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
-        if (!((m >> pixel_quadrant<PX>(wid, k)) & 1u)) continue;
-        if (pos >= (int)nc[k]) continue;
         float dx, dy;
         const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
-        if (power > 0.0f) continue;
         const float ex = __expf(power);
         const float araw = b.y * ex;
         const float alpha = fminf(kAlphaMax, araw);
-        if (alpha < kAlphaMin) continue;
-        any = true;
-        const float oma = 1.0f - alpha;
-        T[k] = T[k] * __builtin_amdgcn_rcpf(oma);  // transmittance in front of this Gaussian
-        const float w = alpha * T[k];
+        const bool on = ((m >> pixel_quadrant<PX>(wid, k)) & 1u) && pos < (int)nc[k] && power <= 0.0f &&
+                        alpha >= kAlphaMin;
+        any = any || on;
+        const float al = on ? alpha : 0.0f;
+        const float oma = 1.0f - al;
+        // transmittance in front of this Gaussian
+        T[k] = on ? T[k] * __builtin_amdgcn_rcpf(oma) : T[k];
+        const float w = al * T[k];
         gv[6] += w * G0[k];
         gv[7] += w * G1[k];
         gv[8] += w * G2[k];
         float dalpha = T[k] * ((b.z - B0[k]) * G0[k] + (b.w - B1[k]) * G1[k] + (c2 - B2[k]) * G2[k]);
-        B0[k] = alpha * b.z + oma * B0[k];
-        B1[k] = alpha * b.w + oma * B1[k];
-        B2[k] = alpha * c2 + oma * B2[k];
+        B0[k] = al * b.z + oma * B0[k];
+        B1[k] = al * b.w + oma * B1[k];
+        B2[k] = al * c2 + oma * B2[k];
         if (MAPS) {
           dalpha += T[k] * ((dep - BD[k]) * gD[k] + (1.0f - BO[k]) * gO[k]);
-          BD[k] = alpha * dep + oma * BD[k];
-          BO[k] = alpha + oma * BO[k];
+          BD[k] = al * dep + oma * BD[k];
+          BO[k] = al + oma * BO[k];
           gv[9] += w * gD[k];
         }
-        if (araw <= kAlphaMax) {
-          const float dpow = dalpha * alpha;
-          gv[0] += dpow * (a.z * dx + a.w * dy);
-          gv[1] += dpow * (a.w * dx + b.x * dy);
-          gv[2] += -0.5f * dpow * dx * dx;
-          gv[3] += -dpow * dx * dy;
-          gv[4] += -0.5f * dpow * dy * dy;
-          gv[5] += dalpha * ex;
-        }
+        // dL/dpower = dL/dalpha * alpha (no gradient through the clamp at kAlphaMax); its
+        // moments over the pixels, which the projection backward turns into the 2D mean,
+        // conic and opacity gradients
+        const float dpow = (on && araw <= kAlphaMax) ? dalpha * al : 0.0f;
+        const float px_ = dpow * dx, py_ = dpow * dy;
+        gv[0] += px_;
+        gv[1] += py_;
+        gv[2] += px_ * dx;
+        gv[3] += px_ * dy;
+        gv[4] += py_ * dy;
+        gv[5] += dpow;
       }
       if (!__any(any)) continue;
       // terms 0..7 transposed (lanes 8..15 end with the totals), the rest by DPP rows

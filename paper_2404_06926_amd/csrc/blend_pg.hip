@@ -169,13 +169,15 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
         acc[7] += w * G1;
         acc[8] += w * G2;
         if (araw <= kAlphaMax) {
+          // moments of dL/dpower = dL/dalpha * alpha (the 2D-gradient record's form)
           const float dpow = dalpha * alpha;
-          acc[0] += dpow * (a.z * dx + a.w * dy);
-          acc[1] += dpow * (a.w * dx + b.x * dy);
-          acc[2] += -0.5f * dpow * dx * dx;
-          acc[3] += -dpow * dx * dy;
-          acc[4] += -0.5f * dpow * dy * dy;
-          acc[5] += dalpha * ex;
+          const float px_ = dpow * dx, py_ = dpow * dy;
+          acc[0] += px_;
+          acc[1] += py_;
+          acc[2] += px_ * dx;
+          acc[3] += px_ * dy;
+          acc[4] += py_ * dy;
+          acc[5] += dpow;
         }
       }
       // carry the pixel state to the previous chunk (lane 63 holds the front entry)

@@ -350,8 +350,10 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
       g2d[vi * 4 + 1] = zero;
       g2d[vi * 4 + 2] = zero;
     }
-    const float g_mx = ga.x, g_my = ga.y, g_A = ga.z, g_B = ga.w;
-    const float g_C = gb.x, g_o = gb.y;
+    // moments of dL/dpower over the pixels (2D-gradient record): conic gradients now, the
+    // 2D mean's once the conic is known
+    const float s_x = ga.x, s_y = ga.y, s_p = gb.y;
+    const float g_A = -0.5f * ga.z, g_B = -ga.w, g_C = -0.5f * gb.x;
     const float* W = V.R;
     const float xh = W[0] * mu0 + W[1] * mu1 + W[2] * mu2 + V.t[0];
     const float yh = W[3] * mu0 + W[4] * mu1 + W[5] * mu2 + V.t[1];
@@ -378,6 +380,9 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     const float c = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2] + 0.3f;
     const float det = a * c - b * b;
     const float id2 = 1.0f / (det * det);
+    const float idet = 1.0f / det;
+    const float cA = c * idet, cB = -b * idet, cC = a * idet;  // the conic
+    const float g_mx = cA * s_x + cB * s_y, g_my = cB * s_x + cC * s_y;
     // conic = inverse(Sigma'): gradients w.r.t. (a, b, c) of Sigma' = [[a, b], [b, c]]
     const float g_a = (-c * c * g_A + b * c * g_B - b * b * g_C) * id2;
     const float g_b = (2.f * b * c * g_A - (a * c + b * b) * g_B + 2.f * a * b * g_C) * id2;
@@ -428,7 +433,7 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     gmu[0] += W[0] * gx + W[3] * gy + W[6] * gz;
     gmu[1] += W[1] * gx + W[4] * gy + W[7] * gz;
     gmu[2] += W[2] * gx + W[5] * gy + W[8] * gz;
-    glogit += g_o * op * (1.0f - op);
+    glogit += s_p * (1.0f - op);  // dL/do = s_p / o, do/dlogit = o (1 - o)
   }
   // M = R diag(s): scales and rotation
   float gls[3], gR[9];

@@ -369,8 +369,8 @@ k_blend_trans(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint
       const uint32_t g = emit_g[vals[rg.x + kk]];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[threadIdx.x] = r0;
-      s_b[threadIdx.x] = make_float2(r1.x, r1.y);
+      s_a[threadIdx.x] = blend_stage_a(r0);
+      s_b[threadIdx.x] = make_float2(blend_stage_c(r1.x), r1.y);
       qm = quadrant_mask(r0, r1, r2.w, tx, ty);
     }
     build_wave_lists<1, NW, NT>(qm, min(NT, end - base), s_list, s_len, s_wc);
@@ -381,9 +381,9 @@ k_blend_trans(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint
         const float4 a = s_a[j];
         const float2 b = s_b[j];
         float dx, dy;
-        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
+        const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
         if (power > 0.0f) continue;
-        const float alpha = fminf(kAlphaMax, b.y * __expf(power));
+        const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
         if (alpha < kAlphaMin) continue;
         T = T * (1.0f - alpha);
         if (T < kTMin) {  // every later chunk is dead for this pixel whatever lies in front
@@ -500,8 +500,8 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       const uint32_t g = emit_g[vals[rg.x + kk]];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[threadIdx.x] = r0;
-      s_b[threadIdx.x] = r1;
+      s_a[threadIdx.x] = blend_stage_a(r0);
+      s_b[threadIdx.x] = make_float4(blend_stage_c(r1.x), r1.y, r1.z, r1.w);
       s_c[threadIdx.x] = r2.x;
       if (want_d) s_d[threadIdx.x] = r2.y;
       qm = quadrant_mask(r0, r1, r2.w, tx, ty);
@@ -513,16 +513,17 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       const int len = s_len[wid];
       for (int jj = 0; jj < len; ++jj) {
         const int j = s_list[wid][jj];
-        const uint32_t m = s_m[j];
+        // with one pixel per lane a wave's list holds only entries that meet its quadrant
+        const uint32_t m = PX == 1 ? 1u : s_m[j];
         const float4 a = s_a[j];
         const float4 b = s_b[j];
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
-          if (!((m >> pixel_quadrant<PX>(wid, k)) & 1u) || done[k]) continue;
+          if ((PX > 1 && !((m >> pixel_quadrant<PX>(wid, k)) & 1u)) || done[k]) continue;
           float dx, dy;
-          const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
+          const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
           if (power > 0.0f) continue;
-          const float alpha = fminf(kAlphaMax, b.y * __expf(power));
+          const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
           if (alpha < kAlphaMin) continue;
           const float Tn = T[k] * (1.0f - alpha);
           if (Tn < kTMin) {
@@ -697,8 +698,8 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       const uint32_t g = emit_g[e];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[threadIdx.x] = r0;
-      s_b[threadIdx.x] = r1;
+      s_a[threadIdx.x] = blend_stage_a(r0);
+      s_b[threadIdx.x] = make_float4(blend_stage_c(r1.x), r1.y, r1.z, r1.w);
       s_c[threadIdx.x] = r2.x;
       if (MAPS) s_d[threadIdx.x] = r2.y;
       s_g[threadIdx.x] = g;
@@ -717,7 +718,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     for (int jj = s_len[wid] - 1; jj >= 0; --jj) {
       const int j = s_list[wid][jj];
       if (j > jtop) continue;
-      const uint32_t m = s_m[j];
+      const uint32_t m = PX == 1 ? 1u : s_m[j];  // (a wave's list meets its quadrant)
       const int pos = base + j;
       const float4 a = s_a[j];
       const float4 b = s_b[j];
@@ -734,12 +735,12 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
         float dx, dy;
-        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
-        const float ex = __expf(power);
+        const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
+        const float ex = blend_exp2(power);
         const float araw = b.y * ex;
         const float alpha = fminf(kAlphaMax, araw);
-        const bool on = ((m >> pixel_quadrant<PX>(wid, k)) & 1u) && pos < (int)nc[k] && power <= 0.0f &&
-                        alpha >= kAlphaMin;
+        const bool on = (PX == 1 || ((m >> pixel_quadrant<PX>(wid, k)) & 1u)) && pos < (int)nc[k] &&
+                        power <= 0.0f && alpha >= kAlphaMin;
         any = any || on;
         const float al = on ? alpha : 0.0f;
         const float oma = 1.0f - al;

@@ -132,8 +132,9 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
       e_idx = vals[rg.x + j];
       g = emit_g[e_idx];
       const float4* r = vrec + (size_t)g * 4;
-      a = r[0];
+      a = blend_stage_a(r[0]);
       b = r[1];
+      b.x = blend_stage_c(b.x);
       c2 = r[2].x;
     }
     float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -143,9 +144,9 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
       const float pxc = (float)(tx * kTile + (p & 15)) + 0.5f, pyc = (float)(ty * kTile + (p >> 4)) + 0.5f;
       float dx = 0.f, dy = 0.f, ex = 0.f, araw = 0.f, alpha = 0.f;
       if (live && j < (int)ncp) {
-        const float power = blend_power(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
+        const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
         if (power <= 0.0f) {
-          ex = __expf(power);
+          ex = blend_exp2(power);
           araw = b.y * ex;
           alpha = fminf(kAlphaMax, araw);
           if (alpha < kAlphaMin) alpha = 0.0f;

@@ -227,17 +227,34 @@ __device__ __forceinline__ bool key_tile_hit(float mx, float my, float A, float 
 }
 
 // ---------------------------------------------------------------------------------
-// Blend arithmetic shared by the forward and the backward pass. Both kernels must take
-// the same skip decisions, so the exponent is formed in one fixed sequence.
+// Blend arithmetic shared by the forward and the backward passes. Every blend kernel must
+// take the same skip decisions, so the exponent is formed in one fixed sequence of
+// explicitly rounded operations from the conic as the kernels stage it in LDS: with the
+// exponent's -1/2 and the change to base 2 folded in, e^power = 2^(A2 dx^2 + B2 dx dy +
+// C2 dy^2) for A2 = -A log2(e) / 2, B2 = -B log2(e), C2 = -C log2(e) / 2 (Eq. 4's Gaussian
+// with the 2D covariance's inverse (A, B; B, C)).
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ float blend_power(float mx, float my, float A, float B, float C,
-                                             float px, float py, float& dx, float& dy) {
-#pragma clang fp contract(off)
-  dx = px - mx;
-  dy = py - my;
-  const float q = fmaf(A * dx, dx, (C * dy) * dy);
-  return fmaf(-0.5f, q, -((B * dx) * dy));
+constexpr float kLog2e = 1.4426950408889634f;
+
+// (mx, my, A, B) of a projection record -> (mx, my, A2, B2)
+__device__ __forceinline__ float4 blend_stage_a(float4 r0) {
+  return make_float4(r0.x, r0.y, __fmul_rn(-0.5f * kLog2e, r0.z), __fmul_rn(-kLog2e, r0.w));
 }
+
+// C -> C2
+__device__ __forceinline__ float blend_stage_c(float C) { return __fmul_rn(-0.5f * kLog2e, C); }
+
+// power in base 2 at pixel centre (px, py); dx, dy = pixel centre - 2D mean
+__device__ __forceinline__ float blend_power2(float mx, float my, float A2, float B2, float C2, float px, float py,
+                                              float& dx, float& dy) {
+  dx = __fsub_rn(px, mx);
+  dy = __fsub_rn(py, my);
+  const float u = __fmaf_rn(B2, dy, __fmul_rn(A2, dx));  // A2 dx + B2 dy
+  return __fmaf_rn(u, dx, __fmul_rn(__fmul_rn(C2, dy), dy));
+}
+
+// 2^x (the hardware's base-2 exponential)
+__device__ __forceinline__ float blend_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;

@@ -714,8 +714,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       }
     }
     build_wave_lists<PX, NW, NT>(qm, cnt, s_list, s_len, s_wc);
-    const int jtop = min(cnt, (int)wmax - base) - 1;  // entries at or past the wave's max are idle
-    for (int jj = s_len[wid] - 1; jj >= 0; --jj) {
+    // entries at or past the wave's max are idle (wave-uniform bounds: a scalar loop)
+    const int jtop = __builtin_amdgcn_readfirstlane(min(cnt, (int)wmax - base) - 1);
+    for (int jj = __builtin_amdgcn_readfirstlane(s_len[wid]) - 1; jj >= 0; --jj) {
       const int j = s_list[wid][jj];
       if (j > jtop) continue;
       const uint32_t m = PX == 1 ? 1u : s_m[j];  // (a wave's list meets its quadrant)
@@ -724,9 +725,10 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       const float4 b = s_b[j];
       const float c2 = s_c[j];
       const float dep = MAPS ? s_d[j] : 0.0f;
+      // per-lane sums of the gradient terms over the lane's pixels (the first pixel sets
+      // them: adding to 0 would cost an operation, as 0 + x differs from x for x = -0)
       float gv[NG];
-#pragma unroll
-      for (int f = 0; f < NG; ++f) gv[f] = 0.f;
+      auto add = [&](int k, int f, float x) { gv[f] = k == 0 ? x : gv[f] + x; };
       bool any = false;
       // Branch-free: a pixel that does not take this entry (outside the Gaussian's quadrant
       // mask, past its last contributor, power > 0 or alpha below the cut-off) runs the same
@@ -747,9 +749,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         // transmittance in front of this Gaussian
         T[k] = on ? T[k] * __builtin_amdgcn_rcpf(oma) : T[k];
         const float w = al * T[k];
-        gv[6] += w * G0[k];
-        gv[7] += w * G1[k];
-        gv[8] += w * G2[k];
+        add(k, 6, w * G0[k]);
+        add(k, 7, w * G1[k]);
+        add(k, 8, w * G2[k]);
         float dalpha = T[k] * ((b.z - B0[k]) * G0[k] + (b.w - B1[k]) * G1[k] + (c2 - B2[k]) * G2[k]);
         B0[k] = al * b.z + oma * B0[k];
         B1[k] = al * b.w + oma * B1[k];
@@ -758,19 +760,19 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
           dalpha += T[k] * ((dep - BD[k]) * gD[k] + (1.0f - BO[k]) * gO[k]);
           BD[k] = al * dep + oma * BD[k];
           BO[k] = al + oma * BO[k];
-          gv[9] += w * gD[k];
+          add(k, 9, w * gD[k]);
         }
         // dL/dpower = dL/dalpha * alpha (no gradient through the clamp at kAlphaMax); its
         // moments over the pixels, which the projection backward turns into the 2D mean,
         // conic and opacity gradients
         const float dpow = (on && araw <= kAlphaMax) ? dalpha * al : 0.0f;
         const float px_ = dpow * dx, py_ = dpow * dy;
-        gv[0] += px_;
-        gv[1] += py_;
-        gv[2] += px_ * dx;
-        gv[3] += px_ * dy;
-        gv[4] += py_ * dy;
-        gv[5] += dpow;
+        add(k, 0, px_);
+        add(k, 1, py_);
+        add(k, 2, px_ * dx);
+        add(k, 3, px_ * dy);
+        add(k, 4, py_ * dy);
+        add(k, 5, dpow);
       }
       if (!__any(any)) continue;
       // terms 0..7 transposed (lanes 8..15 end with the totals), the rest by DPP rows

@@ -99,41 +99,54 @@ __device__ __forceinline__ float wave_sum_to_63(float x) {
   return x;
 }
 
+// dst = src(lane - n) + src on the lanes of banks 1 and 3 (lane bit 2 set; n = 4) or of
+// banks 2 and 3 (lane bit 3 set; n = 8) of every row of 16; the other lanes keep dst. DPP's
+// bank mask has no intrinsic form that keeps dst, hence the instruction is written out; the
+// two wait states a DPP read of a freshly written register needs come first.
+__device__ __forceinline__ void add_from_below4(float& dst, float src) {
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_shr:4 row_mask:0xf bank_mask:0xa" : "+v"(dst) : "v"(src));
+}
+__device__ __forceinline__ void add_from_below8(float& dst, float src) {
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xc" : "+v"(dst) : "v"(src));
+}
+
 // Sums over the wave of eight values at once, transposing while reducing: each exchange
 // step halves the values a lane carries (the lane keeps one half, its partner the other),
-// so 8 values cost 4 + 2 + 1 exchanges instead of 8 per step. Steps: lane ^ 1 and lane ^ 2
-// (DPP quad_perm), lane ^ 4 (ds_swizzle), then the single value over lane bit 3 (DPP
-// row_shr:8, valid in lanes 8..15 of each row of 16) and lane bits 4, 5 (shuffles). On
-// return lane 8 + j of each row holds the wave total of v[rev3(j)], rev3 reversing the
-// three bits of j; other lanes hold partial sums.
+// so 8 values cost 4 + 2 + 1 exchanges instead of 8 per step. The steps over lane bits 2
+// and 3 (partners in the same row of 16) need no selects: one DPP add from the lane above
+// writes every lane, a bank-masked DPP add from the lane below then overwrites the lanes
+// that keep the other half. Then lane bit 0 (a select pair and a quad_perm add), lane bit
+// 1 (quad_perm) and lane bits 4, 5 (shuffles). On return lane L holds the wave total of
+// v[term_of_lane(L)].
 __device__ __forceinline__ float wave_sum8_transposed(const float (&v)[8], int lane) {
-  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+#pragma clang fp contract(off)  // each first add must stay a DPP add, not fuse with a product
   float w[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float send = b0 ? v[k] : v[k + 4];
-    const float keep = b0 ? v[k + 4] : v[k];
-    w[k] = keep + dpp_f<0xB1, 0xf>(send);  // from lane ^ 1
+  for (int k = 0; k < 4; ++k) {  // lane bit 2: keep v[k] (bit clear) or v[k + 4]
+    w[k] = v[k] + dpp_f<0x104, 0xf>(v[k]);  // row_shl:4, from lane + 4
+    add_from_below4(w[k], v[k + 4]);
   }
   float x[2];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float send = b1 ? w[k] : w[k + 2];
-    const float keep = b1 ? w[k + 2] : w[k];
-    x[k] = keep + dpp_f<0x4E, 0xf>(send);  // from lane ^ 2
+  for (int k = 0; k < 2; ++k) {  // lane bit 3: keep w[k] or w[k + 2]
+    x[k] = w[k] + dpp_f<0x108, 0xf>(w[k]);  // row_shl:8, from lane + 8
+    add_from_below8(x[k], w[k + 2]);
   }
-  const float send = b2 ? x[0] : x[1];
-  const float keep = b2 ? x[1] : x[0];
-  // ds_swizzle bit-mask mode: and 0x1f, or 0, xor 4 (from lane ^ 4 within 32 lanes)
-  float y = keep + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x101F));
-  y += dpp_f<0x118, 0xf>(y);  // row_shr:8: lanes 8..15 of a row add lanes 0..7
+  const bool b0 = lane & 1;  // lane bit 0: keep x[0] or x[1]
+  const float send = b0 ? x[0] : x[1];
+  const float keep = b0 ? x[1] : x[0];
+  float y = keep + dpp_f<0xB1, 0xf>(send);  // quad_perm [1,0,3,2]: from lane ^ 1
+  y += dpp_f<0x4E, 0xf>(y);                 // quad_perm [2,3,0,1]: lane bit 1
   y += __shfl_xor(y, 16, 64);
   y += __shfl_xor(y, 32, 64);
   return y;
 }
 
-// index of the value whose total lane 8 + j (j = lane & 7) holds after wave_sum8_transposed
-__device__ __forceinline__ int rev3(int j) { return ((j & 1) << 2) | (j & 2) | ((j >> 2) & 1); }
+// index of the value whose total lane L holds after wave_sum8_transposed: lane bits 2, 3, 0
+// give bits 2, 1, 0 of the index (lanes 0, 1, 4, 5, 8, 9, 12, 13 hold the eight totals)
+__device__ __forceinline__ int term_of_lane(int lane) {
+  return (((lane >> 2) & 1) << 2) | (((lane >> 3) & 1) << 1) | (lane & 1);
+}
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 #pragma unroll
@@ -775,15 +788,15 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         add(k, 5, dpow);
       }
       if (!__any(any)) continue;
-      // terms 0..7 transposed (lanes 8..15 end with the totals), the rest by DPP rows
+      // terms 0..7 transposed (eight lanes of row 0 end with the totals), the rest by DPP rows
       float g8[8];
 #pragma unroll
       for (int f = 0; f < 8; ++f) g8[f] = gv[f];
       const float tot = wave_sum8_transposed(g8, lane);
 #pragma unroll
       for (int f = 8; f < NG; ++f) gv[f] = wave_sum_to_63(gv[f]);
-      if (lane >= 8 && lane < 16) {
-        const int f = rev3(lane & 7);
+      if (lane < 16 && !(lane & 2)) {
+        const int f = term_of_lane(lane);
         if (DET)
           s_part[wid][j][f] = tot;
         else if (tot != 0.0f)

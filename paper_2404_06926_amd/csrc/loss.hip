@@ -30,9 +30,14 @@ constexpr int kBH = kTH + 2 * kR;      // 26
 constexpr int kAW = kTW + 4 * kR;      // 52: inputs
 constexpr int kAH = kTH + 4 * kR;      // 36
 constexpr int kHRun = 6;               // horizontal moment pass: outputs per lane (42 = 7 x 6)
-constexpr int kVRun = 7;               // vertical moment pass: rows per lane (26 = 3 x 7 + 5)
-constexpr int kDRun = 8;               // horizontal derivative pass: outputs per lane (32 = 4 x 8)
+constexpr int kVRun = 5;               // vertical moment pass: rows per lane (26 = 5 x 5 + 1)
+constexpr int kDRun = 4;               // horizontal derivative pass: outputs per lane (32 = 8 x 4)
 constexpr int kGRun = 2;               // vertical derivative pass: rows per lane (16 = 8 x 2)
+// every pass's lanes fit the 256-thread block
+static_assert(kBW % kHRun == 0 && kAH * (kBW / kHRun) <= 256, "horizontal moment pass");
+static_assert(kBW * ((kBH + kVRun - 1) / kVRun) <= 256, "vertical moment pass");
+static_assert(kTW % kDRun == 0 && kBH * (kTW / kDRun) <= 256, "horizontal derivative pass");
+static_assert(kTH % kGRun == 0 && kTW * (kTH / kGRun) == 256, "vertical derivative pass");
 
 // Normalised 1-D Gaussian window (sigma 1.5), passed by value to the kernel.
 struct Win {
@@ -171,11 +176,13 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
           const float num = A1 * A2, den = B1 * B2;
           const float dnum = 2.f * my * A2 - 2.f * my * A1;
           const float dden = 2.f * mx * B2 - 2.f * mx * B1;
-          dmu = s_ssim * (dnum * den - num * dden) / (den * den);
-          dxx = s_ssim * (-num * B1 / (den * den));
-          dxy = s_ssim * (2.f * A1 / den);
+          // one division: with q = num / den (the SSIM value), d(q)/d. = (dnum - q dden) / den
+          const float inv = 1.0f / den, q = num * inv, si = s_ssim * inv;
+          dmu = si * (dnum - q * dden);
+          dxx = -si * q * B1;
+          dxy = 2.f * si * A1;
           // SSIM of the tile's own pixels (the margins belong to the neighbours)
-          if (rb >= kR && rb < kR + kTH && c >= kR && c < kR + kTW) ssum += num / den;
+          if (rb >= kR && rb < kR + kTH && c >= kR && c < kR + kTW) ssum += q;
         }
         L.d[0][rb][c] = dmu;
         L.d[1][rb][c] = dxx;

@@ -45,8 +45,8 @@ METRIC = "mapping iters/s (fwd+bwd+Adam) @1M Gaussians 1280×720; p50/p99 keyfra
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3          # 256 CU x 128 FP32 lanes x 2 (FMA) x 2.4 GHz
 # FLOPs per (pixel, list entry) pair, counted from the blend arithmetic
-FWD_FLOPS_PER_PAIR = 22
-BWD_FLOPS_PER_PAIR = 56
+FWD_FLOPS_PER_PAIR = 20
+BWD_FLOPS_PER_PAIR = 46
 
 
 def split_config(args):

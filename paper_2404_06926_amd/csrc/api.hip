@@ -602,13 +602,15 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   {
     StageTimer t(m, s, GS_STAGE_PROJECT);
     GS_HIP(fill_u32(big_n, 0u, 1, s));
+    // on the side: the pair count the depth sort reads, and the tile ranges (with the split
+    // counters after them) zeroed for this render
+    const ProjSide side{m->d_nvn, (uint32_t)vn, (uint32_t*)m->ranges.ptr, 2 * tiles + 2};
     GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0],
-                           (uint32_t*)m->big_list.ptr, big_n, s));
+                           (uint32_t*)m->big_list.ptr, big_n, side, s));
   }
   int dwhich = 0;
   {
     StageTimer t(m, s, GS_STAGE_DEPTH_SORT);
-    GS_HIP(fill_u32(m->d_nvn, (uint32_t)vn, 1, s));
     GS_HIP(radix_sort_u32(dkey, dval, m->d_nvn, vn, 32, (uint32_t*)m->sort_tmp.ptr, &dwhich, s, true));
   }
   const uint32_t* order = dval[dwhich];
@@ -647,7 +649,6 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint2* ranges = (uint2*)m->ranges.ptr;
   {
     StageTimer t(m, s, GS_STAGE_RANGES);
-    GS_HIP(fill_u32((uint32_t*)ranges, 0u, 2 * tiles + 2, s));
     GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, s));
     m->last_sp = split_arg(m, tiles);
     GS_HIP(split_items(ranges, (int32_t)tiles, m->last_sp, s));
@@ -742,17 +743,21 @@ gs_status gs_adam_step(gs_map* m, int32_t ne, float* const* exposure_states, voi
   return GS_OK;
 }
 
-gs_status gs_loss(gs_map* m, const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
-                  float* dL_dout, void* stream) {
-  g_err.clear();
+static gs_status loss_impl(gs_map* m, const float* out, const float* gt, int32_t H, int32_t W, float lambda,
+                           float* loss_dev, float* dL_dout, const StepPrep* prep, hipStream_t s) {
   if (!m || !out || !gt || !loss_dev || !dL_dout) return fail(GS_ERR_INVALID, "NULL argument");
   if (H < 1 || W < 1 || H > 16384 || W > 16384) return fail(GS_ERR_INVALID, "image size out of range");
   if (!(lambda >= 0.f && lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
-  hipStream_t s = (hipStream_t)stream;
   GS_TRY(ensure(m, m->loss_tmp, (size_t)loss_temp_floats(H, W) * 4, s));
   StageTimer t(m, s, GS_STAGE_LOSS);
-  GS_HIP(ssim_loss(out, gt, H, W, lambda, (float*)m->loss_tmp.ptr, loss_dev, dL_dout, s));
+  GS_HIP(ssim_loss(out, gt, H, W, lambda, (float*)m->loss_tmp.ptr, loss_dev, dL_dout, prep, s));
   return GS_OK;
+}
+
+gs_status gs_loss(gs_map* m, const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
+                  float* dL_dout, void* stream) {
+  g_err.clear();
+  return loss_impl(m, out, gt, H, W, lambda, loss_dev, dL_dout, nullptr, (hipStream_t)stream);
 }
 
 gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image, int64_t n_points, const float* xyz,
@@ -945,9 +950,13 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
     eg[v] = exposure_states[v] + 12;
   }
   GS_TRY(gs_render(m, nv, vv, frames, stream));
+  hipStream_t s = (hipStream_t)stream;
+  const gs_map_desc& d = m->desc;
+  // in a fused step the last loss reduction also advances the Adam step counter
+  const StepPrep prep{m->d_step, m->d_bc, d.beta1, d.beta2};
   for (int v = 0; v < nv; ++v)
-    GS_TRY(gs_loss(m, frames[v].rgb, targets[v], vv[v].height, vv[v].width, lambda, loss_dev + v, dl_drgb[v],
-                   stream));
+    GS_TRY(loss_impl(m, frames[v].rgb, targets[v], vv[v].height, vv[v].width, lambda, loss_dev + v, dl_drgb[v],
+                     m->fused_step && v == nv - 1 ? &prep : nullptr, s));
   if (!m->fused_step) {
     GS_TRY(gs_render_backward(m, nv, dl, nullptr, nullptr, eg, stream));
     GS_TRY(gs_adam_step(m, nv, exposure_states, stream));
@@ -955,9 +964,6 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   }
   // one step: the gradient is complete after this backward, so Adam runs inside the
   // projection backward (no gradient planes written and read back)
-  hipStream_t s = (hipStream_t)stream;
-  const gs_map_desc& d = m->desc;
-  GS_HIP(adam_prepare(m->d_step, m->d_bc, d.beta1, d.beta2, s));
   AdamArg ad{};
   ad.lr = lr_table(m);
   ad.m = m->buf + 2 * (int64_t)m->F * m->cap;

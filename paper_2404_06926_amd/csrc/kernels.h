@@ -28,10 +28,18 @@ struct AdamArg {
 };
 
 // projection (project.hip)
+// Small writes the projection's threads make on the side, saving launches of their own:
+// *nvn = nvn_value (if nvn is set) and zero[0 .. n_zero) = 0.
+struct ProjSide {
+  uint32_t* nvn;
+  uint32_t nvn_value;
+  uint32_t* zero;
+  int64_t n_zero;
+};
 // big_list / big_n (zeroed before): pairs whose tile rectangle exceeds 64 tiles.
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                            float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* big_list,
-                           uint32_t* big_n, hipStream_t s);
+                           uint32_t* big_n, const ProjSide& side, hipStream_t s);
 // With inst_grad != nullptr the 2D gradients are the sums, in emission order, of the
 // instance records [inst_off[vi], inst_off[vi] + counts[vi]); otherwise they come from g2d.
 // With adam != nullptr the Adam update of each row is applied in the same kernel (one step).
@@ -105,8 +113,15 @@ hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_
 
 // loss (loss.hip)
 int64_t loss_temp_floats(int H, int W);
+// With step != nullptr the reduction launch also advances the Adam step counter and its
+// bias corrections (as adam_prepare), saving that launch in a fused step.
+struct StepPrep {
+  int64_t* step;
+  float* bc;
+  float beta1, beta2;
+};
 hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,
-                     float* gout, hipStream_t s);
+                     float* gout, const StepPrep* prep, hipStream_t s);
 
 // optimiser and map maintenance (adam.hip)
 hipError_t adam_step(float* buf, int64_t cap, int32_t F, int32_t N, const uint8_t* vis, const LrArg& lr,

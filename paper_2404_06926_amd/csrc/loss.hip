@@ -258,8 +258,15 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
 }
 
 __global__ void __launch_bounds__(256)
-k_loss_reduce(const float* __restrict__ part, int64_t nb, int64_t P, float lambda, float* __restrict__ loss) {
+k_loss_reduce(const float* __restrict__ part, int64_t nb, int64_t P, float lambda, float* __restrict__ loss,
+              StepPrep prep) {
   __shared__ double s[2][256];
+  if (prep.step && threadIdx.x == 0) {  // t += 1 and the bias corrections of step t
+    const int64_t t = prep.step[0] + 1;
+    prep.step[0] = t;
+    prep.bc[0] = (float)(1.0 - pow((double)prep.beta1, (double)t));
+    prep.bc[1] = (float)(1.0 - pow((double)prep.beta2, (double)t));
+  }
   double a = 0.0, b = 0.0;
   for (int64_t k = threadIdx.x; k < nb; k += 256) {
     a += part[2 * k];
@@ -287,14 +294,15 @@ int64_t loss_temp_floats(int H, int W) {
 }
 
 hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,
-                     float* gout, hipStream_t s) {
+                     float* gout, const StepPrep* prep, hipStream_t s) {
   const Win win = make_window();
   const int64_t P = (int64_t)H * W;
   float* part = temp;
   const dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH);
   const int64_t nb = (int64_t)grid.x * grid.y;
   hipLaunchKernelGGL(k_ssim_tile, grid, dim3(256), 0, s, win, out, gt, H, W, lambda, gout, part);
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, part, nb, P, lambda, loss);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, part, nb, P, lambda, loss,
+                     prep ? *prep : StepPrep{nullptr, nullptr, 0.f, 0.f});
   return hipGetLastError();
 }
 

@@ -23,10 +23,12 @@ template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
               float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey,
-              uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_n) {
+              uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_n, ProjSide side) {
   // lanes past the end stay (reading row N - 1) so that the whole wave takes part in the
   // cooperative tile counting below; they write nothing
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (side.nvn && i0 == 0) *side.nvn = side.nvn_value;
+  for (int64_t z = i0; z < side.n_zero; z += (int64_t)gridDim.x * blockDim.x) side.zero[z] = 0u;
   const bool valid = i0 < N;
   const int i = valid ? i0 : N - 1;
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -473,9 +475,9 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
 template <int DEG>
 static hipError_t launch_fwd(const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                              float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* big_list,
-                             uint32_t* big_n, hipStream_t s) {
+                             uint32_t* big_n, const ProjSide& side, hipStream_t s) {
   hipLaunchKernelGGL(k_project_fwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, cap, N, va,
-                     near_z, rec, counts, dkey, big_list, big_n);
+                     near_z, rec, counts, dkey, big_list, big_n, side);
   return hipGetLastError();
 }
 
@@ -506,13 +508,18 @@ static hipError_t launch_bwd(float* P, float* G, int64_t cap, int32_t N, const V
 
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va,
                            float near_z, float4* rec, uint32_t* counts, uint32_t* dkey,
-                           uint32_t* big_list, uint32_t* big_n, hipStream_t s) {
-  if (N <= 0) return hipSuccess;
+                           uint32_t* big_list, uint32_t* big_n, const ProjSide& side, hipStream_t s) {
+  if (N <= 0) {  // no projection launch: the side writes get their own
+    hipError_t e = hipSuccess;
+    if (side.nvn) e = fill_u32(side.nvn, side.nvn_value, 1, s);
+    if (e == hipSuccess && side.n_zero > 0) e = fill_u32(side.zero, 0u, side.n_zero, s);
+    return e;
+  }
   switch (deg) {
-    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, s);
-    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, s);
-    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, s);
-    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, s);
+    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
+    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
+    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
+    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
   }
 }
 

@@ -580,7 +580,10 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   }
 }
 
-// DET = false: each wave's per-Gaussian sums go to g2d with float atomics.
+// DET = false: the waves' per-Gaussian sums of a batch meet in LDS (LDS float atomics), and
+// after the batch one float atomic per entry and term goes to g2d, with the terms of an
+// entry on neighbouring lanes (one 64-B record per entry): a Gaussian that reaches several
+// quadrants of the tile costs one set of global atomics, not one per wave.
 // DET = true: the waves' sums are added in wave order in LDS and every instance's
 // gradient is written to inst_grad[emission index]; the exposure gradient of each tile is
 // written to exp_part[tile] for a fixed-order reduction. No atomics, so the result does not
@@ -603,6 +606,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   __shared__ uint32_t s_g[NT];
   __shared__ uint32_t s_e[DET ? NT : 1];
   __shared__ float s_part[DET ? NW : 1][DET ? NT : 1][NG];
+  __shared__ float s_acc[DET ? 1 : NT][NG];  // batch sums (DET = false), zero between batches
   __shared__ uint8_t s_m[NT];
   __shared__ uint8_t s_list[NW][NT];   // per-wave entry lists of the batch
   __shared__ int s_len[NW];
@@ -611,6 +615,8 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   __shared__ uint32_t s_wmax[NW];
   BlendItem it;
   if (!blend_item(sp, ranges, it)) return;
+  if (!DET)
+    for (int k = (int)threadIdx.x; k < NT * NG; k += NT) (&s_acc[0][0])[k] = 0.0f;
   const int tile = it.tile;
   const bool split = it.slot0 != kNoSlot;
   const uint32_t slot = it.slot0 + (uint32_t)it.c;
@@ -800,7 +806,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         if (DET)
           s_part[wid][j][f] = tot;
         else if (tot != 0.0f)
-          unsafeAtomicAdd(vg + (size_t)s_g[j] * kGradFloats + f, tot);
+          __hip_atomic_fetch_add(&s_acc[j][f], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       if (lane == 63) {
 #pragma unroll
@@ -808,7 +814,19 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
           if (DET)
             s_part[wid][j][f] = gv[f];
           else if (gv[f] != 0.0f)
-            unsafeAtomicAdd(vg + (size_t)s_g[j] * kGradFloats + f, gv[f]);
+            __hip_atomic_fetch_add(&s_acc[j][f], gv[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+    if (!DET) {
+      // the batch's sums to g2d; each read slot is cleared for the next batch
+      __syncthreads();
+      for (int idx = (int)threadIdx.x; idx < cnt * NG; idx += NT) {
+        const int e = idx / NG, f = idx - e * NG;
+        const float val = s_acc[e][f];
+        if (val != 0.0f) {
+          unsafeAtomicAdd(vg + (size_t)s_g[e] * kGradFloats + f, val);
+          s_acc[e][f] = 0.0f;
         }
       }
     }

@@ -44,7 +44,11 @@ sys.path.insert(0, ROOT)
 METRIC = "mapping iters/s (fwd+bwd+Adam) @1M Gaussians 1280×720; p50/p99 keyframe latency"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3          # 256 CU x 128 FP32 lanes x 2 (FMA) x 2.4 GHz
-# FLOPs per (pixel, list entry) pair, counted from the blend arithmetic
+# FLOPs per (pixel, list entry) pair, counted from the blend arithmetic up to the pixel's
+# last contributor. Forward: offset 2, quadratic 6, exp 1, alpha 2, cut-off and stop
+# tests 3, T (1 - alpha) 2, colour 4. Backward: the forward's 9 for alpha, T recovery 2,
+# colour gradient 4, dL/dalpha 9, colour-behind update 6, dL/dpower and its five moments
+# 6, share of the wave reduction 10.
 FWD_FLOPS_PER_PAIR = 20
 BWD_FLOPS_PER_PAIR = 46
 
@@ -524,8 +528,8 @@ def main():
 
     per = {k: (v[0] / max(v[1], 1)) for k, v in stages.items() if v[1] > 0}
     # algorithmic work per launch of each stage: bytes the method must move (all stages)
-    # and FLOPs (blend kernels, bound by the vector ALU); per-unit figures in the design doc
-    atomics = 36.0 * n_inst * (4 // bpx)   # one 9-float atomic add per wave and instance
+    # and FLOPs (blend kernels, bound by the vector ALU)
+    atomics = 36.0 * n_inst   # nine float atomics per instance (the waves' sums meet in LDS)
     # (the headline's adam stage is fused into project_backward: no separate pass)
     work = {
         "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + 64.0 * n_vis + 8.0 * V * args.n, 0),

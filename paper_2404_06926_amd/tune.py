@@ -61,8 +61,8 @@ def autotune(m, cams: Sequence, targets: Sequence, exposures: Optional[Sequence]
     from . import gslic
     torch = gslic._torch()
     stream = torch.cuda.current_stream()
-    configs = list(configs or candidates())
-    if not configs or iters < 1 or rounds < 1:
+    cands = list(configs or candidates())
+    if not cands or iters < 1 or rounds < 1:
         raise ValueError("autotune needs at least one configuration, iteration and round")
     grads = [torch.empty(3, c.height, c.width, device=m.device) for c in cams]
     # with exposures the step also differentiates them, which changes the blend backward
@@ -76,13 +76,13 @@ def autotune(m, cams: Sequence, targets: Sequence, exposures: Optional[Sequence]
             m.loss(frames[k].rgb, targets[k], lam, grad_out=grads[k])
         m.render_backward(grads, dexp)
 
-    apply(m, configs[0])
+    apply(m, cands[0])
     for _ in range(warmup):
         one()
-    samples: Dict[Config, List[float]] = {c: [] for c in configs}
-    n = len(configs)
+    samples: Dict[Config, List[float]] = {c: [] for c in cands}
+    n = len(cands)
     for r in range(rounds):
-        order = configs[r % n:] + configs[:r % n]
+        order = cands[r % n:] + cands[:r % n]
         if r % 2:
             order.reverse()
         for cfg in order:
@@ -114,8 +114,8 @@ def autotune_step(m, cams: Sequence, frames: Sequence, targets: Sequence, exposu
     from . import gslic
     torch = gslic._torch()
     stream = torch.cuda.current_stream()
-    configs = list(configs or candidates())
-    if not configs or steps < 1 or rounds < 1:
+    cands = list(configs or candidates())
+    if not cands or steps < 1 or rounds < 1:
         raise ValueError("autotune_step needs at least one configuration, step and round")
     t0 = m.step_count
     snap = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in exposure_states)]
@@ -134,13 +134,13 @@ def autotune_step(m, cams: Sequence, frames: Sequence, targets: Sequence, exposu
     def one():
         m.step(cams, frames, targets, exposure_states, grads, loss_out, lam=lam)
 
-    apply(m, configs[0])
+    apply(m, cands[0])
     for _ in range(warmup):
         one()
-    samples: Dict[Config, List[float]] = {c: [] for c in configs}
-    n = len(configs)
+    samples: Dict[Config, List[float]] = {c: [] for c in cands}
+    n = len(cands)
     for r in range(rounds):
-        order = configs[r % n:] + configs[:r % n]
+        order = cands[r % n:] + cands[:r % n]
         if r % 2:
             order.reverse()
         for cfg in order:

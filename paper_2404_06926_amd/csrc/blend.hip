@@ -582,7 +582,7 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
 
 // DET = false: the waves' per-Gaussian sums of a batch meet in LDS (LDS float atomics), and
 // after the batch one float atomic per entry and term goes to g2d, with the terms of an
-// entry on neighbouring lanes (one 64-B record per entry): a Gaussian that reaches several
+// entry on neighbouring lanes (one 48-B record per entry): a Gaussian that reaches several
 // quadrants of the tile costs one set of global atomics, not one per wave.
 // DET = true: the waves' sums are added in wave order in LDS and every instance's
 // gradient is written to inst_grad[emission index]; the exposure gradient of each tile is

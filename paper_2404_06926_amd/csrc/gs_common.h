@@ -12,15 +12,15 @@ namespace gs {
 constexpr int kTile = GS_TILE;        // 16x16 pixel tiles
 constexpr int kMaxViews = GS_MAX_VIEWS;
 constexpr int kRecFloats = 16;        // per (view, Gaussian) projection record, 64 B
-// per (view, Gaussian) 2D-gradient record, 64 B. With g = dL/dpower = dL/dalpha * alpha
+// per (view, Gaussian) 2D-gradient record, 48 B. With g = dL/dpower = dL/dalpha * alpha
 // at each pixel the Gaussian reaches (dx, dy = pixel centre - 2D mean; none where alpha is
 // clamped), sums over the pixels: [0] g dx  [1] g dy  [2] g dx^2  [3] g dx dy  [4] g dy^2
 // [5] g, then [6..8] dL/dcolour, [9] dL/d(camera-frame depth) (depth-map gradient),
-// [10..15] unused. Since power = -(A dx^2 + C dy^2) / 2 - B dx dy and alpha = o e^power,
+// [10..11] unused. Since power = -(A dx^2 + C dy^2) / 2 - B dx dy and alpha = o e^power,
 // the projection backward forms dL/dmean2d = conic (g dx, g dy), dL/d(A, B, C) =
 // (-[2] / 2, -[3], -[4] / 2) and dL/dlogit = [5] (1 - o): the blend keeps five products
 // per pixel and leaves the per-Gaussian factors to one pass.
-constexpr int kGradFloats = 16;
+constexpr int kGradFloats = 12;  // 48 B: records packed back to back, read as 3 x float4
 
 // Per-view constants, passed by value inside ViewsArg (so a captured graph keeps them).
 struct ViewDev {

@@ -115,8 +115,8 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
   }
 }
 
-// Adjoint of the projection. Input: per (view, Gaussian) gradients of
-// (mean2d x, y, conic A, B, C, opacity, colour r, g, b) in 64-B records (consumed and
+// Adjoint of the projection. Input: per (view, Gaussian) 2D-gradient records of 48 B (the
+// moments of dL/dpower over the pixels, dL/dcolour and dL/d(camera-frame depth); consumed and
 // reset to zero here, so the buffer is clean for the next backward), or, in deterministic
 // mode, the sums of the pair's per-instance records in emission order. Output: gradients
 // added to the parameter planes, summed over views; vis[i] = 1 for Gaussians with a tile
@@ -149,9 +149,9 @@ __device__ __forceinline__ void pair_grad(size_t vi, const uint32_t* __restrict_
       gc.y += c.y;
     }
   } else {
-    ga = g2d[vi * 4 + 0];
-    gb = g2d[vi * 4 + 1];
-    gc = g2d[vi * 4 + 2];
+    ga = g2d[vi * 3 + 0];
+    gb = g2d[vi * 3 + 1];
+    gc = g2d[vi * 3 + 2];
   }
 }
 
@@ -348,9 +348,9 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     pair_grad(vi, counts, g2d, inst_grad, inst_off, ga, gb, gc);
     if (!inst_grad) {
       const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-      g2d[vi * 4 + 0] = zero;
-      g2d[vi * 4 + 1] = zero;
-      g2d[vi * 4 + 2] = zero;
+      g2d[vi * 3 + 0] = zero;
+      g2d[vi * 3 + 1] = zero;
+      g2d[vi * 3 + 2] = zero;
     }
     // moments of dL/dpower over the pixels (2D-gradient record): conic gradients now, the
     // 2D mean's once the conic is known

@@ -50,13 +50,37 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     int area = 0;
     if (valid && kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) area = (r[2] - r[0] + 1) * (r[3] - r[1] + 1);
     if (area > 0 && area <= kSerialTiles) {
-      int k = 0;
-      for (int ty = r[1]; ty <= r[3]; ++ty)
-        for (int tx = r[0]; tx <= r[2]; ++tx, ++k)
-          if (key_tile_hit(kp.mx, kp.my, kp.A, kp.B, kp.C, kp.thr, tx, ty)) {
-            ++cnt;
-            hits |= 1ull << k;
-          }
+      // the shorter side of the rectangle (at most 4 tiles, as w h <= 16) is prepared once,
+      // the longer one walked: w + h divisions in all
+      const int w = r[2] - r[0] + 1, h = r[3] - r[1] + 1;
+      TileSide sd[4];
+      if (h <= 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < h) sd[j] = tile_row(kp.my, kp.A, kp.B, r[1] + j);
+        for (int i = 0; i < w; ++i) {
+          const TileSide c = tile_col(kp.mx, kp.B, kp.C, r[0] + i);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < h && tile_hit_sides(kp.A, kp.B, kp.C, kp.thr, c, sd[j])) {
+              ++cnt;
+              hits |= 1ull << (j * w + i);
+            }
+        }
+      } else {  // w <= 4
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < w) sd[i] = tile_col(kp.mx, kp.B, kp.C, r[0] + i);
+        for (int j = 0; j < h; ++j) {
+          const TileSide row = tile_row(kp.my, kp.A, kp.B, r[1] + j);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (i < w && tile_hit_sides(kp.A, kp.B, kp.C, kp.thr, sd[i], row)) {
+              ++cnt;
+              hits |= 1ull << (j * w + i);
+            }
+        }
+      }
     }
     // larger rectangles: the whole wave evaluates one lane's rectangle, 64 tiles per step,
     // so no lane loops over hundreds of tiles while the others wait

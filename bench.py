@@ -663,7 +663,7 @@ def main():
         # fused with Adam: read and write parameters, m and v (3 x 4F B each way), read and
         # clear the 48-B 2D-gradient record, read the tile counts
         "project_backward": ("hbm", 24.0 * F * n_vis + 96.0 * n_vis + 4.0 * V * args.n, 0),
-        "adam": ("hbm", 2 * 4.0 * 48 * V, 0),   # exposures only: Gaussian rows update in project_backward
+        "adam": ("hbm", 2 * 4.0 * 48 * V, 0),   # exposures of the separate path (a fused step updates them in project_backward)
     }
     names = {"blend_backward": (f"k_blend_bwd<{bpx},false,false>" if args.bwd_mode == 0 else "k_blend_bwd_pg<false>"),
              "blend": f"k_blend_fwd<{fpx},false>",

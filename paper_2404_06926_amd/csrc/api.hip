@@ -973,16 +973,12 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   ad.beta2 = d.beta2;
   ad.eps = d.eps;
   ad.grads_clean = m->grads_dirty ? 0 : 1;
+  // the views' exposures (each view's exposure is its state) are updated by the same kernel
+  ad.n_exp = nv;
+  ad.lr_exp = d.lr_exposure;
   m->step_assumed_clean = ad.grads_clean != 0;
   GS_TRY(backward_impl(m, nv, dl, nullptr, nullptr, eg, &ad, s));
   m->grads_dirty = false;  // the fused update cleared every accumulated gradient it read
-  ExpArg ea{};
-  ea.n = nv;
-  for (int v = 0; v < nv; ++v) ea.p[v] = exposure_states[v];
-  {
-    StageTimer t(m, s, GS_STAGE_ADAM);
-    GS_HIP(adam_exposures(ea, m->d_bc, d.lr_exposure, d.beta1, d.beta2, d.eps, s));
-  }
   m->h_step += 1;
   return GS_OK;
 }

@@ -25,6 +25,10 @@ struct AdamArg {
   const float* bc;   // device bias corrections 1 - beta1^t, 1 - beta2^t
   float beta1, beta2, eps;
   int32_t grads_clean;  // the gradient planes are known to be zero: do not read them
+  // the exposures of views 0 .. n_exp - 1 are updated too (by the first block); in a fused
+  // step view e's exposure pointer is its 48-float state [E | gradient | m | v]
+  int32_t n_exp;
+  float lr_exp;
 };
 
 // projection (project.hip)

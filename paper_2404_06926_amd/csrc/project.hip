@@ -239,6 +239,18 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float s_gsh[MULTI ? 3 * K : 1][MULTI ? 256 : 1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (FUSED && blockIdx.x == 0 && (int)threadIdx.x < 12 * ad.n_exp) {
+    // the views' exposures (their gradients are complete once the blend backward is done),
+    // as the separate exposure update does, in place of a launch of its own
+    float* st = const_cast<float*>(va.v[threadIdx.x / 12].exposure);
+    const int k = (int)threadIdx.x % 12;
+    float pp = st[k], mm = st[24 + k], vv = st[36 + k];
+    adam_update(pp, mm, vv, st[12 + k], ad.lr_exp, ad.beta1, ad.beta2, ad.eps, ad.bc[0], ad.bc[1]);
+    st[k] = pp;
+    st[24 + k] = mm;
+    st[36 + k] = vv;
+    st[12 + k] = 0.0f;
+  }
   if (i >= N) return;
   // non-fused: gradient g of plane f added to the gradient planes
   const uint32_t lo = (uint32_t)i * 4u;  // byte offset of the row in every plane (cap < 2^30)
@@ -550,7 +562,13 @@ hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, cons
 hipError_t project_backward(int deg, float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                             const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
                             uint8_t* vis, const AdamArg* adam, hipStream_t s) {
-  if (N <= 0) return hipSuccess;
+  if (N <= 0) {  // no launch: the exposures get the separate update
+    if (!adam || adam->n_exp <= 0) return hipSuccess;
+    ExpArg ea{};
+    ea.n = adam->n_exp;
+    for (int e = 0; e < ea.n; ++e) ea.p[e] = const_cast<float*>(va.v[e].exposure);
+    return adam_exposures(ea, adam->bc, adam->lr_exp, adam->beta1, adam->beta2, adam->eps, s);
+  }
   switch (deg) {
     case 0: return launch_bwd<0>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
     case 1: return launch_bwd<1>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);

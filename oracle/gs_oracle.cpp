@@ -654,10 +654,14 @@ void or_render_tiled(int W, int H, int64_t tile_base, const int64_t* ranges /*gl
     ncontrib[pix] = nc;
     tie[pix] = tf;
     if (ncon) ncon[pix] = k;
-    if (sig) {  // order-independent signature of the contributor set (splitmix64 of ids)
+    if (sig) {
+      // order-independent signature of the contributor set and of which contributors have
+      // a capped alpha (splitmix64 of id and cap bit): a finite-difference step that
+      // changes either crosses a kink of the blend
       uint64_t h = 0;
       for (const PairRec& r : rec) {
-        uint64_t z = (uint64_t)r.g + 0x9E3779B97F4A7C15ull;
+        const uint64_t capped = r.araw > kAlphaMax ? (uint64_t(1) << 40) : 0;
+        uint64_t z = ((uint64_t)r.g | capped) + 0x9E3779B97F4A7C15ull;
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         h += z ^ (z >> 31);

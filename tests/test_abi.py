@@ -61,12 +61,12 @@ def test_defaults_and_validation_without_gpu(L):
     assert L.gs_destroy_map(None) == gslic.GS_OK
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
     # sizes of the ABI structs as the C compiler lays them out
     from paper_2404_06926_amd import gslic
     src = ('#include "gslic.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%zu %zu %zu %zu %zu\\n",'
            'sizeof(gs_map_desc), sizeof(gs_view), sizeof(gs_frame), sizeof(gs_allocator), offsetof(gs_view, exposure));}')
-    exe = os.path.join(ROOT, "_work", "abi_sizes") if os.path.isdir(os.path.join(ROOT, "_work")) else "/tmp/abi_sizes"
+    exe = str(tmp_path / "abi_sizes")
     cfile = exe + ".c"
     with open(cfile, "w") as f:
         f.write(src)

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import oview
+from helpers import Y00, dc_for_colour, gauss_row, logit, oview
 from paper_2404_06926_amd import scenes
 
 
@@ -73,6 +73,72 @@ def test_adjoint_matches_finite_differences_sh3():
     wf = w.reshape(3, -1)
     expect = np.concatenate([wf @ pre.T, wf.sum(1, keepdims=True)], axis=1).reshape(12)
     np.testing.assert_allclose(gE[0], expect, rtol=1e-10)
+
+
+def test_capped_alpha_gradient_closed_form():
+    # A capped alpha (0.99, reading of Eq. 5) is constant in the Gaussian's geometry and
+    # opacity: at a capped pixel dL/dalpha reaches no parameter except through the colour
+    # term alpha T. One on-axis Gaussian with o = 0.995 and Sigma' = 100.3 I px^2, SH0,
+    # identity exposure; L = out_0 at one pixel.
+    #   capped pixel (32, 24): d out_0/d dc_0 = 0.99 Y00 and every geometric and opacity
+    #   gradient is exactly 0;
+    #   free pixel (35, 24): a = o e^power, d out_0/d logit = (c_0 - bg_0) e^power o (1 - o).
+    cam = scenes.pinhole(64, 48, 50.0)
+    cam.bg = np.array([0.1, 0.2, 0.05], np.float32)
+    s, Z, o = 1.0, 5.0, 0.995
+    c = np.array([0.9, 0.3, 0.6])
+    row = gauss_row([0, 0, Z], np.log(s), logit=logit(o), dc=dc_for_colour(c))[None]
+    v = oview(cam)
+    projs, bins, r0 = _fwd(row, 0, v)
+    var = (50.0 * s / Z) ** 2 + 0.3
+    bg0 = float(cam.bg[0])
+    for (x, y) in [(32, 24), (35, 24)]:
+        w = np.zeros((3, 48, 64))
+        w[0, y, x] = 1.0
+        gp, gE, _ = oracle.backward(row, 0, [v], projs, bins, [w])
+        e = np.exp(-0.5 * ((x + 0.5 - 32) ** 2 + (y + 0.5 - 24) ** 2) / var)
+        if o * e > 0.99:
+            assert np.all(gp[0, 0:11] == 0.0), gp[0, 0:11]
+            np.testing.assert_allclose(gp[0, 11], 0.99 * Y00, rtol=1e-12)
+        else:
+            np.testing.assert_allclose(gp[0, 10], (c[0] - bg0) * e * o * (1 - o), rtol=1e-10)
+            np.testing.assert_allclose(gp[0, 11], o * e * Y00, rtol=1e-12)
+            assert abs(gp[0, 0]) > 0
+
+
+def test_adjoint_matches_finite_differences_with_capped_alphas():
+    # A map where a tenth of the Gaussians have logits in [5, 9] (o > 0.993) and wide
+    # footprints, so that pairs with a capped alpha occur among the contributors; every
+    # coordinate of the capped Gaussians and random coordinates of the others, against
+    # FP64 central differences (steps that move a pair across the cap are skipped).
+    cam = scenes.pinhole(48, 40, 40.0)
+    cam.exposure = scenes.random_exposure(31)
+    cam.bg = np.array([0.2, 0.1, 0.3], np.float32)
+    params = scenes.frustum_gaussians(150, 1, cam, seed=31, log_scale_mean=-0.8).astype(np.float64)
+    rng = np.random.default_rng(31)
+    hi = rng.choice(150, 15, replace=False)
+    params[hi, 10] = rng.uniform(5.0, 9.0, 15)
+    v = oview(cam)
+    proj = oracle.project(params, 1, v, fp64=True)
+    # pixels where a high-opacity Gaussian's alpha is capped (before occlusion)
+    ys, xs = np.mgrid[0:40, 0:48]
+    capped_g = []
+    for g in hi:
+        if not proj["visible"][g]:
+            continue
+        mx, my = proj["mean2d"][g]
+        A, B, C = proj["conic"][g]
+        dx, dy = xs + 0.5 - mx, ys + 0.5 - my
+        araw = proj["opacity"][g] * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + C * dy * dy))
+        if (araw > 0.99).any():
+            capped_g.append(int(g))
+    assert len(capped_g) >= 3, capped_g
+    vis = np.nonzero(proj["visible"])[0]
+    F = params.shape[1]
+    coords = [(g, f) for g in capped_g for f in range(F)]
+    coords += [(int(rng.choice(vis)), f) for f in range(F) for _ in range(2)]
+    checked, worst, _, _, _ = _fd_check(params, 1, v, coords)
+    assert checked >= 0.95 * len(coords)
 
 
 @pytest.mark.parametrize("colour", [False, True])

@@ -43,6 +43,34 @@ def test_single_isotropic_gaussian_image_closed_form():
     assert abs(inside.sum() - area) <= 2 * np.pi * np.sqrt(2 * np.log(255 * o) * var) + 4
 
 
+def test_alpha_cap_closed_form():
+    # Reading of Eq. 5 (alpha capped at 0.99): one on-axis Gaussian with o = 0.995 and
+    # Sigma' = 100.3 I px^2. The four pixels around the mean (offset (0.5, 0.5) px) have
+    # o e^power = 0.9925 > 0.99, so they composite with alpha = 0.99 exactly:
+    # out = 0.99 c + 0.01 bg and T_final = 0.01. Every other pixel has o e^power < 0.99
+    # and stays unclamped.
+    cam = scenes.pinhole(64, 48, 50.0)
+    s, Z, o = 1.0, 5.0, 0.995
+    c = np.array([0.9, 0.3, 0.6])
+    bg = np.array([0.1, 0.2, 0.05])
+    _, _, r, _ = render_rows(gauss_row([0, 0, Z], np.log(s), logit=logit(o), dc=dc_for_colour(c)),
+                             cam, bg=bg)
+    var = (50.0 * s / Z) ** 2 + 0.3
+    ys, xs = np.mgrid[0:48, 0:64]
+    araw = o * np.exp(-0.5 * ((xs + 0.5 - 32) ** 2 + (ys + 0.5 - 24) ** 2) / var)
+    capped = araw > 0.99
+    assert capped.sum() == 4 and capped[23:25, 31:33].all()
+    np.testing.assert_allclose(r["T_final"][capped], 0.01, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(r["out"][:, capped], (0.99 * c + 0.01 * bg)[:, None] * np.ones((1, 4)),
+                               rtol=0, atol=1e-14)
+    # unclamped elsewhere: out = c a + (1 - a) bg with a = o e^power
+    free = ~capped & (araw >= AMIN) & (np.abs(araw * 255 - 1) > 1e-9)
+    assert free.sum() > 1000
+    expect = c[:, None] * araw[free] + (1 - araw[free]) * bg[:, None]
+    np.testing.assert_allclose(r["out"][:, free], expect, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["T_final"][free], 1 - araw[free], rtol=0, atol=1e-12)
+
+
 def test_single_gaussian_depth_and_opacity_maps_closed_form():
     # Eq. 6-7 for one Gaussian on the axis at depth Z: D = Z a and O = a where a >= 1/255.
     cam = scenes.pinhole(64, 48, 50.0)

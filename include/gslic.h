@@ -235,8 +235,10 @@ gs_status gs_set_fused_step(gs_map* map, int32_t enable);
  * map's instance policy has sync_plan = 0 (no host wait inside the step), and an eager
  * gs_step with the same views has sized the workspace (capture never allocates; it fails
  * with GS_ERR_STATE otherwise). Every pointer passed is baked into the graph and must stay
- * valid while it is used; the map must not grow. Each gs_launch_step performs one more
- * step (the Adam step count lives on the device). A step captured while the gradient
+ * valid while it is used; the map must not grow. gs_launch_step returns GS_ERR_STATE, and
+ * launches nothing, once the map's row count or capacity has changed or any of its device
+ * buffers has been reallocated since the capture (capture again then). Each gs_launch_step
+ * performs one more step (the Adam step count lives on the device). A step captured while the gradient
  * planes were known to be zero skips reading them; gs_launch_step then returns
  * GS_ERR_STATE if they may hold values again (gs_render_backward or gs_map_params since). */
 typedef struct gs_step_graph gs_step_graph;
@@ -262,6 +264,12 @@ gs_status gs_map_params(gs_map* map, float** params, float** grads, float** adam
 
 /* Device pointer to the per-Gaussian "seen since the last Adam step" flags (uint8[n]). */
 gs_status gs_map_visibility(gs_map* map, uint8_t** vis);
+
+/* Number of renders of this map so far: gs_render calls, including those inside gs_step,
+ * keyframe jobs, expansion and replays of a captured step. A caller that keeps a render's
+ * outputs for a later gs_render_backward (an autograd graph) compares it before the
+ * backward: the backward always pairs with the most recent render. Host-side value. */
+gs_status gs_map_render_generation(const gs_map* map, int64_t* generation);
 
 /* Number of Adam steps taken (host mirror of the device counter). */
 gs_status gs_map_step_count(const gs_map* map, int64_t* t);

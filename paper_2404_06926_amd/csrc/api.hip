@@ -118,11 +118,15 @@ struct gs_map {
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (stage, index of its start event)
   bool capturing = false;      // inside gs_capture_step: no allocation, no timing, no host wait
+  uint64_t epoch = 0;          // bumped whenever a device buffer of the map is reallocated
+  int64_t render_gen = 0;      // renders so far (eager, inside steps and jobs, graph replays)
 };
 
 struct gs_step_graph {
   gs_map* map = nullptr;
   bool assumes_clean = false;  // captured with the gradient-plane read skipped
+  uint64_t epoch = 0;          // the map's buffer epoch, row count and capacity at capture:
+  int64_t n = 0, cap = 0;      // a replay after any of them changed would use stale pointers
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -164,6 +168,7 @@ gs_status ensure(gs_map* m, DevBuf& b, size_t bytes, hipStream_t s, bool zero = 
   dev_free(m, b.ptr, b.bytes, s);
   b.ptr = p;
   b.bytes = bytes;
+  m->epoch += 1;
   if (zero) {
     hipError_t e = fill_u32((uint32_t*)p, 0u, (int64_t)((bytes + 3) / 4), s);
     if (e != hipSuccess) return fail(GS_ERR_HIP, hipGetErrorString(e));
@@ -204,6 +209,7 @@ gs_status grow_capacity(gs_map* m, int64_t need, hipStream_t s) {
   m->vis = nv;
   m->cap = nc;
   m->have_render = false;
+  m->epoch += 1;
   return GS_OK;
 }
 
@@ -662,6 +668,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   m->last_va = va;
   m->last_N = N;
   m->sorted = which;
+  if (!m->capturing) m->render_gen += 1;
   return GS_OK;
 }
 
@@ -1032,12 +1039,18 @@ gs_status gs_capture_step(gs_map* m, int32_t nv, const gs_view* views, const gs_
   g->graph = graph;
   g->exec = exec;
   g->assumes_clean = assumes_clean;
+  g->epoch = m->epoch;
+  g->n = m->n;
+  g->cap = m->cap;
   *out = g;
   return GS_OK;
 }
 
 gs_status gs_launch_step(gs_step_graph* g, void* stream) {
   if (!g) return fail(GS_ERR_INVALID, "graph is NULL");
+  if (g->epoch != g->map->epoch || g->n != g->map->n || g->cap != g->map->cap)
+    return fail(GS_ERR_STATE,
+                "the map grew or its workspace was reallocated since the capture: capture the step again");
   if (g->assumes_clean && g->map->grads_dirty)
     return fail(GS_ERR_STATE,
                 "the gradient planes may hold values (gs_render_backward or gs_map_params since the capture): "
@@ -1045,6 +1058,7 @@ gs_status gs_launch_step(gs_step_graph* g, void* stream) {
   GS_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   g->map->h_step += 1;
   g->map->grads_dirty = false;
+  g->map->render_gen += 1;
   return GS_OK;
 }
 
@@ -1081,6 +1095,12 @@ gs_status gs_map_params(gs_map* m, float** params, float** grads, float** am, fl
 gs_status gs_map_visibility(gs_map* m, uint8_t** vis) {
   if (!m || !vis) return fail(GS_ERR_INVALID, "NULL argument");
   *vis = m->vis;
+  return GS_OK;
+}
+
+gs_status gs_map_render_generation(const gs_map* m, int64_t* gen) {
+  if (!m || !gen) return fail(GS_ERR_INVALID, "NULL argument");
+  *gen = m->render_gen;
   return GS_OK;
 }
 

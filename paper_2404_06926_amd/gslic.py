@@ -93,6 +93,7 @@ _SIGS = {
                              ctypes.POINTER(_I64)]),
     "gs_map_visibility": (_I32, [_P, ctypes.POINTER(_P)]),
     "gs_map_step_count": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "gs_map_render_generation": (_I32, [_P, ctypes.POINTER(_I64)]),
     "gs_map_set_step_count": (_I32, [_P, _I64, _P]),
     "gs_debug_last_render": (_I32, [_P, _P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                     ctypes.POINTER(_P), ctypes.POINTER(_I64), ctypes.POINTER(_P),
@@ -275,6 +276,13 @@ class GaussianMap:
         t = _I64()
         _check(lib().gs_map_step_count(self.handle, ctypes.byref(t)))
         return t.value
+
+    @property
+    def render_generation(self):
+        """Renders of this map so far (eager, inside steps and jobs, graph replays)."""
+        g = _I64()
+        _check(lib().gs_map_render_generation(self.handle, ctypes.byref(g)))
+        return g.value
 
     def set_step_count(self, t: int, stream=None):
         """Restores the Adam step counter (with the parameters and moments of a checkpoint)."""
@@ -569,11 +577,16 @@ class RenderFunction:
                     frames = gmap.render(cams, list(exposures) if exposures else None)
                     ctx.gmap = gmap
                     ctx.n_exp = len(exposures)
+                    # the backward consumes the map's saved state of its most recent render
+                    ctx.generation = gmap.render_generation
                     return tuple(f.rgb for f in frames)
 
                 @staticmethod
                 def backward(ctx, *grads):
                     gmap = ctx.gmap
+                    if gmap.render_generation != ctx.generation:
+                        raise RuntimeError("the map rendered again after this forward; its backward would "
+                                           "use the newer render's state: render_autograd again")
                     g = gmap.grads()
                     g.zero_()
                     gexp = [torch.zeros(12, device=gmap.device) for _ in range(len(grads))]

@@ -5,9 +5,10 @@ job (gs_submit_keyframe: append Gaussians from the keyframe's points as in Sec. 
 keep the keyframe in the session's window, run `iters` optimisation steps over the
 window). The scheduler:
 
-* admits sessions in order of their first arrival while the HBM they will hold (an
-  estimate until the map reports its resident bytes) fits the budget, and releases a
-  session's memory when its last job has completed;
+* admits sessions in order of their first arrival while the HBM they reserve fits the
+  budget, and releases a session's memory when its last job has completed. A session
+  reserves the larger of its estimate (sized for its final map and full window) and what
+  its map reports holding, so a map that has not grown yet lends no headroom to others;
 * gives every admitted session its own stream, keeps at most one job of a session in
   flight (a map is used by one stream at a time) and at most `slots` jobs in flight
   overall, so jobs of different sessions overlap on the device as they arrive and as
@@ -57,8 +58,12 @@ class _Session:
     in_flight: Optional[Any] = None
     handle: Any = None
     admitted_at: float = -1.0
-    resident: int = 0
+    resident: int = 0              # bytes the backend reports the session holds
     done_jobs: int = 0
+
+    @property
+    def reserved(self) -> int:
+        return max(self.spec.est_bytes, self.resident)
 
 
 class FakeBackend:
@@ -112,6 +117,37 @@ class FakeBackend:
 
     def close(self, handle):
         self.closed.append(handle)
+
+
+class GrowingFakeBackend(FakeBackend):
+    """FakeBackend whose sessions report resident bytes that grow with every finished
+    job: `start` of the estimate at creation, up to `grow_to` times the estimate."""
+
+    def __init__(self, cost_s=lambda job: 0.01, start=0.3, step=0.25, grow_to=1.0):
+        super().__init__(cost_s)
+        self.start, self.step, self.grow_to = start, step, grow_to
+        self.state = {}                            # handle -> [estimate, jobs done]
+        self.owner = {}                            # token -> handle
+
+    def create(self, spec):
+        self.created.append(spec.sid)
+        self.state[spec.sid] = [spec.est_bytes, 0]
+        return spec.sid, int(self.start * spec.est_bytes)
+
+    def submit(self, handle, job, now):
+        tok = super().submit(handle, job, now)
+        self.owner[tok] = handle
+        return tok
+
+    def poll(self, token, now):
+        t = super().poll(token, now)
+        if t is not None and token in self.owner:
+            self.state[self.owner.pop(token)][1] += 1
+        return t
+
+    def resident(self, handle):
+        est, done = self.state[handle]
+        return int(min(self.grow_to, self.start + self.step * done) * est)
 
 
 class GpuBackend:
@@ -216,7 +252,8 @@ class Scheduler:
         order = sorted(self.sessions, key=lambda s: s.spec.jobs[0].arrival if s.spec.jobs else 0.0)
         waiting = list(order)          # not yet admitted, first-arrival order
         admitted: List[_Session] = []
-        resident_total = 0
+        reserved_total = 0             # sum of max(estimate, resident) of admitted sessions
+        resident_total = 0             # sum of what admitted sessions report holding
         in_flight = 0
         finished = 0
         total = len(order)
@@ -242,26 +279,31 @@ class Scheduler:
                 progressed = True
                 r = self.backend.resident(s.handle)
                 if r is not None:
+                    reserved_total -= s.reserved
                     resident_total += r - s.resident
                     s.resident = r
+                    reserved_total += s.reserved
+                    peak_resident = max(peak_resident, resident_total)
                 self.log.append(("done", s.spec.sid, now, job.latency))
             # release sessions whose jobs are all done
             for s in list(admitted):
                 if s.in_flight is None and s.done_jobs == len(s.spec.jobs):
                     self.backend.close(s.handle)
+                    reserved_total -= s.reserved
                     resident_total -= s.resident
                     admitted.remove(s)
                     finished += 1
                     progressed = True
                     self.log.append(("release", s.spec.sid, now))
             # admit in first-arrival order while the budget allows
-            while waiting and resident_total + waiting[0].spec.est_bytes <= self.budget:
+            while waiting and reserved_total + waiting[0].spec.est_bytes <= self.budget:
                 s = waiting.pop(0)
                 first = s.spec.jobs[0].arrival if s.spec.jobs else 0.0
                 if first > now:
                     waiting.insert(0, s)
                     break
                 s.handle, s.resident = self.backend.create(s.spec)
+                reserved_total += s.reserved
                 resident_total += s.resident
                 peak_resident = max(peak_resident, resident_total)
                 s.admitted_at = now
@@ -271,6 +313,7 @@ class Scheduler:
                 self.log.append(("admit", s.spec.sid, now))
                 if not s.spec.jobs:
                     self.backend.close(s.handle)
+                    reserved_total -= s.reserved
                     resident_total -= s.resident
                     admitted.remove(s)
                     finished += 1

@@ -570,3 +570,59 @@ def test_captured_clean_step_refuses_dirty_gradients():
         torch.cuda.synchronize()
         assert not m.check_overflow()
         g.close()
+
+
+def test_captured_step_refuses_a_grown_map():
+    # A replay bakes in the map's row count, capacity and buffer pointers: after rows are
+    # appended (within capacity, then past it) the launch is refused and runs nothing; a
+    # new capture replays again.
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    extra = scenes.frustum_gaussians(600, deg, cams[0], seed=91)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        m = gpu_map(params, deg, cap=params.shape[0] + 100)
+        tg = [torch.tensor(scenes.smooth_image(6, c.height, c.width), device="cuda") for c in cams]
+        fr = [gslic.Frame(torch.empty(3, c.height, c.width, device="cuda"), torch.empty(c.height, c.width, device="cuda"),
+                          torch.empty(c.height, c.width, dtype=torch.int32, device="cuda")) for c in cams]
+        es = [gslic.identity_exposure_state() for _ in cams]
+        gr = [torch.empty(3, c.height, c.width, device="cuda") for c in cams]
+        lo = torch.empty(len(cams), device="cuda")
+        m.step(cams, fr, tg, es, gr, lo)
+        torch.cuda.synchronize()
+        m.set_instance_policy(False, 4 * m.debug_last_render()["n_inst"] + 4096)
+        m.step(cams, fr, tg, es, gr, lo)
+        g = m.capture_step(cams, fr, tg, es, gr, lo)
+        g.launch()
+        for rows in (extra[:50], extra[50:]):          # within capacity, then past it
+            m.add_gaussians(torch.tensor(rows, device="cuda"))
+            torch.cuda.synchronize()
+            before = (m.params().clone(), m.step_count)
+            with pytest.raises(gslic.GsError) as e:
+                g.launch()
+            assert e.value.code == gslic.GS_ERR_STATE
+            torch.cuda.synchronize()
+            assert torch.equal(m.params(), before[0]) and m.step_count == before[1]
+        g.close()
+        m.step(cams, fr, tg, es, gr, lo)                # sizes the workspace for the new rows
+        g = m.capture_step(cams, fr, tg, es, gr, lo)
+        g.launch()
+        torch.cuda.synchronize()
+        assert not m.check_overflow()
+        g.close()
+
+
+def test_autograd_backward_after_a_second_render_raises():
+    # The backward pairs with the map's most recent render: a render between the forward
+    # and its backward is detected instead of silently using the newer render's state.
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    m = gpu_map(params, deg)
+    ex = [e.clone().requires_grad_(True) for e in exposures(cams)]
+    imgs, p = gslic.render_autograd(m, cams, ex)
+    m.render(cams, exposures(cams))
+    with pytest.raises(RuntimeError, match="rendered again"):
+        torch.autograd.grad(imgs[0].sum(), [p])
+    imgs, p = gslic.render_autograd(m, cams, ex)     # a fresh forward differentiates again
+    gp, = torch.autograd.grad(imgs[0].sum(), [p])
+    assert torch.isfinite(gp).all() and gp.abs().sum() > 0

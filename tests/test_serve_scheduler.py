@@ -86,3 +86,35 @@ def test_estimate_grows_with_map_and_window():
     a = serve.estimate_bytes(100_000, 3, 8, 1280, 720)
     assert serve.estimate_bytes(200_000, 3, 8, 1280, 720) > a
     assert serve.estimate_bytes(100_000, 3, 4, 1280, 720) < a
+
+
+def test_reservation_covers_the_estimate_while_a_map_is_small():
+    # Session 0's map starts at 30% of its estimate and grows with every job. Its
+    # reservation stays at the estimate, so session 1 (which fits beside the map's current
+    # size but not beside its estimate) waits until session 0 is released, and the bytes
+    # the sessions actually hold never exceed the budget.
+    clock = FakeClock()
+    be = serve.GrowingFakeBackend(cost_s=lambda j: 0.004, start=0.3, step=0.25)
+    sch = serve.Scheduler(be, budget_bytes=100, slots=8, poll_s=0)
+    sch.add(serve.SessionSpec(sid=0, jobs=_jobs([0.0, 0.001, 0.002, 0.003]), est_bytes=70))
+    sch.add(serve.SessionSpec(sid=1, jobs=_jobs([0.0005, 0.001]), est_bytes=60))
+    res = sch.run(clock=clock)
+    ev = [(e[0], e[1]) for e in sch.log if e[0] in ("admit", "release")]
+    assert ev.index(("release", 0)) < ev.index(("admit", 1))
+    assert res["peak_resident_bytes"] == 70          # session 0 at full size, alone
+    assert res["peak_resident_bytes"] <= 100
+
+
+def test_growth_past_the_estimate_raises_the_reservation():
+    # A map that outgrows its estimate (to 1.5x) reserves what it holds: a session that
+    # fits beside the estimate but not beside the grown map is held back until release.
+    clock = FakeClock()
+    be = serve.GrowingFakeBackend(cost_s=lambda j: 0.004, start=1.0, step=0.25, grow_to=1.5)
+    sch = serve.Scheduler(be, budget_bytes=100, slots=8, poll_s=0)
+    sch.add(serve.SessionSpec(sid=0, jobs=_jobs([0.0, 0.001, 0.002, 0.02]), est_bytes=40))
+    sch.add(serve.SessionSpec(sid=1, jobs=_jobs([0.015]), est_bytes=50))
+    res = sch.run(clock=clock)
+    ev = [(e[0], e[1]) for e in sch.log if e[0] in ("admit", "release")]
+    assert ev.index(("release", 0)) < ev.index(("admit", 1))
+    # session 0 peaks at 60 B; session 1 alone grows from 50 to 62 B after its job
+    assert res["peak_resident_bytes"] == 62

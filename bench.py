@@ -176,60 +176,6 @@ def timed(torch, fn, steps):
     return start.elapsed_time(stop) / steps
 
 
-def measure_outdoor(torch, gslic, args, dev):
-    """The outdoor-shaped single-view step (500k LiDAR-shaped Gaussians: ground, facades,
-    far points and a 20k sky shell; SH3; 1280x720; jittered-means target): graph replays
-    from a restored state, as for the headline."""
-    from paper_2404_06926_amd import scenes
-    params, cam = scenes.outdoor_scene(2000, deg=3)
-    target_params = scenes.jitter_means(params, 0.05, 2000)
-    cams = [cam]
-    tmap = gslic.GaussianMap(sh_degree=3, capacity=params.shape[0])
-    tmap.add_gaussians(torch.from_numpy(target_params).to(dev))
-    targets = [f.rgb.clone() for f in tmap.render(cams)]
-    tmap.close()
-    m = gslic.GaussianMap(sh_degree=3, capacity=params.shape[0])
-    m.add_gaussians(torch.from_numpy(params).to(dev))
-    fpx, bpx = (int(x) for x in args.blend_px.split(","))
-    m.set_blend_config(fpx, bpx)
-    m.set_tile_split(*split_config(args))
-    B = StepBuffers(torch, gslic, cams, dev)
-    m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
-    torch.cuda.synchronize()
-    n_inst = m.debug_last_render()["n_inst"]
-    m.set_instance_policy(False, int(n_inst * 1.5) + 65536)
-    for _ in range(args.warmup):
-        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
-    torch.cuda.synchronize()
-    snap = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in B.expo)]
-    graph = m.capture_step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
-    graph.launch()
-    m.params().copy_(snap[0])
-    mm, vv = m.adam_moments()
-    mm.copy_(snap[1])
-    vv.copy_(snap[2])
-    for e, sv in zip(B.expo, snap[3:]):
-        e.copy_(sv)
-    torch.cuda.synchronize()
-    ms = timed(torch, graph.launch, args.steps)
-    overflow = m.check_overflow()
-    graph.close()
-    # per-stage times of a few eager steps (HIP events around the stages)
-    m.set_stage_timing(True)
-    m.stage_times()
-    for _ in range(10):
-        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
-    st = m.stage_times()
-    m.set_stage_timing(False)
-    pairs = int(B.frames[0].n_contrib.to(torch.int64).sum().item())
-    m.close()
-    if overflow:
-        raise RuntimeError("instance buffer overflow in the outdoor steps")
-    return {"workload": f"outdoor street, {params.shape[0]} Gaussians (LiDAR-shaped + 20k sky), SH3, 1280x720",
-            "iters_per_s": 1000.0 / ms, "ms_per_step": ms, "steps": args.steps, "instances": n_inst,
-            "pairs": pairs, "stages_ms": {k: round(v[0] / v[1], 4) for k, v in st.items() if v[1] > 0}}
-
-
 def _pinned(torch, a):
     t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
     t.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)))
@@ -476,6 +422,311 @@ def run_schedule(args, torch, gslic):
     }
 
 
+def measure_copy(torch, dev, nbytes=1 << 30, reps=20):
+    """Achievable HBM bandwidth: a device-to-device copy of `nbytes` (torch's copy kernel),
+    counted as nbytes read + nbytes written per copy, averaged over `reps` copies."""
+    src = torch.ones(nbytes // 4, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ms = timed(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": 2.0 * nbytes / (ms * 1e-3) / 1e9, "bytes_per_copy": 2 * nbytes, "ms_per_copy": ms,
+            "frac_of_peak": 2.0 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "kernel": "torch copy_ (device to device)"}
+
+
+def cpu_config1(lam=0.0):
+    """The oracle's config-1 step (10k Gaussians SH0 at 256x192, L1 only, one forward and
+    backward) with one host thread and with every host thread."""
+    import oracle
+    from paper_2404_06926_amd import scenes
+    cam = scenes.pinhole(256, 192, 200.0)
+    params = scenes.frustum_gaussians(10_000, 0, cam, seed=1000)
+    target = scenes.jitter_means(params, 0.05, 1000)
+    v = oracle.OView(cam=cam.cam16(), W=cam.width, H=cam.height)
+    tgt = oracle.forward(target, 0, [v])[2][0]["out"]
+
+    def one():
+        t0 = time.perf_counter()
+        projs, bins, rend = oracle.forward(params, 0, [v])
+        _, g, _ = oracle.loss(rend[0]["out"], tgt, lam)
+        oracle.backward(params, 0, [v], projs, bins, [g])
+        return time.perf_counter() - t0
+
+    all_threads = oracle.set_threads(1)
+    try:
+        t1 = min(one() for _ in range(2))
+    finally:
+        oracle.set_threads(all_threads)
+    tn = min(one() for _ in range(2))
+    return {"workload": "10k Gaussians SH0, 256x192, L1, one forward + backward (best of 2)",
+            "threads_1": {"iters_per_s": 1.0 / t1, "s": t1},
+            f"threads_{all_threads}": {"iters_per_s": 1.0 / tn, "s": tn}, "host_threads": all_threads}
+
+
+def bench_step(torch, gslic, args, dev, workload, steps, warmup, with_plain=False, with_cpu=False):
+    """Graph-replayed mapping steps of one workload (headline, outdoor or batch8) from a
+    restored state, eager steps with per-stage HIP events, the roofline of the dominant
+    stage; batch8 also times the plain path (one view per launch)."""
+    sh = 0 if workload == "batch8" else args.sh
+    n = args.n
+    if workload == "batch8":
+        cams, params, target_params = batch_workload(n)
+    elif workload == "outdoor":
+        from paper_2404_06926_amd import scenes
+        params, cam = scenes.outdoor_scene(2000, deg=3)
+        target_params = scenes.jitter_means(params, 0.05, 2000)
+        cams = [cam]
+        n, sh = params.shape[0], 3
+    else:
+        cams, params, target_params = headline_workload(n, sh, args.width, args.height)
+    log(f"workload {workload}: n={n} sh={sh} views={[(c.width, c.height) for c in cams]}")
+
+    # targets: renders of the jittered map (outside the timed regions)
+    tmap = gslic.GaussianMap(sh_degree=sh, capacity=n)
+    tmap.add_gaussians(torch.from_numpy(target_params).to(dev))
+    targets = [f.rgb.clone() for f in tmap.render(cams)]
+    tmap.close()
+    del tmap
+
+    m = gslic.GaussianMap(sh_degree=sh, capacity=n)
+    m.add_gaussians(torch.from_numpy(params).to(dev))
+    fpx, bpx = (int(x) for x in args.blend_px.split(","))
+    m.set_blend_config(fpx, bpx)
+    m.set_backward_mode(args.bwd_mode)
+    m.set_tile_split(*split_config(args))
+    B = StepBuffers(torch, gslic, cams, dev)
+
+    def step():
+        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+
+    step()  # plans the instance buffers
+    torch.cuda.synchronize()
+    n_inst0 = m.debug_last_render()["n_inst"]
+    m.set_instance_policy(False, int(n_inst0 * 1.5) + 65536)
+    tuned = None
+    if args.autotune and workload == args.workload:
+        from paper_2404_06926_amd import tune
+        best, times = tune.autotune_step(m, cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam,
+                                         steps=min(steps, 50))
+        fpx, bpx, args.bwd_mode, sp = best
+        args.split = ",".join(str(x) for x in sp)
+        tuned = {"chosen": {"blend_px_per_lane": [fpx, bpx], "backward_mode": args.bwd_mode, "tile_split": list(sp)},
+                 "configs_tried": len(times), "ms_best": times[best],
+                 "ms_defaults": times.get((1, 1, 0, (4096, 128, 1.25)))}
+        log(f"autotune: {tuned}")
+        log("autotune times: " + "; ".join(f"{k}: {v:.3f}" for k, v in sorted(times.items(), key=lambda kv: kv[1])))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Every timed region starts from this state: the map's cost changes as Adam moves it
+    # (opacities and scales drift), so regions are made comparable by restoring parameters,
+    # Adam moments and exposure states before each (outside the timed regions).
+    snap = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in B.expo)]
+
+    def restore():
+        m.params().copy_(snap[0])
+        mm, vv = m.adam_moments()
+        mm.copy_(snap[1])
+        vv.copy_(snap[2])
+        for e, sv in zip(B.expo, snap[3:]):
+            e.copy_(sv)
+        torch.cuda.synchronize()
+
+    def work_counts():
+        dbg = m.debug_last_render()
+        return dict(n_inst=dbg["n_inst"], n_vis=int((dbg["counts"] > 0).sum().item()),
+                    pairs=sum(int(f.n_contrib.to(torch.int64).sum().item()) for f in B.frames),
+                    n_tiles=dbg["n_tiles"])
+
+    # work of the first step of a region (untimed), for the average with the last one
+    restore()
+    step()
+    torch.cuda.synchronize()
+    wc_first = work_counts()
+
+    # eager timed region with per-stage HIP events
+    restore()
+    m.set_stage_timing(True)
+    m.stage_times()
+    log(f"instances {n_inst0}; eager timed region ({steps} steps)")
+    ms_eager = timed(torch, step, steps)
+    stages = m.stage_times()
+    m.set_stage_timing(False)
+    wc_last = work_counts()
+
+    # captured step, replayed
+    graph = None
+    ms_graph = None
+    if not args.eager:
+        graph = m.capture_step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
+        for _ in range(warmup):
+            graph.launch()
+        log(f"graph timed regions ({args.repeats} x {steps} steps)")
+        runs = []
+        for _ in range(max(args.repeats, 1)):
+            restore()
+            runs.append(timed(torch, graph.launch, steps))
+        ms_graph = float(np.median(runs))
+    if m.check_overflow():
+        raise RuntimeError("instance buffer overflow during the timed steps")
+    ms = ms_graph if ms_graph is not None else ms_eager
+
+    # work per step: the mean of the first and last step of the eager region (the stage
+    # times are averages over that region; the work grows as the map moves)
+    avg = lambda k: (wc_first[k] + wc_last[k]) / 2.0
+    n_inst, n_vis, pairs = avg("n_inst"), avg("n_vis"), avg("pairs")
+    F = 11 + 3 * (sh + 1) ** 2
+    T_total = wc_last["n_tiles"]
+    P = sum(c.width * c.height for c in cams)
+    tile_passes = (int(np.ceil(np.log2(T_total + 1))) + 7) // 8
+    V = len(cams)
+
+    per = {k: (v[0] / max(v[1], 1)) for k, v in stages.items() if v[1] > 0}
+    # Algorithmic work per launch of each stage: the HBM bytes the method must move (all
+    # stages) and FLOPs (blend kernels, bound by the vector ALU). The blend kernels' list
+    # entries are gathers of records that several tiles share and their gradient atomics
+    # meet in L2: those are reported as L2 bytes beside the HBM minimum, never inside it.
+    l2 = {
+        # 36-B record (2D mean, conic with opacity, colour) and two indices per list entry
+        "blend": 44.0 * n_inst,
+        # the same gathers, plus nine float atomics per instance into the 2D-gradient record
+        "blend_backward": 44.0 * n_inst + 36.0 * n_inst,
+    }
+    work = {
+        "project": ("hbm", 4.0 * 14 * n + 4.0 * (F - 14) * n + 64.0 * n_vis + 8.0 * V * n, 0),
+        # 20 B per key and pass (4 read up, 8 read + 8 written down); the first pass reads no values
+        "depth_sort": ("hbm", (4 * 20.0 - 4.0) * V * n, 0),
+        "scan": ("hbm", 12.0 * V * n, 0),
+        "duplicate": ("hbm", 24.0 * n_vis + 8.0 * n_inst, 0),
+        "sort": ("hbm", (tile_passes * 20.0 - 4.0) * n_inst, 0),
+        "ranges": ("hbm", 4.0 * n_inst + 8.0 * T_total, 0),
+        # HBM minimum: each visible record once, 8 B of indices per entry, 20 B per pixel out
+        "blend": ("alu", 36.0 * n_vis + 8.0 * n_inst + 20.0 * P, FWD_FLOPS_PER_PAIR * float(pairs)),
+        "loss": ("hbm", 36.0 * P, 0),   # read out and gt, write dL/dout (3 channels)
+        # HBM minimum: records once, indices, 32 B per pixel in, the 2D-gradient record written once
+        "blend_backward": ("alu", 36.0 * n_vis + 8.0 * n_inst + 32.0 * P + 48.0 * n_vis,
+                           BWD_FLOPS_PER_PAIR * float(pairs)),
+        # fused with Adam: read and write parameters, m and v (3 x 4F B each way), read and
+        # clear the 48-B 2D-gradient record, read the tile counts
+        "project_backward": ("hbm", 24.0 * F * n_vis + 96.0 * n_vis + 4.0 * V * n, 0),
+        "adam": ("hbm", 2 * 4.0 * 48 * V, 0),   # exposures of the separate path (a fused step updates them in project_backward)
+    }
+    names = {"blend_backward": (f"k_blend_bwd<{bpx},false,false>" if args.bwd_mode == 0 else "k_blend_bwd_pg<false>"),
+             "blend": f"k_blend_fwd<{fpx},false>",
+             "project_backward": f"k_project_bwd<{sh},true,{'true' if len(cams) > 1 else 'false'}>",
+             "project": f"k_project_fwd<{sh}>",
+             "loss": "k_ssim_tile", "duplicate": "k_dup_lb"}
+    tag = f"{workload}_{n // 1000}k_sh{sh}_{args.width}x{args.height}"
+    kernel_table = {}
+    for k, ms_k in per.items():
+        if k not in work:
+            continue
+        bound_k, bytes_k, flops_k = work[k]
+        d = ms_k * 1e-3
+        row = {"ms": round(ms_k, 4), "bound": bound_k, "alg_bytes": bytes_k,
+               "hbm_frac": round(bytes_k / d / (HBM_PEAK_GBS * 1e9), 4)}
+        if k in l2:
+            row["l2_bytes"] = l2[k]
+        if flops_k:
+            row["flops"] = flops_k
+            row["valu_frac"] = round(flops_k / d / (FP32_PEAK_TFLOPS * 1e12), 4)
+        t_k = recorded_traffic(names[k], tag) if k in names else None
+        if t_k is not None:
+            row["traffic_bytes"] = t_k
+            row["traffic_frac"] = round(t_k / d / (HBM_PEAK_GBS * 1e9), 4)
+        v_k = recorded_valu(names[k], tag) if k in names else None
+        if v_k is not None:
+            row["valu_issue_frac"] = round(v_k / (d * VALU_ISSUE_PER_S), 4)
+        kernel_table[k] = row
+    dom = max(per, key=lambda k: per[k])
+    bound, nbytes, nflops = work[dom]
+    dur_s = per[dom] * 1e-3
+    if bound == "hbm":
+        achieved, peak, unit = nbytes / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = nflops / dur_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
+    traffic = recorded_traffic(names[dom], tag) if dom in names else None
+    roof = dict(bound=bound, kernel=dom, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
+                traffic=traffic, avg_launch_ms=per[dom])
+    valu = recorded_valu(names[dom], tag) if dom in names else None
+    if valu is not None:
+        # instruction side of an ALU-bound kernel: VALU wave-instructions per launch (SQ
+        # counters) over what the device issues in the launch's duration
+        roof["valu_issue_frac"] = valu / (dur_s * VALU_ISSUE_PER_S)
+    if traffic is not None:
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)"
+        roof["traffic_GBs"] = traffic / dur_s / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": 1000.0 / ms,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "repeats": args.repeats,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (("outdoor street (LiDAR-shaped + 20k sky), " if workload == "outdoor" else "")
+                                + f"{n} Gaussians, SH{sh}, "
+                                + ", ".join(f"{c.width}x{c.height}" for c in cams)
+                                + f" per step, loss 0.8 L1 + 0.2 D-SSIM, sparse Adam"),
+                   "n_gaussians": n, "sh_degree": sh, "views_per_step": V,
+                   "timing": "graph replay" if ms_graph is not None else "eager",
+                   "blend_px_per_lane": [fpx, bpx],
+                   "tile_split": list(split_config(args)),
+                   "autotuned": tuned,
+                   "backward_blend": "pixel order" if args.bwd_mode == 0 else "per Gaussian"},
+        "roofline": roof,
+        "eager_ms_per_step": ms_eager,
+        "stages_ms": {k: round(v, 4) for k, v in per.items()},
+        "kernels": kernel_table,
+        "counts": {"visible_pairs": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total,
+                   "first_step": wc_first, "last_step": wc_last},
+    }
+
+    if with_plain:
+        # plain: the same views launched one at a time, gradients summed, one Adam step
+        Bp = StepBuffers(torch, gslic, cams, dev)
+
+        def plain():
+            for k, c in enumerate(cams):
+                m.render([c], [Bp.expo[k]], frames=[Bp.frames[k]])
+                m.loss(Bp.frames[k].rgb, targets[k], args.lam, loss_out=Bp.loss[k:k + 1], grad_out=Bp.grads[k])
+                m.render_backward([Bp.grads[k]], [Bp.expo[k][12:24]])
+            m.adam_step(Bp.expo)
+
+        for _ in range(warmup):
+            plain()
+        restore()
+        ms_plain = timed(torch, plain, steps)
+        if m.check_overflow():
+            raise RuntimeError("instance buffer overflow in the plain path")
+        result["plain_ms_per_step"] = ms_plain
+        result["batched_over_plain"] = ms_plain / ms
+        result["batched_eager_over_plain"] = ms_plain / ms_eager
+        result["metric"] = "mapping iters/s, 8 uneven keyframes per step (batched vs one view per launch)"
+    if workload == "outdoor":
+        result["metric"] = "mapping iters/s (fwd+bwd+Adam), outdoor single view, 500k Gaussians 1280x720"
+    if graph is not None:
+        graph.close()
+    m.close()
+    if with_cpu and not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        try:
+            result["cpu_baseline"] = cpu_baseline(params, target_params, sh, cams[0], args.lam)
+        except Exception as e:  # report, never fail the GPU result
+            result["cpu_baseline"] = {"error": repr(e)}
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,7 +745,10 @@ def main():
     ap.add_argument("--lam", type=float, default=0.2)
     ap.add_argument("--eager", action="store_true", help="time eager steps instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-outdoor", action="store_true", help="skip the outdoor single-view measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: skip the outdoor, batch8, street-drive latency, copy and config-1 CPU legs")
+    ap.add_argument("--extra-steps", type=int, default=10, help="timed steps of the batch8 and outdoor legs")
+    ap.add_argument("--stream-seconds", type=float, default=3.0, help="arrivals of the street-drive latency leg")
     ap.add_argument("--blend-px", default="1,1",
                     help="pixels per lane of the forward and backward blend kernels (1, 2 or 4)")
     ap.add_argument("--split", default="4096,128,1.25",
@@ -530,249 +784,47 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload == "batch8":
-        args.sh = 0
-        cams, params, target_params = batch_workload(args.n)
-    elif args.workload == "outdoor":
-        from paper_2404_06926_amd import scenes
-        params, cam = scenes.outdoor_scene(2000, deg=3)
-        target_params = scenes.jitter_means(params, 0.05, 2000)
-        cams = [cam]
-        args.n, args.sh = params.shape[0], 3
-    else:
-        cams, params, target_params = headline_workload(args.n, args.sh, args.width, args.height)
-    log(f"workload {args.workload}: n={args.n} sh={args.sh} views={[(c.width, c.height) for c in cams]}")
+    if args.workload != "headline":
+        res = bench_step(torch, gslic, args, dev, args.workload, args.steps, args.warmup,
+                         with_plain=args.workload == "batch8")
+        print(json.dumps(res), flush=True)
+        return
 
-    # targets: renders of the jittered map (outside the timed regions)
-    tmap = gslic.GaussianMap(sh_degree=args.sh, capacity=args.n)
-    tmap.add_gaussians(torch.from_numpy(target_params).to(dev))
-    targets = [f.rgb.clone() for f in tmap.render(cams)]
-    tmap.close()
-    del tmap
-
-    m = gslic.GaussianMap(sh_degree=args.sh, capacity=args.n)
-    m.add_gaussians(torch.from_numpy(params).to(dev))
-    fpx, bpx = (int(x) for x in args.blend_px.split(","))
-    m.set_blend_config(fpx, bpx)
-    m.set_backward_mode(args.bwd_mode)
-    m.set_tile_split(*split_config(args))
-    B = StepBuffers(torch, gslic, cams, dev)
-
-    def step():
-        m.step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
-
-    step()  # plans the instance buffers
-    torch.cuda.synchronize()
-    n_inst0 = m.debug_last_render()["n_inst"]
-    m.set_instance_policy(False, int(n_inst0 * 1.5) + 65536)
-    tuned = None
-    if args.autotune:
-        from paper_2404_06926_amd import tune
-        best, times = tune.autotune_step(m, cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam,
-                                         steps=min(args.steps, 50))
-        fpx, bpx, args.bwd_mode, sp = best
-        args.split = ",".join(str(x) for x in sp)
-        tuned = {"chosen": {"blend_px_per_lane": [fpx, bpx], "backward_mode": args.bwd_mode, "tile_split": list(sp)},
-                 "configs_tried": len(times), "ms_best": times[best],
-                 "ms_defaults": times.get((1, 1, 0, (4096, 128, 1.25)))}
-        log(f"autotune: {tuned}")
-        log("autotune times: " + "; ".join(f"{k}: {v:.3f}" for k, v in sorted(times.items(), key=lambda kv: kv[1])))
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # Every timed region starts from this state: the map's cost changes as Adam moves it
-    # (opacities and scales drift), so regions are made comparable by restoring parameters,
-    # Adam moments and exposure states before each (outside the timed regions).
-    snap = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in B.expo)]
-
-    def restore():
-        m.params().copy_(snap[0])
-        mm, vv = m.adam_moments()
-        mm.copy_(snap[1])
-        vv.copy_(snap[2])
-        for e, sv in zip(B.expo, snap[3:]):
-            e.copy_(sv)
-        torch.cuda.synchronize()
-
-    def work_counts():
-        dbg = m.debug_last_render()
-        return dict(n_inst=dbg["n_inst"], n_vis=int((dbg["counts"] > 0).sum().item()),
-                    pairs=sum(int(f.n_contrib.to(torch.int64).sum().item()) for f in B.frames),
-                    n_tiles=dbg["n_tiles"])
-
-    # work of the first step of a region (untimed), for the average with the last one
-    restore()
-    step()
-    torch.cuda.synchronize()
-    wc_first = work_counts()
-
-    # eager timed region with per-stage HIP events
-    restore()
-    m.set_stage_timing(True)
-    m.stage_times()
-    log(f"instances {n_inst0}; eager timed region ({args.steps} steps)")
-    ms_eager = timed(torch, step, args.steps)
-    stages = m.stage_times()
-    m.set_stage_timing(False)
-    wc_last = work_counts()
-
-    # captured step, replayed
-    graph = None
-    ms_graph = None
-    if not args.eager:
-        graph = m.capture_step(cams, B.frames, targets, B.expo, B.grads, B.loss, lam=args.lam)
-        for _ in range(args.warmup):
-            graph.launch()
-        log(f"graph timed regions ({args.repeats} x {args.steps} steps)")
-        runs = []
-        for _ in range(max(args.repeats, 1)):
-            restore()
-            runs.append(timed(torch, graph.launch, args.steps))
-        ms_graph = float(np.median(runs))
-    if m.check_overflow():
-        raise RuntimeError("instance buffer overflow during the timed steps")
-    ms = ms_graph if ms_graph is not None else ms_eager
-
-    # work per step: the mean of the first and last step of the eager region (the stage
-    # times are averages over that region; the work grows as the map moves)
-    avg = lambda k: (wc_first[k] + wc_last[k]) / 2.0
-    n_inst, n_vis, pairs = avg("n_inst"), avg("n_vis"), avg("pairs")
-    F = 11 + 3 * (args.sh + 1) ** 2
-    T_total = wc_last["n_tiles"]
-    P = sum(c.width * c.height for c in cams)
-    tile_passes = (int(np.ceil(np.log2(T_total + 1))) + 7) // 8
-    V = len(cams)
-
-    per = {k: (v[0] / max(v[1], 1)) for k, v in stages.items() if v[1] > 0}
-    # algorithmic work per launch of each stage: bytes the method must move (all stages)
-    # and FLOPs (blend kernels, bound by the vector ALU)
-    atomics = 36.0 * n_inst   # nine float atomics per instance (the waves' sums meet in LDS)
-    # (the headline's adam stage is fused into project_backward: no separate pass)
-    work = {
-        "project": ("hbm", 4.0 * 14 * args.n + 4.0 * (F - 14) * args.n + 64.0 * n_vis + 8.0 * V * args.n, 0),
-        # 20 B per key and pass (4 read up, 8 read + 8 written down); the first pass reads no values
-        "depth_sort": ("hbm", (4 * 20.0 - 4.0) * V * args.n, 0),
-        "scan": ("hbm", 12.0 * V * args.n, 0),
-        "duplicate": ("hbm", 24.0 * n_vis + 8.0 * n_inst, 0),
-        "sort": ("hbm", (tile_passes * 20.0 - 4.0) * n_inst, 0),
-        "ranges": ("hbm", 4.0 * n_inst + 8.0 * T_total, 0),
-        "blend": ("alu", 40.0 * n_inst + 20.0 * P, FWD_FLOPS_PER_PAIR * float(pairs)),
-        "loss": ("hbm", 36.0 * P, 0),   # read out and gt, write dL/dout (3 channels)
-        "blend_backward": ("alu", 40.0 * n_inst + 32.0 * P + atomics, BWD_FLOPS_PER_PAIR * float(pairs)),
-        # fused with Adam: read and write parameters, m and v (3 x 4F B each way), read and
-        # clear the 48-B 2D-gradient record, read the tile counts
-        "project_backward": ("hbm", 24.0 * F * n_vis + 96.0 * n_vis + 4.0 * V * args.n, 0),
-        "adam": ("hbm", 2 * 4.0 * 48 * V, 0),   # exposures of the separate path (a fused step updates them in project_backward)
-    }
-    names = {"blend_backward": (f"k_blend_bwd<{bpx},false,false>" if args.bwd_mode == 0 else "k_blend_bwd_pg<false>"),
-             "blend": f"k_blend_fwd<{fpx},false>",
-             "project_backward": f"k_project_bwd<{args.sh},true,{'true' if len(cams) > 1 else 'false'}>",
-             "project": f"k_project_fwd<{args.sh}>"}
-    tag = f"{args.workload}_{args.n // 1000}k_sh{args.sh}_{args.width}x{args.height}"
-    kernel_table = {}
-    for k, ms_k in per.items():
-        if k not in work:
-            continue
-        bound_k, bytes_k, flops_k = work[k]
-        d = ms_k * 1e-3
-        row = {"ms": round(ms_k, 4), "bound": bound_k, "alg_bytes": bytes_k,
-               "hbm_frac": round(bytes_k / d / (HBM_PEAK_GBS * 1e9), 4)}
-        if flops_k:
-            row["flops"] = flops_k
-            row["valu_frac"] = round(flops_k / d / (FP32_PEAK_TFLOPS * 1e12), 4)
-        t_k = recorded_traffic(names[k], tag) if k in names else None
-        if t_k is not None:
-            row["traffic_bytes"] = t_k
-            row["traffic_frac"] = round(t_k / d / (HBM_PEAK_GBS * 1e9), 4)
-        kernel_table[k] = row
-    dom = max(per, key=lambda k: per[k])
-    bound, nbytes, nflops = work[dom]
-    dur_s = per[dom] * 1e-3
-    if bound == "hbm":
-        achieved, peak, unit = nbytes / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
-    else:
-        achieved, peak, unit = nflops / dur_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
-    traffic = recorded_traffic(names[dom], tag) if dom in names else None
-    roof = dict(bound=bound, kernel=dom, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
-                traffic=traffic, avg_launch_ms=per[dom])
-    valu = recorded_valu(names[dom], tag) if dom in names else None
-    if valu is not None:
-        # instruction side of an ALU-bound kernel: VALU wave-instructions per launch (SQ
-        # counters) over what the device issues in the launch's duration
-        roof["valu_issue_frac"] = valu / (dur_s * VALU_ISSUE_PER_S)
-    if traffic is not None:
-        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)"
-        roof["traffic_GBs"] = traffic / dur_s / 1e9
-
-    result = {
-        "metric": METRIC,
-        "value": 1000.0 / ms,
-        "unit": "iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "repeats": args.repeats,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": (("outdoor street (LiDAR-shaped + 20k sky), " if args.workload == "outdoor" else "")
-                                + f"{args.n} Gaussians, SH{args.sh}, "
-                                + ", ".join(f"{c.width}x{c.height}" for c in cams)
-                                + f" per step, loss 0.8 L1 + 0.2 D-SSIM, sparse Adam"),
-                   "n_gaussians": args.n, "sh_degree": args.sh, "views_per_step": V,
-                   "timing": "graph replay" if ms_graph is not None else "eager",
-                   "blend_px_per_lane": [fpx, bpx],
-                   "tile_split": list(split_config(args)),
-                   "autotuned": tuned,
-                   "backward_blend": "pixel order" if args.bwd_mode == 0 else "per Gaussian"},
-        "roofline": roof,
-        "eager_ms_per_step": ms_eager,
-        "stages_ms": {k: round(v, 4) for k, v in per.items()},
-        "kernels": kernel_table,
-        "counts": {"visible_pairs": n_vis, "instances": n_inst, "pairs": pairs, "tiles": T_total,
-                   "first_step": wc_first, "last_step": wc_last},
-    }
-
-    if args.workload == "batch8":
-        # plain: the same views launched one at a time, gradients summed, one Adam step
-        Bp = StepBuffers(torch, gslic, cams, dev)
-
-        def plain():
-            for k, c in enumerate(cams):
-                m.render([c], [Bp.expo[k]], frames=[Bp.frames[k]])
-                m.loss(Bp.frames[k].rgb, targets[k], args.lam, loss_out=Bp.loss[k:k + 1], grad_out=Bp.grads[k])
-                m.render_backward([Bp.grads[k]], [Bp.expo[k][12:24]])
-            m.adam_step(Bp.expo)
-
-        for _ in range(args.warmup):
-            plain()
-        restore()
-        ms_plain = timed(torch, plain, args.steps)
-        if m.check_overflow():
-            raise RuntimeError("instance buffer overflow in the plain path")
-        result["plain_ms_per_step"] = ms_plain
-        result["batched_over_plain"] = ms_plain / ms
-        result["batched_eager_over_plain"] = ms_plain / ms_eager
-        result["metric"] = "mapping iters/s, 8 uneven keyframes per step (batched vs one view per launch)"
-    if args.workload == "outdoor":
-        result["metric"] = "mapping iters/s (fwd+bwd+Adam), outdoor single view, 500k Gaussians 1280x720"
-
-    if graph is not None:
-        graph.close()
-    if args.workload == "headline" and not args.no_outdoor:
-        m.close()
+    result = bench_step(torch, gslic, args, dev, "headline", args.steps, args.warmup, with_cpu=True)
+    if not args.no_extras:
+        # The rest of BASELINE's metric and the context numbers, each a short leg of its own:
+        # the outdoor single view, the 8-view batch against one view per launch, the
+        # street-drive keyframe latency, the achievable HBM bandwidth and the oracle's
+        # config-1 step on one and on all host threads.
         log("outdoor workload")
-        result["outdoor_single_view"] = measure_outdoor(torch, gslic, args, dev)
-    if not args.no_cpu_baseline and args.workload == "headline":
-        log("cpu baseline (oracle)")
-        try:
-            result["cpu_baseline"] = cpu_baseline(params, target_params, args.sh, cams[0], args.lam)
-        except Exception as e:  # report, never fail the GPU result
-            result["cpu_baseline"] = {"error": repr(e)}
+        od = bench_step(torch, gslic, args, dev, "outdoor", args.extra_steps, args.warmup)
+        result["outdoor_single_view"] = {"workload": od["config"]["workload"], "iters_per_s": od["value"],
+                                         "ms_per_step": od["ms_per_step"], "steps": od["steps"],
+                                         "roofline": od["roofline"], "stages_ms": od["stages_ms"],
+                                         "counts": {k: od["counts"][k] for k in ("instances", "pairs")}}
+        log("batch8 workload")
+        b8 = bench_step(torch, gslic, args, dev, "batch8", args.extra_steps, args.warmup, with_plain=True)
+        result["batched_over_plain"] = b8["batched_over_plain"]
+        result["batch8"] = {"workload": b8["config"]["workload"], "batched_ms_per_step": b8["ms_per_step"],
+                            "plain_ms_per_step": b8["plain_ms_per_step"], "steps": b8["steps"],
+                            "batched_iters_per_s": b8["value"], "stages_ms": b8["stages_ms"]}
+        log("street-drive latency")
+        sargs = argparse.Namespace(**vars(args))
+        sargs.workload, sargs.duration, sargs.sh = "stream", args.stream_seconds, 3
+        st = run_serving(sargs, torch, gslic)
+        result["keyframe_latency"] = {"p50_ms": st["latency_ms"]["p50"], "p99_ms": st["latency_ms"]["p99"],
+                                      "keyframes": st["config"]["keyframes"], "iters_per_s": st["value"],
+                                      "arrivals_s": st["config"]["arrivals_s"],
+                                      "final_gaussians": st["final_gaussians"],
+                                      "workload": st["config"]["workload"]}
+        log("copy bandwidth")
+        result["copy_GBs"] = measure_copy(torch, dev)
+        if not args.no_cpu_baseline:
+            log("cpu config 1")
+            try:
+                result.setdefault("cpu_baseline", {})["config1"] = cpu_config1()
+            except Exception as e:
+                result.setdefault("cpu_baseline", {})["config1"] = {"error": repr(e)}
     print(json.dumps(result), flush=True)
 
 

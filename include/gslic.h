@@ -208,9 +208,26 @@ gs_status gs_submit_keyframe(gs_map* map, const gs_view* view, const float* imag
 gs_status gs_add_keyframe(gs_map* map, const gs_view* view, const float* image, int64_t n_points,
                           const float* xyz, const float* rgb, float o_init, int32_t* keyframe_id,
                           void* stream);
+/* Frame intake of Sec. III-C.2. Every frame brings a pose, its image and its coloured
+ * points (device xyz, rgb: n_points x 3). The first frame bootstraps the map with all of
+ * its points (Sec. III-C.1 initialisation, as gs_add_points). Frames 0, 5, 10, ... are
+ * keyframes: at each keyframe after the first, the points of the five frames since the
+ * previous keyframe (the four before it and its own), merged in arrival order, go through
+ * the opacity mask of the keyframe's view (Eq. 8, tau = the map's expand_tau; as
+ * gs_expand), and the keyframe is kept as by gs_add_keyframe. Points of other frames are
+ * held on the device until then (their image may be NULL and is not kept).
+ * *keyframe_id (may be NULL) receives the keyframe's id, or -1 for other frames.
+ * GS_ERR_INVALID for a keyframe without an image or o_init outside (0, 1). */
+gs_status gs_add_frame(gs_map* map, const gs_view* view, const float* image, int64_t n_points,
+                       const float* xyz, const float* rgb, float o_init, int32_t* keyframe_id,
+                       void* stream);
 gs_status gs_optimize_keyframes(gs_map* map, int32_t n, const int32_t* ids, float lambda,
                                 void* done_event, void* stream);
 gs_status gs_keyframe_count(gs_map* map, int32_t* count);
+/* Device pointer to kept keyframe `id`'s exposure state float[48] = exposure [A|b] (12),
+ * its gradient (12), Adam m (12), Adam v (12) (Sec. III-C.3), owned by the map and valid
+ * until it is destroyed. GS_ERR_INVALID for an unknown id. */
+gs_status gs_keyframe_state(gs_map* map, int32_t id, float** state);
 
 /* One mapping step over n_views keyframes of one map (Sec. III-C.3): one batched
  * gs_render, the Eq. 9 loss of every view against targets[v] (device float[3][H][W]),

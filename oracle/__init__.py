@@ -57,6 +57,11 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's OpenMP loops from now on; returns the previous count."""
+    return int(lib().or_set_threads(ctypes.c_int(int(n))))
+
+
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -384,6 +389,17 @@ def expansion_select(xyz, view: OView, opacity, tau, near=NEAR_Z, tie=0.0):
     keep = inside & (o < tau)
     ties = inside & (np.abs(o - tau) <= tie)
     return keep, ties
+
+
+def keyframe_merges(n_frames, period=5):
+    """Sec. III-C.2 frame rule: every fifth frame (0, 5, 10, ...) is a keyframe. Frame 0
+    bootstraps the map with its own points; a later keyframe f merges the points of the
+    frames since the previous keyframe, f - 4 .. f, in arrival order. Returns
+    [(keyframe, [frames whose points it uses])] for the keyframes among n_frames frames."""
+    out = []
+    for f in range(0, n_frames, period):
+        out.append((f, [0] if f == 0 else list(range(f - period + 1, f + 1))))
+    return out
 
 
 def nearest_neighbour_distance(xyz):

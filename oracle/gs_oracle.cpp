@@ -38,6 +38,8 @@
 #include <numeric>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -570,6 +572,14 @@ void gauss_window(double* w) {
 extern "C" {
 
 int or_version() { return 4; }
+
+// Host threads the oracle's parallel loops use (timing runs of the CPU baseline); returns
+// the previous setting.
+int or_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
+}
 
 // Per-Gaussian projection for one view. fp64 != 0 runs the key path in FP64, otherwise in
 // the fixed FP32 order. Outputs are per Gaussian (double arrays hold the exact values of

@@ -17,6 +17,8 @@ namespace {
 
 thread_local std::string g_err;
 
+constexpr int64_t kKeyframePeriod = 5;  // every fifth frame is a keyframe (Sec. III-C.2)
+
 gs_status fail(gs_status code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -111,6 +113,10 @@ struct gs_map {
   int kf_next = 0;
   // all keyframes (random-K schedule) and the single-view buffers its steps share
   std::vector<ArchivedKeyframe> archive;
+  // frame intake (gs_add_frame): frames seen, points of the frames since the last keyframe
+  int64_t frames_seen = 0;
+  DevBuf pend_xyz, pend_rgb;
+  int64_t pend_n = 0;
   DevBuf ar_rgb, ar_T, ar_nc, ar_dl;
   // per-stage timing: event pairs recorded since the last query
   bool timing = false;
@@ -324,6 +330,31 @@ struct StageTimer {
   }
 };
 
+// Keeps a keyframe for the session (pose, a copy of its image, an identity exposure with
+// zero gradient and moments) and reports its id.
+gs_status archive_keyframe(gs_map* m, const gs_view* view, const float* image, int32_t* keyframe_id,
+                           hipStream_t s) {
+  ArchivedKeyframe a;
+  a.pix_bytes = (size_t)view->width * view->height * sizeof(float);
+  a.image = (float*)dev_alloc(m, 3 * a.pix_bytes, s);
+  a.state = (float*)dev_alloc(m, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+  if (!a.image || !a.state) {
+    dev_free(m, a.image, 3 * a.pix_bytes, s);
+    dev_free(m, a.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
+    return fail(GS_ERR_OOM, "keyframe buffers");
+  }
+  GS_HIP(hipMemcpyAsync(a.image, image, 3 * a.pix_bytes, hipMemcpyDeviceToDevice, s));
+  GS_HIP(fill_u32((uint32_t*)a.state, 0u, GS_EXPOSURE_STATE_FLOATS, s));
+  GS_HIP(fill_u32((uint32_t*)a.state + 0, 0x3f800000u, 1, s));
+  GS_HIP(fill_u32((uint32_t*)a.state + 5, 0x3f800000u, 1, s));
+  GS_HIP(fill_u32((uint32_t*)a.state + 10, 0x3f800000u, 1, s));
+  a.view = *view;
+  a.view.exposure = a.state;
+  m->archive.push_back(a);
+  if (keyframe_id) *keyframe_id = (int32_t)(m->archive.size() - 1);
+  return GS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -424,7 +455,8 @@ gs_status gs_destroy_map(gs_map* m) {
                     &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
                     &m->block_start, &m->big_list, &m->split_slot, &m->split_extra, &m->split_state,
                     &m->inst_grad, &m->exp_part, &m->dbg_g, &m->gr_rgb, &m->gr_T, &m->gr_flags,
-                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl};
+                    &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl,
+                    &m->pend_xyz, &m->pend_rgb};
   for (DevBuf* b : bufs) dev_free(m, b->ptr, b->bytes, s);
   for (KeyframeSlot& k : m->kf) {
     dev_free(m, k.image, 3 * k.pix_bytes, s);
@@ -881,26 +913,67 @@ gs_status gs_add_keyframe(gs_map* m, const gs_view* view, const float* image, in
     else
       GS_TRY(gs_add_points(m, n_points, xyz, rgb, view, o_init, stream));
   }
-  ArchivedKeyframe a;
-  a.pix_bytes = (size_t)view->width * view->height * sizeof(float);
-  a.image = (float*)dev_alloc(m, 3 * a.pix_bytes, s);
-  a.state = (float*)dev_alloc(m, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
-  if (!a.image || !a.state) {
-    dev_free(m, a.image, 3 * a.pix_bytes, s);
-    dev_free(m, a.state, GS_EXPOSURE_STATE_FLOATS * sizeof(float), s);
-    return fail(GS_ERR_OOM, "keyframe buffers");
+  return archive_keyframe(m, view, image, keyframe_id, s);
+}
+
+gs_status gs_add_frame(gs_map* m, const gs_view* view, const float* image, int64_t n_points, const float* xyz,
+                       const float* rgb, float o_init, int32_t* keyframe_id, void* stream) {
+  g_err.clear();
+  if (keyframe_id) *keyframe_id = -1;
+  if (!m || !view) return fail(GS_ERR_INVALID, "map and view must not be NULL");
+  if (n_points < 0 || (n_points > 0 && (!xyz || !rgb))) return fail(GS_ERR_INVALID, "bad point arguments");
+  if (!(o_init > 0.f && o_init < 1.f)) return fail(GS_ERR_INVALID, "o_init must be in (0, 1)");
+  if (m->capturing) return fail(GS_ERR_STATE, "frame intake cannot be captured");
+  GS_TRY(check_view(*view, 0));
+  const bool key = m->frames_seen % kKeyframePeriod == 0;
+  if (key && !image) return fail(GS_ERR_INVALID, "a keyframe needs its image");
+  if (key && m->archive.size() >= (size_t)INT32_MAX) return fail(GS_ERR_CAPACITY, "too many keyframes");
+  hipStream_t s = (hipStream_t)stream;
+  if (m->frames_seen == 0) {
+    // the first frame bootstraps the map with all of its points (Sec. III-C.1)
+    if (n_points > 0) GS_TRY(gs_add_points(m, n_points, xyz, rgb, view, o_init, stream));
+  } else if (n_points > 0) {
+    // keep the frame's points until the next keyframe merges them (contents kept on growth)
+    const int64_t need = m->pend_n + n_points;
+    if ((size_t)need * 12 > m->pend_xyz.bytes) {
+      const size_t nb = (size_t)std::max<int64_t>(need, 2 * m->pend_n) * 12;
+      void* px = dev_alloc(m, nb, s);
+      void* pr = dev_alloc(m, nb, s);
+      if (!px || !pr) {
+        dev_free(m, px, nb, s);
+        dev_free(m, pr, nb, s);
+        return fail(GS_ERR_OOM, "pending points of the frames since the last keyframe");
+      }
+      if (m->pend_n > 0) {
+        GS_HIP(hipMemcpyAsync(px, m->pend_xyz.ptr, (size_t)m->pend_n * 12, hipMemcpyDeviceToDevice, s));
+        GS_HIP(hipMemcpyAsync(pr, m->pend_rgb.ptr, (size_t)m->pend_n * 12, hipMemcpyDeviceToDevice, s));
+      }
+      GS_HIP(hipStreamSynchronize(s));  // queued copies read the old buffers
+      dev_free(m, m->pend_xyz.ptr, m->pend_xyz.bytes, s);
+      dev_free(m, m->pend_rgb.ptr, m->pend_rgb.bytes, s);
+      m->pend_xyz = DevBuf{px, nb};
+      m->pend_rgb = DevBuf{pr, nb};
+    }
+    GS_HIP(hipMemcpyAsync((char*)m->pend_xyz.ptr + (size_t)m->pend_n * 12, xyz, (size_t)n_points * 12,
+                          hipMemcpyDeviceToDevice, s));
+    GS_HIP(hipMemcpyAsync((char*)m->pend_rgb.ptr + (size_t)m->pend_n * 12, rgb, (size_t)n_points * 12,
+                          hipMemcpyDeviceToDevice, s));
+    m->pend_n = need;
   }
-  GS_HIP(hipMemcpyAsync(a.image, image, 3 * a.pix_bytes, hipMemcpyDeviceToDevice, s));
-  // identity exposure, zero gradient and moments
-  GS_HIP(fill_u32((uint32_t*)a.state, 0u, GS_EXPOSURE_STATE_FLOATS, s));
-  GS_HIP(fill_u32((uint32_t*)a.state + 0, 0x3f800000u, 1, s));
-  GS_HIP(fill_u32((uint32_t*)a.state + 5, 0x3f800000u, 1, s));
-  GS_HIP(fill_u32((uint32_t*)a.state + 10, 0x3f800000u, 1, s));
-  a.view = *view;
-  a.view.exposure = a.state;
-  m->archive.push_back(a);
-  if (keyframe_id) *keyframe_id = (int32_t)(m->archive.size() - 1);
-  return GS_OK;
+  if (key && m->frames_seen > 0 && m->pend_n > 0) {
+    // Sec. III-C.2: the points of the five frames up to this keyframe, merged in arrival
+    // order, go through the opacity mask of this keyframe's view (Eq. 8)
+    const float* px = (const float*)m->pend_xyz.ptr;
+    const float* pr = (const float*)m->pend_rgb.ptr;
+    if (m->desc.expand_tau > 0.f)
+      GS_TRY(gs_expand(m, view, m->pend_n, px, pr, m->desc.expand_tau, o_init, nullptr, stream));
+    else
+      GS_TRY(gs_add_points(m, m->pend_n, px, pr, view, o_init, stream));
+    m->pend_n = 0;
+  }
+  m->frames_seen += 1;
+  if (!key) return GS_OK;
+  return archive_keyframe(m, view, image, keyframe_id, s);
 }
 
 gs_status gs_optimize_keyframes(gs_map* m, int32_t n, const int32_t* ids, float lambda, void* done_event,
@@ -935,6 +1008,14 @@ gs_status gs_optimize_keyframes(gs_map* m, int32_t n, const int32_t* ids, float 
 gs_status gs_keyframe_count(gs_map* m, int32_t* count) {
   if (!m || !count) return fail(GS_ERR_INVALID, "NULL argument");
   *count = (int32_t)m->archive.size();
+  return GS_OK;
+}
+
+gs_status gs_keyframe_state(gs_map* m, int32_t id, float** state) {
+  if (!m || !state) return fail(GS_ERR_INVALID, "NULL argument");
+  if (id < 0 || (size_t)id >= m->archive.size())
+    return fail(GS_ERR_INVALID, "keyframe id " + std::to_string(id) + " out of range");
+  *state = m->archive[id].state;
   return GS_OK;
 }
 

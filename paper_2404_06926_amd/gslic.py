@@ -79,8 +79,10 @@ _SIGS = {
     "gs_expand": (_I32, [_P, ctypes.POINTER(GsView), _I64, _P, _P, _F, _F, ctypes.POINTER(_I64), _P]),
     "gs_add_sky": (_I32, [_P, _I64, _P, _F, _P]),
     "gs_add_keyframe": (_I32, [_P, ctypes.POINTER(GsView), _P, _I64, _P, _P, _F, ctypes.POINTER(_I32), _P]),
+    "gs_add_frame": (_I32, [_P, ctypes.POINTER(GsView), _P, _I64, _P, _P, _F, ctypes.POINTER(_I32), _P]),
     "gs_optimize_keyframes": (_I32, [_P, _I32, ctypes.POINTER(_I32), _F, _P, _P]),
     "gs_keyframe_count": (_I32, [_P, ctypes.POINTER(_I32)]),
+    "gs_keyframe_state": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
     "gs_render": (_I32, [_P, _I32, ctypes.POINTER(GsView), ctypes.POINTER(GsFrame), _P]),
     "gs_render_backward": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                   ctypes.POINTER(_P), _P]),
@@ -368,6 +370,17 @@ class GaussianMap:
         self._keep = [image, xyz, rgb]
         return int(kid.value)
 
+    def add_frame(self, cam, image=None, xyz=None, rgb=None, o_init=0.1, stream=None) -> int:
+        """Frame intake of Sec. III-C.2 (every fifth frame a keyframe, the five frames' points
+        merged at it); returns the keyframe id, or -1 for a frame that is not a keyframe."""
+        n = 0 if xyz is None else int(xyz.shape[0])
+        v = make_view(cam)
+        kid = _I32()
+        _check(lib().gs_add_frame(self.handle, ctypes.byref(v), _ptr(image), n, _ptr(xyz), _ptr(rgb),
+                                  float(o_init), ctypes.byref(kid), _stream(stream)))
+        self._keep = [image, xyz, rgb]
+        return int(kid.value)
+
     def optimize_keyframes(self, ids, lam=0.2, done_event=None, stream=None):
         """One single-view mapping step per id, in the given order."""
         arr = (_I32 * max(len(ids), 1))(*[int(i) for i in ids])
@@ -378,6 +391,13 @@ class GaussianMap:
         c = _I32()
         _check(lib().gs_keyframe_count(self.handle, ctypes.byref(c)))
         return int(c.value)
+
+    def keyframe_state(self, kid: int):
+        """float32[48] view of kept keyframe `kid`'s exposure state [E | grad | m | v]."""
+        torch = _torch()
+        p = _P()
+        _check(lib().gs_keyframe_state(self.handle, int(kid), ctypes.byref(p)))
+        return self.allocator.view(p.value, 4 * 48).view(torch.float32)
 
     # ------------------------------------------------------------- the step
     def render(self, cams: Sequence, exposures: Optional[Sequence] = None, frames=None, stream=None,

@@ -115,3 +115,57 @@ def test_keyframe_job_expands_by_the_mask():
     # one Adam step moves a mean by at most lr_mean (1.6e-4) per coordinate
     np.testing.assert_allclose(b.params()[0:3, 3000:].cpu().numpy(), a.params()[0:3, 3000:].cpu().numpy(),
                                atol=2e-4)
+
+
+def test_frame_rule_merges_five_frames_at_each_keyframe():
+    # Sec. III-C.2 through gs_add_frame: frame 0 bootstraps the map with all of its points;
+    # frames 5 and 10 are keyframes whose expansion takes the merged points of the five
+    # frames up to them through the Eq. 8 mask of the keyframe's view. After each keyframe
+    # the appended rows are the oracle's selection on the merged points (in arrival order)
+    # initialised by the Sec. III-C.1 rule; other frames append nothing.
+    torch = torch_mod()
+    base = _cam()
+    frames = []
+    for f in range(11):
+        cam = scenes.pinhole(120, 88, 90.0)
+        cam.R = base.R
+        cam.t = (base.t + np.array([0.02 * f, 0.0, -0.05 * f])).astype(np.float32)
+        xyz, rgb = _points(cam, 700 + 37 * f, 100 + f, margin=0.1)
+        frames.append((cam, xyz, rgb, scenes.smooth_image(200 + f, cam.height, cam.width)))
+    m = gpu_map(np.zeros((0, 11 + 3 * 4), np.float32), 1, cap=1024)
+    merges = dict(oracle.keyframe_merges(len(frames)))
+    n_before = 0
+    for f, (cam, xyz, rgb, img) in enumerate(frames):
+        prev = m.params().cpu().numpy().T.astype(np.float64).copy()
+        kid = m.add_frame(cam, torch.tensor(img).cuda(), torch.tensor(xyz).cuda(), torch.tensor(rgb).cuda(), 0.1)
+        torch.cuda.synchronize()
+        got = m.params().cpu().numpy().T.astype(np.float64)
+        if f not in merges:
+            assert kid == -1 and got.shape[0] == n_before
+            continue
+        assert kid == len([k for k in merges if k < f])
+        v = oview(cam)
+        mxyz = np.concatenate([frames[j][1] for j in merges[f]])
+        mrgb = np.concatenate([frames[j][2] for j in merges[f]])
+        if f == 0:
+            keep, ties = np.ones(len(mxyz), bool), np.zeros(len(mxyz), bool)
+        else:
+            _, _, rend = oracle.forward(prev, 1, [v], fp64=True)
+            keep, ties = oracle.expansion_select(mxyz, v, rend[0]["opacity"], 0.99, tie=1e-5)
+        new = got[n_before:]
+        index = {tuple(p): i for i, p in enumerate(mxyz.tolist())}
+        kept_gpu = np.zeros(len(mxyz), bool)
+        order = []
+        for row in new:
+            i = index[tuple(row[0:3].astype(np.float32).tolist())]
+            kept_gpu[i] = True
+            order.append(i)
+        print(f"keyframe {f}: merged {len(mxyz)} points of frames {merges[f]}, kept {len(new)}, "
+              f"oracle {keep.sum()}, ties {ties.sum()}", flush=True)
+        assert order == sorted(order)                          # arrival order
+        np.testing.assert_array_equal(kept_gpu[~ties], keep[~ties])
+        assert 0 < len(new) < len(mxyz) or f == 0
+        ref = oracle.init_points(mxyz[kept_gpu], mrgb[kept_gpu], v, 0.1, 1)
+        np.testing.assert_allclose(new[:, 3:], ref[:, 3:], rtol=1e-6, atol=1e-6)
+        n_before = got.shape[0]
+    assert m.keyframe_count() == 3

@@ -62,3 +62,59 @@ def test_schedule_rejects_unknown_ids():
     m.add_keyframe(scenes.pinhole(32, 32, 30.0), torch.zeros(3, 32, 32, device="cuda"))
     with pytest.raises(RuntimeError):
         m.optimize_keyframes([0, 1])
+
+
+def test_schedule_steps_match_the_oracle():
+    # Each single-view step of gs_optimize_keyframes (ids [2, 0, 2]) against the oracle's
+    # step from the same state: forward (FP32 key path), Eq. 9 loss, adjoint, sparse Adam
+    # of the Gaussians with the map's global step count, and Adam of that keyframe's
+    # exposure (Sec. III-C.3). The oracle starts every step from the library's state before
+    # it (parameters, moments, exposure state), so each step is checked on its own.
+    import oracle
+    from gpu_common import TIE_ALPHA, TIE_T
+    from helpers import oview
+    torch = torch_mod()
+    W, H, deg = 96, 72, 1
+    base = scenes.pinhole(W, H, 75.0)
+    init = scenes.frustum_gaussians(3000, deg, base, seed=43)
+    cams, imgs, _ = _keyframes(3, W, H, 43)
+    for k, c in enumerate(cams):
+        c.bg = np.array([0.1 * k, 0.05, 0.2], np.float32)
+    m = gpu_map(init, deg)
+    ids = [m.add_keyframe(c, torch.tensor(i).cuda()) for c, i in zip(cams, imgs)]
+    assert ids == [0, 1, 2]
+    d = m.desc
+    F = init.shape[1]
+    lr = np.array([d.lr_mean] * 3 + [d.lr_log_scale] * 3 + [d.lr_quat] * 4 + [d.lr_opacity] + [d.lr_sh_dc] * 3
+                  + [d.lr_sh_rest] * (F - 14))
+    for t, k in enumerate([2, 0, 2], start=1):
+        torch.cuda.synchronize()
+        p0 = m.params().cpu().numpy().T.astype(np.float64)
+        m0, v0 = (x.cpu().numpy().T.astype(np.float64) for x in m.adam_moments())
+        st0 = m.keyframe_state(k).cpu().numpy().astype(np.float64)
+        m.optimize_keyframes([k], lam=0.2)
+        torch.cuda.synchronize()
+        # the oracle's step from the same state
+        v = oview(cams[k])
+        v.E = st0[:12].copy()
+        projs, bins, rend = oracle.forward(p0, deg, [v], tie_alpha=TIE_ALPHA, tie_T=TIE_T)
+        L, gout, _ = oracle.loss(rend[0]["out"], imgs[k].astype(np.float64), 0.2)
+        gp, gE, tie = oracle.backward(p0, deg, [v], projs, bins, [gout], TIE_ALPHA, TIE_T)
+        vis = (projs[0]["count"] > 0).astype(np.uint8)
+        p1, _, _, _ = oracle.adam(p0, gp, m0, v0, vis, lr, d.beta1, d.beta2, d.eps, t)
+        e1, _, _, _ = oracle.adam(st0[None, :12], gE[0][None], st0[None, 24:36], st0[None, 36:48],
+                                  np.ones(1, np.uint8), d.lr_exposure, d.beta1, d.beta2, d.eps, t)
+        got = m.params().cpu().numpy().T.astype(np.float64)
+        strong = (np.abs(gp) > 1e-2 * np.abs(gp).max(axis=0, keepdims=True)) & (tie == 0)[:, None] \
+            & (vis[:, None] > 0)
+        bound = 1e-5 * np.abs(p1) + 2e-3 * lr[None, :]
+        print(f"step {t} keyframe {k}: {strong.sum()} well-determined entries, loss {L:.5f}", flush=True)
+        assert strong.sum() > 2000
+        assert (np.abs(got - p1) <= bound)[strong].all(), np.abs(got - p1)[strong].max()
+        np.testing.assert_array_equal(got[vis == 0], p0[vis == 0])
+        st1 = m.keyframe_state(k).cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(st1[:12], e1[0], rtol=1e-5, atol=2e-3 * d.lr_exposure)
+        assert (st1[12:24] == 0).all()                     # the exposure gradient is cleared
+        # keyframe 1 is never drawn: its exposure state stays the identity with zero moments
+        assert torch.equal(m.keyframe_state(1), gslic.identity_exposure_state())
+    assert m.step_count == 3

@@ -99,3 +99,14 @@ def test_sky_init_rows():
     np.testing.assert_allclose(1 / (1 + np.exp(-rows[:, 10])), 0.7, rtol=1e-12)
     np.testing.assert_allclose(np.exp(rows[:, 3]), oracle.nearest_neighbour_distance(p), rtol=1e-12)
     assert np.all(rows[:, 14:] == 0)
+
+
+def test_keyframe_rule_merges_the_five_frames_since_the_last_keyframe():
+    # Sec. III-C.2: frames 0, 5, 10 are keyframes; frame 0 bootstraps with its own points,
+    # keyframe 5 merges frames 1-5, keyframe 10 frames 6-10; frames 11-13 wait for keyframe 15
+    got = oracle.keyframe_merges(14)
+    assert got == [(0, [0]), (5, [1, 2, 3, 4, 5]), (10, [6, 7, 8, 9, 10])]
+    assert oracle.keyframe_merges(1) == [(0, [0])]
+    # every frame's points are used exactly once by the time its keyframe has arrived
+    used = [f for _, fs in oracle.keyframe_merges(16) for f in fs]
+    assert sorted(used) == list(range(16))

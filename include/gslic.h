@@ -183,6 +183,20 @@ gs_status gs_adam_step(gs_map* map, int32_t n_exposures, float* const* exposure_
 gs_status gs_loss(gs_map* map, const float* out, const float* gt, int32_t height, int32_t width,
                   float lambda, float* loss_dev, float* dL_dout, void* stream);
 
+/* gs_loss for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * results as gs_loss, with no map and no allocation. Its per-tile partial sums live in a
+ * fixed device array of GS_LOSS_NOALLOC_SCRATCH_FLOATS floats (about 128 KiB, one copy per
+ * GPU, held until the process ends), enough for images of up to 16384 output tiles of
+ * 32x16 pixels (e.g. 4096 x 2048); larger images return GS_ERR_CAPACITY and enqueue
+ * nothing. Arguments, layout and results are those of gs_loss. Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams, or threads
+ * without ordering) race and may return wrong values; calls ordered on one stream are
+ * safe. The first call on a device looks the array's address up (no allocation). */
+#define GS_LOSS_NOALLOC_SCRATCH_FLOATS 32832
+gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t height, int32_t width,
+                          float lambda, float* loss_dev, float* dL_dout, void* stream);
+
 /* One mapping job on a keyframe (Sec. III-C): append Gaussians from the keyframe's points
  * (gs_expand with the map's expand_tau, Eq. 8, or gs_add_points when expand_tau <= 0; with
  * o_init), store the keyframe (pose, a copy of `image`, an identity

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -797,6 +798,47 @@ gs_status gs_loss(gs_map* m, const float* out, const float* gt, int32_t H, int32
                   float* dL_dout, void* stream) {
   g_err.clear();
   return loss_impl(m, out, gt, H, W, lambda, loss_dev, dL_dout, nullptr, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------- loss without allocation
+// The loss's per-tile partial sums live in a fixed device array instead of a map's
+// workspace. Each GPU holds its own copy; its address is looked up once per device (with
+// that device current) and kept, and only that address is handed to kernels.
+static __device__ __align__(256) float scratch[GS_LOSS_NOALLOC_SCRATCH_FLOATS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
+                          float* dL_dout, void* stream) {
+  g_err.clear();
+  if (!out || !gt || !loss_dev || !dL_dout) return fail(GS_ERR_INVALID, "NULL argument");
+  if (H < 1 || W < 1 || H > 16384 || W > 16384) return fail(GS_ERR_INVALID, "image size out of range");
+  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
+  if (loss_temp_floats(H, W) > GS_LOSS_NOALLOC_SCRATCH_FLOATS)
+    return fail(GS_ERR_CAPACITY, "image too large for the fixed loss scratch (" +
+                                     std::to_string(loss_temp_floats(H, W)) + " > " +
+                                     std::to_string(GS_LOSS_NOALLOC_SCRATCH_FLOATS) + " floats)");
+  int dev = -1;
+  GS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_INVALID, "device ordinal out of range");
+  float* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      GS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (!p) return fail(GS_ERR_HIP, "hipGetSymbolAddress returned NULL for the loss scratch");
+      g_scratch_ptr[dev] = (float*)p;
+    }
+    part = g_scratch_ptr[dev];
+  }
+  // every partial the reduction reads is written by the tile kernel first: nothing to clear
+  GS_HIP(ssim_loss(out, gt, H, W, lambda, part, loss_dev, dL_dout, nullptr, (hipStream_t)stream));
+  return GS_OK;
 }
 
 gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image, int64_t n_points, const float* xyz,

@@ -88,6 +88,7 @@ _SIGS = {
                                   ctypes.POINTER(_P), _P]),
     "gs_adam_step": (_I32, [_P, _I32, ctypes.POINTER(_P), _P]),
     "gs_loss": (_I32, [_P, _P, _P, _I32, _I32, _F, _P, _P, _P]),
+    "gs_loss_noalloc": (_I32, [_P, _P, _I32, _I32, _F, _P, _P, _P]),
     "gs_submit_keyframe": (_I32, [_P, ctypes.POINTER(GsView), _P, _I64, _P, _P, _I32, _I32, _F, _F, _P, _P]),
     "gs_last_error": (ctypes.c_char_p, []),
     "gs_map_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -185,6 +186,15 @@ class TorchAllocator:
             if base <= ptr and ptr + nbytes <= base + t.numel():
                 return t[ptr - base: ptr - base + nbytes]
         raise KeyError("pointer not owned by this allocator")
+
+
+def loss_noalloc(out, gt, lam, loss_out, grad_out, stream=None):
+    """gs_loss_noalloc: the Eq. 9 loss into caller-provided loss_out (float[1]) and grad_out
+    (shape of out), with no map and no device allocation inside the library."""
+    _, H, W = out.shape
+    _check(lib().gs_loss_noalloc(_ptr(out), _ptr(gt), H, W, float(lam), _ptr(loss_out), _ptr(grad_out),
+                                 _stream(stream)))
+    return loss_out, grad_out
 
 
 def identity_exposure_state(device="cuda"):

@@ -106,7 +106,7 @@ def test_fullsize_gradients_of_sampled_gaussians(name):
     sel = rng.choice(cand, size=min(20000, cand.size), replace=False)
     ok, err = grad_close(g_gpu[sel], gp[sel])
     print(f"{name}: {sel.size} Gaussians, {ok.mean():.6f} of elements within bar, worst {err.max():.2e}", flush=True)
-    assert ok.mean() >= 0.999
+    assert ok.all(), err.max()
     for k in range(len(cams)):
         np.testing.assert_allclose(gexp[k].cpu().numpy(), gE[k], rtol=1e-3, atol=1e-4 * np.abs(gE[k]).max())
 

@@ -38,6 +38,12 @@ def _oracle(name):
     return _ORACLE[name]
 
 
+# Least fraction of the visible Gaussians that must be compared (not touching a tie pixel),
+# per case, just under what the oracle's tie marking leaves: c1 0.965, c3a and ragged 1.0,
+# multi 0.889 (three views, so more Gaussians touch some tie), dense 0.906 (long opaque
+# lists stop close to the 1e-4 transmittance limit).
+COMPARED_FLOOR = {"c1": 0.95, "c3a": 0.99, "ragged": 0.99, "multi": 0.88, "dense": 0.9}
+
 # (pixels per lane, deterministic backward) of the blend kernels
 BLEND = [(1, False), (2, False), (4, False)]
 BWD = [(n, px, det) for n in CASES for px, det in BLEND] + [(n, px, True) for n in ("c3a", "multi") for px in (1, 2, 4)]
@@ -158,11 +164,11 @@ def _check_backward(name, px, det, mode, split=None):
     g_gpu = m.grads().cpu().numpy().T
     sel = vis_ref & (tie == 0)
     print(f"Gaussians compared: {sel.sum()} of {vis_ref.sum()} visible", flush=True)
-    assert sel.sum() > 0.75 * vis_ref.sum()
+    assert sel.sum() >= COMPARED_FLOOR[name] * vis_ref.sum()
     ok, err = grad_close(g_gpu[sel], gp[sel])
     frac = ok.mean()
     print(f"grad elements within bar: {frac:.6f}, worst {err.max():.3e}, tie Gaussians {int((tie > 0).sum())}")
-    assert frac >= 0.999, (frac, err.max())
+    assert ok.all(), (frac, err.max())
     for k, c in enumerate(cams):
         np.testing.assert_allclose(gexp[k].cpu().numpy(), gE[k], rtol=1e-3,
                                    atol=1e-4 * np.abs(gE[k]).max())
@@ -226,11 +232,11 @@ def test_backward_with_map_gradients_matches_oracle(name, px, det, split):
         vis_ref |= pr["count"] > 0
     g_gpu = m.grads().cpu().numpy().T
     sel = vis_ref & (tie == 0)
-    assert sel.sum() > 0.75 * vis_ref.sum()
+    assert sel.sum() >= COMPARED_FLOOR[name] * vis_ref.sum()
     ok, err = grad_close(g_gpu[sel], gp[sel])
     frac = ok.mean()
     print(f"grad elements within bar: {frac:.6f}, worst {err.max():.3e}", flush=True)
-    assert frac >= 0.999, (frac, err.max())
+    assert ok.all(), (frac, err.max())
     for k, c in enumerate(cams):
         np.testing.assert_allclose(gexp[k].cpu().numpy(), gE[k], rtol=1e-3, atol=1e-4 * np.abs(gE[k]).max())
 
@@ -247,7 +253,10 @@ def test_loss_matches_oracle():
         L, gref, _ = oracle.loss(out.astype(np.float64), gt.astype(np.float64), 0.2)
         np.testing.assert_allclose(lo.item(), L, rtol=2e-5)
         ok, err = grad_close(g.cpu().numpy().reshape(-1, 1), gref.reshape(-1, 1))
-        assert ok.mean() >= 0.999, (ok.mean(), err.max())
+        print(f"loss {H}x{W}: {ok.mean():.6f} of gradient elements within bar, worst {err.max():.3e}", flush=True)
+        # the SSIM terms subtract nearly equal FP32 moments (E[x^2] - mu^2), so about 1e-3
+        # of the elements exceed 1e-3 relative (worst measured 1.3e-2 at 1280x720)
+        assert ok.mean() >= 0.999 and err.max() <= 2e-2, (ok.mean(), err.max())
 
 
 def test_sparse_adam_matches_oracle():
@@ -291,13 +300,18 @@ def test_sparse_adam_matches_oracle():
     np.testing.assert_allclose(m.params().cpu().numpy().T, p2, rtol=1e-6, atol=1e-7)
 
 
-def test_batched_equals_per_view_launches():
+@pytest.mark.parametrize("split", ["whole", "default"])
+def test_batched_equals_per_view_launches(split):
     torch = torch_mod()
     params, deg, cams = case("multi")
     m = gpu_map(params, deg)
-    # the long-list split depends on the batch's mean list length: keep every tile whole so
-    # that the same lists are blended in the same order
-    m.set_tile_split(0, 256, 2.0)
+    if split == "whole":
+        # every tile blended whole: the same lists in the same order, so the images are
+        # bit-identical and the gradients differ only by atomic summation order
+        m.set_tile_split(0, 256, 2.0)
+    # "default": the long-list split depends on the batch's mean list length, so a batch
+    # may cut a list that a single view keeps whole; chunks composite in depth order, so the
+    # two agree within FP32 rounding
     ex = exposures(cams)
     batched = m.render(cams, ex)
     rng = np.random.default_rng(5)
@@ -308,11 +322,17 @@ def test_batched_equals_per_view_launches():
     m.visibility().zero_()
     for k, c in enumerate(cams):
         single = m.render([c], [ex[k]])
-        assert torch.equal(single[0].rgb, batched[k].rgb)
-        assert torch.equal(single[0].n_contrib, batched[k].n_contrib)
+        if split == "whole":
+            assert torch.equal(single[0].rgb, batched[k].rgb)
+            assert torch.equal(single[0].n_contrib, batched[k].n_contrib)
+        else:
+            assert (single[0].rgb - batched[k].rgb).abs().max().item() <= 1e-5
+            same = (single[0].n_contrib == batched[k].n_contrib).float().mean().item()
+            assert same >= 0.999, same
         m.render_backward([gouts[k]])
     ok, err = grad_close(m.grads().cpu().numpy().T, gb.cpu().numpy().T, rel=1e-4)
-    assert ok.mean() > 0.999, err.max()
+    print(f"split {split}: {ok.mean():.6f} of gradient elements within 1e-4, worst {err.max():.3e}", flush=True)
+    assert ok.mean() > 0.999 and err.max() <= 1e-3, (ok.mean(), err.max())
 
 
 def test_autograd_function_against_fp64_adjoint():
@@ -330,7 +350,7 @@ def test_autograd_function_against_fp64_adjoint():
     gp, gE, tie = oracle.backward(params, deg, views, projs, bins, [w], TIE_ALPHA, TIE_T)
     sel = (projs[0]["count"] > 0) & (tie == 0)
     ok, err = grad_close(gp_t.cpu().numpy().T[sel], gp[sel])
-    assert ok.mean() >= 0.999, err.max()
+    assert ok.all(), err.max()
     np.testing.assert_allclose(ge_t.cpu().numpy(), gE[0], rtol=1e-3, atol=1e-4 * np.abs(gE[0]).max())
 
 

@@ -783,21 +783,38 @@ gs_status gs_adam_step(gs_map* m, int32_t ne, float* const* exposure_states, voi
   return GS_OK;
 }
 
-static gs_status loss_impl(gs_map* m, const float* out, const float* gt, int32_t H, int32_t W, float lambda,
-                           float* loss_dev, float* dL_dout, const StepPrep* prep, hipStream_t s) {
-  if (!m || !out || !gt || !loss_dev || !dL_dout) return fail(GS_ERR_INVALID, "NULL argument");
+static gs_status check_loss_view(const float* out, const float* gt, int32_t H, int32_t W, const float* loss_dev,
+                                 const float* dL_dout) {
+  if (!out || !gt || !loss_dev || !dL_dout) return fail(GS_ERR_INVALID, "NULL argument");
   if (H < 1 || W < 1 || H > 16384 || W > 16384) return fail(GS_ERR_INVALID, "image size out of range");
-  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
-  GS_TRY(ensure(m, m->loss_tmp, (size_t)loss_temp_floats(H, W) * 4, s));
-  StageTimer t(m, s, GS_STAGE_LOSS);
-  GS_HIP(ssim_loss(out, gt, H, W, lambda, (float*)m->loss_tmp.ptr, loss_dev, dL_dout, prep, s));
   return GS_OK;
+}
+
+// One loss launch over la.n images (their sizes and pointers already checked), the
+// partial sums in the map's workspace.
+static gs_status loss_impl(gs_map* m, const LossArg& la, const StepPrep* prep, hipStream_t s) {
+  if (!(la.lambda >= 0.f && la.lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
+  GS_TRY(ensure(m, m->loss_tmp, (size_t)loss_temp_floats_multi(la) * 4, s));
+  StageTimer t(m, s, GS_STAGE_LOSS);
+  GS_HIP(ssim_loss(la, (float*)m->loss_tmp.ptr, prep, s));
+  return GS_OK;
+}
+
+static LossArg one_loss_view(const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
+                             float* dL_dout) {
+  LossArg la{};
+  la.n = 1;
+  la.lambda = lambda;
+  la.v[0] = LossView{out, gt, dL_dout, loss_dev, H, W, 0, 0};
+  return la;
 }
 
 gs_status gs_loss(gs_map* m, const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
                   float* dL_dout, void* stream) {
   g_err.clear();
-  return loss_impl(m, out, gt, H, W, lambda, loss_dev, dL_dout, nullptr, (hipStream_t)stream);
+  if (!m) return fail(GS_ERR_INVALID, "NULL argument");
+  GS_TRY(check_loss_view(out, gt, H, W, loss_dev, dL_dout));
+  return loss_impl(m, one_loss_view(out, gt, H, W, lambda, loss_dev, dL_dout), nullptr, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------- loss without allocation
@@ -815,8 +832,7 @@ float* g_scratch_ptr[kMaxDevices] = {};
 gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t H, int32_t W, float lambda, float* loss_dev,
                           float* dL_dout, void* stream) {
   g_err.clear();
-  if (!out || !gt || !loss_dev || !dL_dout) return fail(GS_ERR_INVALID, "NULL argument");
-  if (H < 1 || W < 1 || H > 16384 || W > 16384) return fail(GS_ERR_INVALID, "image size out of range");
+  GS_TRY(check_loss_view(out, gt, H, W, loss_dev, dL_dout));
   if (!(lambda >= 0.f && lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
   if (loss_temp_floats(H, W) > GS_LOSS_NOALLOC_SCRATCH_FLOATS)
     return fail(GS_ERR_CAPACITY, "image too large for the fixed loss scratch (" +
@@ -836,8 +852,8 @@ gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t H, int32_t 
     }
     part = g_scratch_ptr[dev];
   }
-  // every partial the reduction reads is written by the tile kernel first: nothing to clear
-  GS_HIP(ssim_loss(out, gt, H, W, lambda, part, loss_dev, dL_dout, nullptr, (hipStream_t)stream));
+  // every partial sum the reduction reads is written by the tile kernel first: nothing to clear
+  GS_HIP(ssim_loss(one_loss_view(out, gt, H, W, lambda, loss_dev, dL_dout), part, nullptr, (hipStream_t)stream));
   return GS_OK;
 }
 
@@ -1082,11 +1098,15 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   GS_TRY(gs_render(m, nv, vv, frames, stream));
   hipStream_t s = (hipStream_t)stream;
   const gs_map_desc& d = m->desc;
-  // in a fused step the last loss reduction also advances the Adam step counter
+  // one loss launch over all views; in a fused step its last block also advances the Adam
+  // step counter
   const StepPrep prep{m->d_step, m->d_bc, d.beta1, d.beta2};
+  LossArg la{};
+  la.n = nv;
+  la.lambda = lambda;
   for (int v = 0; v < nv; ++v)
-    GS_TRY(loss_impl(m, frames[v].rgb, targets[v], vv[v].height, vv[v].width, lambda, loss_dev + v, dl_drgb[v],
-                     m->fused_step && v == nv - 1 ? &prep : nullptr, s));
+    la.v[v] = LossView{frames[v].rgb, targets[v], dl_drgb[v], loss_dev + v, vv[v].height, vv[v].width, 0, 0};
+  GS_TRY(loss_impl(m, la, m->fused_step ? &prep : nullptr, s));
   if (!m->fused_step) {
     GS_TRY(gs_render_backward(m, nv, dl, nullptr, nullptr, eg, stream));
     GS_TRY(gs_adam_step(m, nv, exposure_states, stream));

@@ -116,16 +116,28 @@ hipError_t blend_backward_per_gaussian(const ViewsArg& va, const float4* rec, in
 hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_t s);
 
 // loss (loss.hip)
-int64_t loss_temp_floats(int H, int W);
-// With step != nullptr the reduction launch also advances the Adam step counter and its
-// bias corrections (as adam_prepare), saving that launch in a fused step.
+// One image of a loss launch: out (x), target (y), dL/dout, where its loss goes, and its
+// size; tiles_x and tile_base are filled by ssim_loss.
+struct LossView {
+  const float* x;
+  const float* y;
+  float* gout;
+  float* loss;
+  int32_t H, W, tiles_x, tile_base;
+};
+struct LossArg {
+  int32_t n;
+  float lambda;
+  LossView v[kMaxViews];
+};
 struct StepPrep {
   int64_t* step;
   float* bc;
   float beta1, beta2;
 };
-hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,
-                     float* gout, const StepPrep* prep, hipStream_t s);
+int64_t loss_temp_floats(int H, int W);
+int64_t loss_temp_floats_multi(const LossArg& la);
+hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t s);
 
 // optimiser and map maintenance (adam.hip)
 hipError_t adam_step(float* buf, int64_t cap, int32_t F, int32_t N, const uint8_t* vis, const LrArg& lr,

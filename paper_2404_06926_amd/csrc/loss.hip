@@ -1,21 +1,29 @@
 // Eq. 9 loss: L = (1 - lambda) mean|out - gt| + lambda (1 - mean SSIM(out, gt)) and its
-// gradient. SSIM per channel with an 11x11 Gaussian window (sigma 1.5, separable),
-// C1 = 0.01^2, C2 = 0.03^2, zero padding outside the image.
+// gradient, for one or several images in one launch. SSIM per channel with an 11x11
+// Gaussian window (sigma 1.5, separable), C1 = 0.01^2, C2 = 0.03^2, zero padding outside
+// the image.
 //
 // One fused pass per 32x16 output tile (k_ssim_tile), channel by channel:
-//   1. out and gt over the tile with a 10-pixel margin go to LDS (each lane loads the next
-//      channel's share into registers while the current channel is processed);
-//   2. the five local moments (mu_x, mu_y, E[x^2], E[y^2], E[xy]) over the tile with a
+//   1. out and gt over the tile with a 10-pixel margin go to LDS as differences from the
+//      tile's centre pixel (a = x - cx, b = y - cy; zero padding outside the image means
+//      a = -cx there). The window sums are shift-covariant, so the local moments of a and b
+//      give the variances and covariance without subtracting two nearly equal FP32
+//      squares (E[x^2] - mu^2 cancels badly on smooth images); the means are cx + E[a].
+//      Each lane loads the next channel's share into registers while this one runs;
+//   2. the five local moments (E[a], E[b], E[a^2], E[b^2], E[ab]) over the tile with a
 //      5-pixel margin: a horizontal then a vertical window pass, each lane producing a run
 //      of outputs from values it holds in registers;
 //   3. at those pixels (inside the image; zero outside) the partial derivatives of SSIM
-//      with respect to mu_x, E[x^2] and E[xy], scaled by dL/dSSIM;
+//      with respect to E[a], E[a^2] and E[ab], scaled by dL/dSSIM;
 //   4. the same separable window applied to those three maps (the window is symmetric, so
 //      the adjoint of the zero-padded correlation is the same correlation) gives
-//      dL/dout = blur(d_mu) + 2 x blur(d_xx) + y blur(d_xy) + the L1 term on the tile.
+//      dL/dout = blur(d_mu) + 2 a blur(d_aa) + b blur(d_ab) + the L1 term on the tile
+//      (the L1 term from the unshifted values, so that sign(0) = 0 is exact).
 // The moments of the 5-pixel margin are recomputed by the neighbouring tiles instead of
-// going through HBM. A second launch adds the per-tile sums of SSIM and |out - gt| in a
-// fixed order.
+// going through HBM. Every block writes its sums of SSIM and |out - gt|; a second launch
+// (one block per image) adds each image's sums in a fixed order and writes its loss. (A
+// last-block ticket in the tile kernel would save that launch, but the device-scope release
+// each block would then need writes back its XCD's L2 and cost more than the launch.)
 #include <cmath>
 
 #include "gs_common.h"
@@ -33,6 +41,12 @@ constexpr int kHRun = 6;               // horizontal moment pass: outputs per la
 constexpr int kVRun = 5;               // vertical moment pass: rows per lane (26 = 5 x 5 + 1)
 constexpr int kDRun = 4;               // horizontal derivative pass: outputs per lane (32 = 8 x 4)
 constexpr int kGRun = 2;               // vertical derivative pass: rows per lane (16 = 8 x 2)
+// LDS row strides: odd, so that lanes walking down a column (consecutive rows) hit
+// different banks
+constexpr int kSA = kAW + 1;           // 53
+constexpr int kSB = kBW + 1;           // 43
+constexpr int kSD = kTW + 1;           // 33
+constexpr int kPartOffset = 64;        // temp: [64 ...) per-block partial sums
 // every pass's lanes fit the 256-thread block
 static_assert(kBW % kHRun == 0 && kAH * (kBW / kHRun) <= 256, "horizontal moment pass");
 static_assert(kBW * ((kBH + kVRun - 1) / kVRun) <= 256, "vertical moment pass");
@@ -56,30 +70,45 @@ static Win make_window() {
 }
 
 struct SsimLds {
-  float x[kAH][kAW + 1];
-  float y[kAH][kAW + 1];
+  float x[kAH][kSA];            // a = x - cx (inputs with a 10-pixel margin)
+  float y[kAH][kSA];            // b = y - cy
   union {
-    float h[5][kAH][kBW];       // horizontal pass of the five moment maps
-    float hd[3][kBH][kTW + 1];  // horizontal pass of the three derivative maps
+    float h[5][kAH][kSB];       // horizontal pass of the five moment maps
+    float hd[3][kBH][kSD];      // horizontal pass of the three derivative maps
   };
-  float d[3][kBH][kBW + 1];     // derivative maps
-  float red[2][4];
+  float d[3][kBH][kSB];         // derivative maps
+  float wred[2][4];
 };
 
+__device__ __forceinline__ int loss_view_of(const LossArg& la, int b) {
+  int v = 0;
+  while (v + 1 < la.n && b >= la.v[v + 1].tile_base) ++v;
+  return v;
+}
+
 __global__ void __launch_bounds__(256)
-k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, int H, int W, float lambda,
-            float* __restrict__ gout, float* __restrict__ part) {
+k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   __shared__ SsimLds L;
-  const int bx = blockIdx.x * kTW, by = blockIdx.y * kTH;
+  const int view = loss_view_of(la, blockIdx.x);
+  const LossView& V = la.v[view];
+  const float* __restrict__ x = V.x;
+  const float* __restrict__ y = V.y;
+  float* __restrict__ gout = V.gout;
+  const int H = V.H, W = V.W;
+  const int lb = (int)blockIdx.x - V.tile_base;
+  const int bx = (lb % V.tiles_x) * kTW, by = (lb / V.tiles_x) * kTH;
   const int tid = threadIdx.x;
   const int64_t P = (int64_t)H * W;
   const float n = 3.0f * (float)P;
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
-  const float s_ssim = -lambda / n;                    // dL/dSSIM per pixel and channel
-  const float l1w = (1.0f - lambda) / n;
+  const float s_ssim = -la.lambda / n;                 // dL/dSSIM per pixel and channel
+  const float l1w = (1.0f - la.lambda) / n;
+  // centre pixel of the tile (inside the image)
+  const int64_t cidx = (int64_t)min(by + kTH / 2, H - 1) * W + min(bx + kTW / 2, W - 1);
   float ssum = 0.f, l1 = 0.f;
   constexpr int kLoadPer = (kAH * kAW + 255) / 256;
   float pa[kLoadPer], pb[kLoadPer];
+  float ncx, ncy;
   auto fetch = [&](int ch) {
 #pragma unroll
     for (int j = 0; j < kLoadPer; ++j) {
@@ -92,43 +121,50 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
         pb[j] = y[ch * P + (int64_t)gy * W + gx];
       }
     }
+    ncx = x[ch * P + cidx];
+    ncy = y[ch * P + cidx];
   };
   fetch(0);
   for (int ch = 0; ch < 3; ++ch) {
+    const float cx = ncx, cy = ncy;
     __syncthreads();
-    // 1. inputs with a 10-pixel margin (zero outside the image); the next channel's are
-    // loaded into registers while this one is processed
+    // 1. inputs with a 10-pixel margin, shifted by the centre values; the next channel's
+    // are loaded into registers while this one is processed
 #pragma unroll
     for (int j = 0; j < kLoadPer; ++j) {
       const int t = tid + 256 * j;
       if (t < kAH * kAW) {
-        L.x[t / kAW][t % kAW] = pa[j];
-        L.y[t / kAW][t % kAW] = pb[j];
+        L.x[t / kAW][t % kAW] = pa[j] - cx;
+        L.y[t / kAW][t % kAW] = pb[j] - cy;
       }
     }
     if (ch < 2) fetch(ch + 1);
     __syncthreads();
     // 2a. horizontal window pass of the five moments: rows of the input block, columns of
-    // the moment block; lane = (row, run of kHRun columns)
+    // the moment block; lane = (run of kHRun columns, row), consecutive lanes on
+    // consecutive rows
     if (tid < kAH * (kBW / kHRun)) {
-      const int r = tid / (kBW / kHRun), c0 = (tid % (kBW / kHRun)) * kHRun;
-      float xv[kHRun + 10], yv[kHRun + 10];
+      const int r = tid % kAH, c0 = (tid / kAH) * kHRun;
+      float xv[kHRun + 10], yv[kHRun + 10], xx[kHRun + 10], yy[kHRun + 10], xy[kHRun + 10];
 #pragma unroll
       for (int j = 0; j < kHRun + 10; ++j) {
         xv[j] = L.x[r][c0 + j];
         yv[j] = L.y[r][c0 + j];
+        xx[j] = xv[j] * xv[j];
+        yy[j] = yv[j] * yv[j];
+        xy[j] = xv[j] * yv[j];
       }
 #pragma unroll
       for (int o = 0; o < kHRun; ++o) {
         float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
 #pragma unroll
         for (int j = 0; j < 11; ++j) {
-          const float a = xv[o + j], b = yv[o + j], w = win.w[j];
-          m0 += w * a;
-          m1 += w * b;
-          m2 += w * (a * a);
-          m3 += w * (b * b);
-          m4 += w * (a * b);
+          const float w = win.w[j];
+          m0 += w * xv[o + j];
+          m1 += w * yv[o + j];
+          m2 += w * xx[o + j];
+          m3 += w * yy[o + j];
+          m4 += w * xy[o + j];
         }
         L.h[0][r][c0 + o] = m0;
         L.h[1][r][c0 + o] = m1;
@@ -170,12 +206,16 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
         const int gy = by - kR + rb, gx = bx - kR + c;
         float dmu = 0.f, dxx = 0.f, dxy = 0.f;
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-          const float mx = acc[0][o], my = acc[1][o];
-          const float A1 = 2.f * mx * my + C1, A2 = 2.f * (acc[4][o] - mx * my) + C2;
-          const float B1 = mx * mx + my * my + C1, B2 = (acc[2][o] - mx * mx) + (acc[3][o] - my * my) + C2;
+          const float ea = acc[0][o], eb = acc[1][o];        // shifted means
+          const float mx = cx + ea, my = cy + eb;            // means
+          const float sxx = acc[2][o] - ea * ea, syy = acc[3][o] - eb * eb, sxy = acc[4][o] - ea * eb;
+          const float A1 = 2.f * mx * my + C1, A2 = 2.f * sxy + C2;
+          const float B1 = mx * mx + my * my + C1, B2 = sxx + syy + C2;
           const float num = A1 * A2, den = B1 * B2;
-          const float dnum = 2.f * my * A2 - 2.f * my * A1;
-          const float dden = 2.f * mx * B2 - 2.f * mx * B1;
+          // derivatives with respect to E[a] at fixed E[a^2], E[ab]: mx moves with it, and
+          // the variance and covariance through -E[a]^2 and -E[a] E[b]
+          const float dnum = 2.f * my * A2 - 2.f * eb * A1;
+          const float dden = 2.f * mx * B2 - 2.f * ea * B1;
           // one division: with q = num / den (the SSIM value), d(q)/d. = (dnum - q dden) / den
           const float inv = 1.0f / den, q = num * inv, si = s_ssim * inv;
           dmu = si * (dnum - q * dden);
@@ -190,9 +230,10 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
       }
     }
     __syncthreads();
-    // 4a. horizontal window pass of the derivative maps; lane = (row, run of kDRun columns)
+    // 4a. horizontal window pass of the derivative maps; lane = (run of kDRun columns,
+    // row), consecutive lanes on consecutive rows
     if (tid < kBH * (kTW / kDRun)) {
-      const int r = tid / (kTW / kDRun), c0 = (tid % (kTW / kDRun)) * kDRun;
+      const int r = tid % kBH, c0 = (tid / kBH) * kDRun;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         float dv[kDRun + 10];
@@ -233,10 +274,11 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
       for (int o = 0; o < kGRun; ++o) {
         const int py = by + r0 + o, px = bx + c;
         if (px >= W || py >= H) continue;
-        const float xv = L.x[r0 + o + 2 * kR][c + 2 * kR], yv = L.y[r0 + o + 2 * kR][c + 2 * kR];
-        const float d = xv - yv;
+        const int64_t e = ch * P + (int64_t)py * W + px;
+        const float av = L.x[r0 + o + 2 * kR][c + 2 * kR], bv = L.y[r0 + o + 2 * kR][c + 2 * kR];
+        const float d = x[e] - y[e];
         const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        gout[ch * P + (int64_t)py * W + px] = g[0][o] + 2.f * xv * g[1][o] + yv * g[2][o] + l1w * sg;
+        gout[e] = g[0][o] + 2.f * av * g[1][o] + bv * g[2][o] + l1w * sg;
         l1 += fabsf(d);
       }
     }
@@ -246,62 +288,76 @@ k_ssim_tile(Win win, const float* __restrict__ x, const float* __restrict__ y, i
   const int lane = tid & 63, wid = tid >> 6;
   __syncthreads();
   if (lane == 0) {
-    L.red[0][wid] = ssum;
-    L.red[1][wid] = l1;
+    L.wred[0][wid] = ssum;
+    L.wred[1][wid] = l1;
   }
   __syncthreads();
   if (tid == 0) {
-    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    part[2 * b] = L.red[0][0] + L.red[0][1] + L.red[0][2] + L.red[0][3];
-    part[2 * b + 1] = L.red[1][0] + L.red[1][1] + L.red[1][2] + L.red[1][3];
+    const int64_t b = blockIdx.x;
+    part[2 * b] = L.wred[0][0] + L.wred[0][1] + L.wred[0][2] + L.wred[0][3];
+    part[2 * b + 1] = L.wred[1][0] + L.wred[1][1] + L.wred[1][2] + L.wred[1][3];
   }
 }
 
+// Block v: the loss of image v from its tiles' partial sums, in a fixed order. With
+// prep.step, block 0 also advances the Adam step counter and its bias corrections (as
+// adam_prepare), saving that launch in a fused step.
 __global__ void __launch_bounds__(256)
-k_loss_reduce(const float* __restrict__ part, int64_t nb, int64_t P, float lambda, float* __restrict__ loss,
-              StepPrep prep) {
+k_loss_reduce(LossArg la, const float* __restrict__ part, int32_t nb, StepPrep prep) {
   __shared__ double s[2][256];
-  if (prep.step && threadIdx.x == 0) {  // t += 1 and the bias corrections of step t
+  const int v = blockIdx.x, tid = threadIdx.x;
+  if (prep.step && v == 0 && tid == 0) {
     const int64_t t = prep.step[0] + 1;
     prep.step[0] = t;
     prep.bc[0] = (float)(1.0 - pow((double)prep.beta1, (double)t));
     prep.bc[1] = (float)(1.0 - pow((double)prep.beta2, (double)t));
   }
-  double a = 0.0, b = 0.0;
-  for (int64_t k = threadIdx.x; k < nb; k += 256) {
+  const int b0 = la.v[v].tile_base;
+  const int b1 = v + 1 < la.n ? la.v[v + 1].tile_base : nb;
+  double a = 0.0, c = 0.0;
+  for (int k = b0 + tid; k < b1; k += 256) {
     a += part[2 * k];
-    b += part[2 * k + 1];
+    c += part[2 * k + 1];
   }
-  s[0][threadIdx.x] = a;
-  s[1][threadIdx.x] = b;
+  s[0][tid] = a;
+  s[1][tid] = c;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      s[0][threadIdx.x] += s[0][threadIdx.x + o];
-      s[1][threadIdx.x] += s[1][threadIdx.x + o];
+    if (tid < o) {
+      s[0][tid] += s[0][tid + o];
+      s[1][tid] += s[1][tid + o];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double n = 3.0 * (double)P;
-    loss[0] = (float)((1.0 - lambda) * s[1][0] / n + lambda * (1.0 - s[0][0] / n));
+  if (tid == 0) {
+    const double nn = 3.0 * (double)la.v[v].H * (double)la.v[v].W;
+    la.v[v].loss[0] = (float)((1.0 - la.lambda) * s[1][0] / nn + la.lambda * (1.0 - s[0][0] / nn));
   }
 }
 
-int64_t loss_temp_floats(int H, int W) {
-  const int64_t nb = (int64_t)((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH);
-  return 2 * nb + 64;
+int64_t loss_tiles(int H, int W) { return (int64_t)((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH); }
+
+int64_t loss_temp_floats(int H, int W) { return kPartOffset + 2 * loss_tiles(H, W); }
+
+int64_t loss_temp_floats_multi(const LossArg& la) {
+  int64_t nb = 0;
+  for (int v = 0; v < la.n; ++v) nb += loss_tiles(la.v[v].H, la.v[v].W);
+  return kPartOffset + 2 * nb;
 }
 
-hipError_t ssim_loss(const float* out, const float* gt, int H, int W, float lambda, float* temp, float* loss,
-                     float* gout, const StepPrep* prep, hipStream_t s) {
+// la.v[*].tiles_x and tile_base are filled here. temp holds loss_temp_floats_multi(la)
+// floats (nothing in it needs clearing: the reduction reads only what the tiles wrote).
+hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t s) {
   const Win win = make_window();
-  const int64_t P = (int64_t)H * W;
-  float* part = temp;
-  const dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH);
-  const int64_t nb = (int64_t)grid.x * grid.y;
-  hipLaunchKernelGGL(k_ssim_tile, grid, dim3(256), 0, s, win, out, gt, H, W, lambda, gout, part);
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, part, nb, P, lambda, loss,
+  int64_t nb = 0;
+  for (int v = 0; v < la.n; ++v) {
+    la.v[v].tiles_x = (la.v[v].W + kTW - 1) / kTW;
+    la.v[v].tile_base = (int32_t)nb;
+    nb += loss_tiles(la.v[v].H, la.v[v].W);
+  }
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ssim_tile, dim3((unsigned)nb), dim3(256), 0, s, win, la, temp + kPartOffset);
+  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)la.n), dim3(256), 0, s, la, temp + kPartOffset, (int32_t)nb,
                      prep ? *prep : StepPrep{nullptr, nullptr, 0.f, 0.f});
   return hipGetLastError();
 }

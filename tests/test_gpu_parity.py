@@ -254,9 +254,11 @@ def test_loss_matches_oracle():
         np.testing.assert_allclose(lo.item(), L, rtol=2e-5)
         ok, err = grad_close(g.cpu().numpy().reshape(-1, 1), gref.reshape(-1, 1))
         print(f"loss {H}x{W}: {ok.mean():.6f} of gradient elements within bar, worst {err.max():.3e}", flush=True)
-        # the SSIM terms subtract nearly equal FP32 moments (E[x^2] - mu^2), so about 1e-3
-        # of the elements exceed 1e-3 relative (worst measured 1.3e-2 at 1280x720)
-        assert ok.mean() >= 0.999 and err.max() <= 2e-2, (ok.mean(), err.max())
+        # the kernel forms the moments about each tile's centre pixel; what is left is the
+        # FP32 sum blur(d_mu) + 2a blur(d_aa) + b blur(d_ab), whose terms can cancel: one
+        # element in 10^5 exceeds 1e-3 relative (measured worst 3.0e-3 at 256x192, 5.5e-4
+        # at 1280x720)
+        assert ok.mean() >= 0.9999 and err.max() <= 5e-3, (ok.mean(), err.max())
 
 
 def test_sparse_adam_matches_oracle():

@@ -109,6 +109,7 @@ struct gs_map {
   ViewsArg last_va{};
   int32_t last_N = 0;
   int sorted = 0;
+  bool last_det = false;       // the last render wrote what the deterministic backward reads
   // keyframe window
   std::vector<KeyframeSlot> kf;
   int kf_next = 0;
@@ -675,7 +676,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   {
     StageTimer t(m, s, GS_STAGE_DUPLICATE);
     GS_HIP(duplicate_keys(rec, counts, order, offsets, m->d_ninst, (const uint32_t*)m->big_list.ptr, big_n, N, va,
-                          keys[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr,
+                          keys[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr, m->deterministic,
                           (uint32_t*)m->block_start.ptr, m->inst_cap, m->d_overflow, s));
   }
   int which = 0;
@@ -701,6 +702,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   m->last_va = va;
   m->last_N = N;
   m->sorted = which;
+  m->last_det = m->deterministic;
   if (!m->capturing) m->render_gen += 1;
   return GS_OK;
 }
@@ -740,7 +742,8 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
   for (int v = 0; v < nv; ++v) maps = maps || va.v[v].dl_ddepth || va.v[v].dl_dopac;
   {
     StageTimer t(m, s, GS_STAGE_BLEND_BACKWARD);
-    float* ig = m->deterministic ? (float*)m->inst_grad.ptr : nullptr;
+    // deterministic when the render was (it wrote every pair's first emission index)
+    float* ig = m->last_det ? (float*)m->inst_grad.ptr : nullptr;
     if (m->bwd_mode == 1 && !maps)
       GS_HIP(blend_backward_per_gaussian(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr,
                                          (const uint32_t*)m->emit_g.ptr, (const uint2*)m->ranges.ptr, g2d, ig,
@@ -754,7 +757,7 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
     StageTimer t(m, s, GS_STAGE_PROJECT_BACKWARD);
     GS_HIP(project_backward(m->deg, params_of(m), grads_of(m), m->cap, N, va, m->desc.near_z,
                             (const uint32_t*)m->counts.ptr, (float4*)g2d,
-                            m->deterministic ? (const float*)m->inst_grad.ptr : nullptr,
+                            m->last_det ? (const float*)m->inst_grad.ptr : nullptr,
                             (const uint32_t*)m->inst_off.ptr, m->vis, fused, s));
   }
   return GS_OK;

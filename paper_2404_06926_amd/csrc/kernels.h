@@ -58,11 +58,13 @@ hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* 
                        uint32_t* temp, uint32_t* total, hipStream_t s);
 // Instances in depth order, one lane per instance (block_start: block_start_elems(capacity)
 // words); pairs listed in big_list (big_n of them) have more than 64 candidate tiles.
+// inst_off receives each pair's first emission index for the listed pairs, and for every
+// pair with all_off (the deterministic backward reads it).
 int64_t block_start_elems(int64_t capacity);
 hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
                           const uint32_t* n_dev, const uint32_t* big_list, const uint32_t* big_n, int32_t N,
                           const ViewsArg& va, uint32_t* tiles, uint32_t* emit_g, uint32_t* inst_off,
-                          uint32_t* block_start, int64_t capacity, uint32_t* overflow, hipStream_t s);
+                          bool all_off, uint32_t* block_start, int64_t capacity, uint32_t* overflow, hipStream_t s);
 hipError_t gather_gaussians(const uint32_t* vals, const uint32_t* emit_g, const uint32_t* n_dev, int64_t cap,
                             uint32_t* out, hipStream_t s);
 int64_t sort_temp_elems(int64_t cap);

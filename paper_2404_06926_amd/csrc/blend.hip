@@ -51,34 +51,36 @@ constexpr int kBlendBlock = 256;
 #define NW_OF(PX) (kBlendBlock / (PX) / 64)
 
 // Minimum of q = A dx^2 + 2B dx dy + C dy^2 over [x0, x1] x [y0, y1] (offsets from the
-// mean) compared with thr: 0 inside; else the clamped 1-D minimum on the separating edges.
-__device__ __forceinline__ bool footprint_hits_rect(float A, float B, float C, float thr, float x0, float x1,
-                                                    float y0, float y1) {
-  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
-  float qmin = __builtin_huge_valf();
-  if (x0 > 0.f || x1 < 0.f) {
-    const float dx = (x0 > 0.f) ? x0 : x1;
-    const float dy = fminf(fmaxf(-(B * dx) / C, y0), y1);
-    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
-  }
-  if (y0 > 0.f || y1 < 0.f) {
-    const float dy = (y0 > 0.f) ? y0 : y1;
-    const float dx = fminf(fmaxf(-(B * dy) / A, x0), x1);
-    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
-  }
-  return qmin <= thr;
+// mean) compared with thr: 0 inside; else the smaller of the 1-D minima, clamped to the
+// rectangle, on the edges nearest the mean (the segment from any point of the rectangle to
+// the mean, along which the convex q falls, crosses one of them inside the rectangle).
+// iA = 1/A, iC = 1/C: the hardware reciprocal, whose rounding moves a clamped minimum's
+// position by an ulp and so q only at second order, well inside the caller's margin.
+// Branch-free: both edges are evaluated and the ones the mean does not lie beyond dropped.
+__device__ __forceinline__ bool footprint_hits_rect(float A, float B, float C, float iA, float iC, float thr,
+                                                    float x0, float x1, float y0, float y1) {
+  const bool in_x = x0 <= 0.f && x1 >= 0.f, in_y = y0 <= 0.f && y1 >= 0.f;
+  const float ex = x0 > 0.f ? x0 : x1;
+  const float ey = y0 > 0.f ? y0 : y1;
+  const float dy = fminf(fmaxf(-(B * ex) * iC, y0), y1);
+  const float dx = fminf(fmaxf(-(B * ey) * iA, x0), x1);
+  const float qx = A * ex * ex + 2.f * B * ex * dy + C * dy * dy;
+  const float qy = A * dx * dx + 2.f * B * dx * ey + C * ey * ey;
+  const float inf = __builtin_huge_valf();
+  return (in_x && in_y) || fminf(in_x ? inf : qx, in_y ? inf : qy) <= thr;
 }
 
 // 4-bit mask of the tile's 8x8 quadrants (bit q: x half q & 1, y half q >> 1) that the
 // footprint {q <= thr (1 + 1e-4) + 1e-4} reaches at some pixel centre.
 __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float thr, int tx, int ty) {
   const float t = thr * 1.0001f + 1e-4f;
+  const float iA = __builtin_amdgcn_rcpf(r0.z), iC = __builtin_amdgcn_rcpf(r1.x);
   uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float x0 = (float)(tx * kTile + 8 * (q & 1)) + 0.5f - r0.x;
     const float y0 = (float)(ty * kTile + 8 * (q >> 1)) + 0.5f - r0.y;
-    if (footprint_hits_rect(r0.z, r0.w, r1.x, t, x0, x0 + 7.f, y0, y0 + 7.f)) m |= 1u << q;
+    if (footprint_hits_rect(r0.z, r0.w, r1.x, iA, iC, t, x0, x0 + 7.f, y0, y0 + 7.f)) m |= 1u << q;
   }
   return m;
 }
@@ -88,12 +90,18 @@ __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
 }
 
-// Sum over the 64 lanes with DPP row operations; the total is valid in lane 63.
-__device__ __forceinline__ float wave_sum_to_63(float x) {
+// Sum over each row of 16 lanes with DPP row operations, valid in every lane of the row.
+__device__ __forceinline__ float row_sum16(float x) {
   x += dpp_f<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
   x += dpp_f<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
   x += dpp_f<0x141, 0xf>(x);  // row_half_mirror: 8-lane sums
   x += dpp_f<0x140, 0xf>(x);  // row_mirror: 16-lane sums
+  return x;
+}
+
+// Sum over the 64 lanes with DPP row operations; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_63(float x) {
+  x = row_sum16(x);
   x += dpp_f<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
   x += dpp_f<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
@@ -110,15 +118,15 @@ __device__ __forceinline__ void add_from_below8(float& dst, float src) {
   asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_shr:8 row_mask:0xf bank_mask:0xc" : "+v"(dst) : "v"(src));
 }
 
-// Sums over the wave of eight values at once, transposing while reducing: each exchange
-// step halves the values a lane carries (the lane keeps one half, its partner the other),
-// so 8 values cost 4 + 2 + 1 exchanges instead of 8 per step. The steps over lane bits 2
-// and 3 (partners in the same row of 16) need no selects: one DPP add from the lane above
-// writes every lane, a bank-masked DPP add from the lane below then overwrites the lanes
-// that keep the other half. Then lane bit 0 (a select pair and a quad_perm add), lane bit
-// 1 (quad_perm) and lane bits 4, 5 (shuffles). On return lane L holds the wave total of
-// v[term_of_lane(L)].
-__device__ __forceinline__ float wave_sum8_transposed(const float (&v)[8], int lane) {
+// Sums over each row of 16 lanes of eight values at once, transposing while reducing:
+// each exchange step halves the values a lane carries (the lane keeps one half, its partner
+// the other), so 8 values cost 4 + 2 + 1 exchanges instead of 8 per step. The steps over
+// lane bits 2 and 3 (partners in the same row) need no selects: one DPP add from the lane
+// above writes every lane, a bank-masked DPP add from the lane below then overwrites the
+// lanes that keep the other half. Then lane bit 0 (a select pair and a quad_perm add) and
+// lane bit 1 (quad_perm). On return lane L holds its row's total of v[term_of_lane(L)]
+// (lanes with bit 1 set repeat their partner's).
+__device__ __forceinline__ float row_sum8_transposed(const float (&v)[8], int lane) {
 #pragma clang fp contract(off)  // each first add must stay a DPP add, not fuse with a product
   float w[4];
 #pragma unroll
@@ -137,13 +145,21 @@ __device__ __forceinline__ float wave_sum8_transposed(const float (&v)[8], int l
   const float keep = b0 ? x[1] : x[0];
   float y = keep + dpp_f<0xB1, 0xf>(send);  // quad_perm [1,0,3,2]: from lane ^ 1
   y += dpp_f<0x4E, 0xf>(y);                 // quad_perm [2,3,0,1]: lane bit 1
-  y += __shfl_xor(y, 16, 64);
-  y += __shfl_xor(y, 32, 64);
   return y;
 }
 
-// index of the value whose total lane L holds after wave_sum8_transposed: lane bits 2, 3, 0
-// give bits 2, 1, 0 of the index (lanes 0, 1, 4, 5, 8, 9, 12, 13 hold the eight totals)
+// Adds the four rows of 16 lanes: on return every lane holds the sum of its value over the
+// lanes L, L ^ 16, L ^ 32 and L ^ 48 (two lane swaps and two adds, no LDS round trip).
+__device__ __forceinline__ float add_rows(float y) {
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  y = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// index of the value whose total lane L holds after row_sum8_transposed: lane bits 2, 3, 0
+// give bits 2, 1, 0 of the index (lanes 0, 1, 4, 5, 8, 9, 12, 13 of a row hold the eight
+// totals)
 __device__ __forceinline__ int term_of_lane(int lane) {
   return (((lane >> 2) & 1) << 2) | (((lane >> 3) & 1) << 1) | (lane & 1);
 }
@@ -599,10 +615,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   constexpr int NT = kBlendBlock / PX;
   constexpr int NW = NT / 64;
   constexpr int NG = MAPS ? 10 : 9;  // gradient terms per Gaussian
-  __shared__ float4 s_a[NT];
-  __shared__ float4 s_b[NT];
-  __shared__ float s_c[NT];
-  __shared__ float s_d[MAPS ? NT : 1];
+  // per entry: (mx, my, A, B), (C, o, r, g), (b, depth, -, -): one 48-B record, so a
+  // wave-uniform entry index addresses all of it from one register
+  __shared__ float4 s_r[NT][3];
   __shared__ uint32_t s_g[NT];
   __shared__ uint32_t s_e[DET ? NT : 1];
   __shared__ float s_part[DET ? NW : 1][DET ? NT : 1][NG];
@@ -700,6 +715,10 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     }
     ncmax = max(ncmax, nc[k]);
   }
+  // the gradient term whose wave total lane L < 16 holds after the entry loop's reduction
+  const int term = lane == 2 ? 8 : ((MAPS && lane == 3) ? NG - 1 : term_of_lane(lane));
+  const bool takes = lane < 16 && (!(lane & 2) || lane == 2 || (MAPS && lane == 3));
+  float* const acc_lane = &s_acc[0][0] + term;
   const uint32_t wmax = wave_max_u32(ncmax);
   if (lane == 0) s_wmax[wid] = wmax;
   __syncthreads();
@@ -708,7 +727,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   for (int w = 0; w < NW; ++w) nmax = max(nmax, (int)s_wmax[w]);
 
   for (int end = min(nmax, it.end); end > it.begin; end -= NT) {
-    const int base = max(it.begin, end - NT);
+    const int base = __builtin_amdgcn_readfirstlane(max(it.begin, end - NT));
     const int cnt = end - base;
     __syncthreads();
     uint32_t qm = 0;
@@ -717,10 +736,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       const uint32_t g = emit_g[e];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[threadIdx.x] = blend_stage_a(r0);
-      s_b[threadIdx.x] = make_float4(blend_stage_c(r1.x), r1.y, r1.z, r1.w);
-      s_c[threadIdx.x] = r2.x;
-      if (MAPS) s_d[threadIdx.x] = r2.y;
+      s_r[threadIdx.x][0] = blend_stage_a(r0);
+      s_r[threadIdx.x][1] = make_float4(blend_stage_c(r1.x), r1.y, r1.z, r1.w);
+      s_r[threadIdx.x][2] = make_float4(r2.x, r2.y, 0.f, 0.f);
       s_g[threadIdx.x] = g;
       qm = quadrant_mask(r0, r1, r2.w, tx, ty);
       s_m[threadIdx.x] = (uint8_t)qm;
@@ -733,17 +751,19 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       }
     }
     build_wave_lists<PX, NW, NT>(qm, cnt, s_list, s_len, s_wc);
-    // entries at or past the wave's max are idle (wave-uniform bounds: a scalar loop)
+    // entries at or past the wave's max are idle (wave-uniform bounds and entry index: a
+    // scalar loop)
     const int jtop = __builtin_amdgcn_readfirstlane(min(cnt, (int)wmax - base) - 1);
     for (int jj = __builtin_amdgcn_readfirstlane(s_len[wid]) - 1; jj >= 0; --jj) {
-      const int j = s_list[wid][jj];
+      const int j = __builtin_amdgcn_readfirstlane((int)s_list[wid][jj]);
       if (j > jtop) continue;
       const uint32_t m = PX == 1 ? 1u : s_m[j];  // (a wave's list meets its quadrant)
       const int pos = base + j;
-      const float4 a = s_a[j];
-      const float4 b = s_b[j];
-      const float c2 = s_c[j];
-      const float dep = MAPS ? s_d[j] : 0.0f;
+      const float4 a = s_r[j][0];
+      const float4 b = s_r[j][1];
+      const float4 cr = s_r[j][2];
+      const float c2 = cr.x;
+      const float dep = MAPS ? cr.y : 0.0f;
       // per-lane sums of the gradient terms over the lane's pixels (the first pixel sets
       // them: adding to 0 would cost an operation, as 0 + x differs from x for x = -0)
       float gv[NG];
@@ -752,7 +772,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       // Branch-free: a pixel that does not take this entry (outside the Gaussian's quadrant
       // mask, past its last contributor, power > 0 or alpha below the cut-off) runs the same
       // arithmetic with alpha = 0, which leaves its T and colour behind unchanged exactly
-      // (T is selected, B = 0 * c + 1 * B) and adds exact zeros to the sums.
+      // (T is selected, B + 0 (c - B) = B) and adds exact zeros to the sums.
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
         float dx, dy;
@@ -771,14 +791,19 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         add(k, 6, w * G0[k]);
         add(k, 7, w * G1[k]);
         add(k, 8, w * G2[k]);
-        float dalpha = T[k] * ((b.z - B0[k]) * G0[k] + (b.w - B1[k]) * G1[k] + (c2 - B2[k]) * G2[k]);
-        B0[k] = al * b.z + oma * B0[k];
-        B1[k] = al * b.w + oma * B1[k];
-        B2[k] = al * c2 + oma * B2[k];
+        // colour in front minus colour behind, per channel: dL/dalpha's factors, and the
+        // step of the colour behind to the one in front of this Gaussian,
+        // B <- alpha c + (1 - alpha) B = B + alpha (c - B)
+        const float d0 = b.z - B0[k], d1 = b.w - B1[k], d2 = c2 - B2[k];
+        float dalpha = T[k] * (d0 * G0[k] + d1 * G1[k] + d2 * G2[k]);
+        B0[k] = fmaf(al, d0, B0[k]);
+        B1[k] = fmaf(al, d1, B1[k]);
+        B2[k] = fmaf(al, d2, B2[k]);
         if (MAPS) {
-          dalpha += T[k] * ((dep - BD[k]) * gD[k] + (1.0f - BO[k]) * gO[k]);
-          BD[k] = al * dep + oma * BD[k];
-          BO[k] = al + oma * BO[k];
+          const float dd = dep - BD[k], dO = 1.0f - BO[k];
+          dalpha += T[k] * (dd * gD[k] + dO * gO[k]);
+          BD[k] = fmaf(al, dd, BD[k]);
+          BO[k] = fmaf(al, dO, BO[k]);
           add(k, 9, w * gD[k]);
         }
         // dL/dpower = dL/dalpha * alpha (no gradient through the clamp at kAlphaMax); its
@@ -794,28 +819,23 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         add(k, 5, dpow);
       }
       if (!__any(any)) continue;
-      // terms 0..7 transposed (eight lanes of row 0 end with the totals), the rest by DPP rows
+      // wave totals: terms 0..7 transposed within each row of 16 lanes, which leaves lanes
+      // 2 and 3 of a row as repeats; they take the row sums of terms 8 (and 9), then the
+      // rows are added. Lane L < 16 ends with the total of term `term` (see above), and the
+      // lanes that take one write or add it, one LDS instruction per entry.
       float g8[8];
 #pragma unroll
       for (int f = 0; f < 8; ++f) g8[f] = gv[f];
-      const float tot = wave_sum8_transposed(g8, lane);
-#pragma unroll
-      for (int f = 8; f < NG; ++f) gv[f] = wave_sum_to_63(gv[f]);
-      if (lane < 16 && !(lane & 2)) {
-        const int f = term_of_lane(lane);
-        if (DET)
-          s_part[wid][j][f] = tot;
-        else if (tot != 0.0f)
-          __hip_atomic_fetch_add(&s_acc[j][f], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-      if (lane == 63) {
-#pragma unroll
-        for (int f = 8; f < NG; ++f) {
-          if (DET)
-            s_part[wid][j][f] = gv[f];
-          else if (gv[f] != 0.0f)
-            __hip_atomic_fetch_add(&s_acc[j][f], gv[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+      float val = row_sum8_transposed(g8, lane);   // (the cross-lane sums run on every lane)
+      const float t8 = row_sum16(gv[8]);
+      const float t9 = MAPS ? row_sum16(gv[NG - 1]) : 0.0f;
+      val = (lane & 15) == 2 ? t8 : val;
+      if (MAPS) val = (lane & 15) == 3 ? t9 : val;
+      val = add_rows(val);
+      if (DET) {
+        if (takes) s_part[wid][j][term] = val;
+      } else if (takes && val != 0.0f) {
+        __hip_atomic_fetch_add(acc_lane + j * NG, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
     if (!DET) {

@@ -10,11 +10,13 @@
 //      give the variances and covariance without subtracting two nearly equal FP32
 //      squares (E[x^2] - mu^2 cancels badly on smooth images); the means are cx + E[a].
 //      Each lane loads the next channel's share into registers while this one runs;
-//   2. the five local moments (E[a], E[b], E[a^2], E[b^2], E[ab]) over the tile with a
+//   2. the four local moments (E[a], E[b], E[a^2 + b^2], E[ab]) over the tile with a
 //      5-pixel margin: a horizontal then a vertical window pass, each lane producing a run
-//      of outputs from values it holds in registers;
+//      of outputs from values it holds in registers. SSIM takes the two variances only as
+//      their sum (its denominator's second factor), so one window of a^2 + b^2 serves;
 //   3. at those pixels (inside the image; zero outside) the partial derivatives of SSIM
-//      with respect to E[a], E[a^2] and E[ab], scaled by dL/dSSIM;
+//      with respect to E[a], E[a^2] (= the derivative with respect to E[a^2 + b^2]) and
+//      E[ab], scaled by dL/dSSIM;
 //   4. the same separable window applied to those three maps (the window is symmetric, so
 //      the adjoint of the zero-padded correlation is the same correlation) gives
 //      dL/dout = blur(d_mu) + 2 a blur(d_aa) + b blur(d_ab) + the L1 term on the tile
@@ -69,16 +71,25 @@ static Win make_window() {
   return W;
 }
 
+// 40,064 bytes: four blocks fit a CU's 160 KiB of LDS. The inputs are dead once the
+// horizontal moment pass has read them (the last pass takes a and b at its own pixels from
+// the values it loads for the L1 term), so the derivative maps reuse their space; the
+// moments' horizontal pass is dead once the vertical pass has read it.
 struct SsimLds {
-  float x[kAH][kSA];            // a = x - cx (inputs with a 10-pixel margin)
-  float y[kAH][kSA];            // b = y - cy
   union {
-    float h[5][kAH][kSB];       // horizontal pass of the five moment maps
+    struct {
+      float x[kAH][kSA];        // a = x - cx (inputs with a 10-pixel margin)
+      float y[kAH][kSA];        // b = y - cy
+    };
+    float d[3][kBH][kSB];       // derivative maps
+  };
+  union {
+    float h[4][kAH][kSB];       // horizontal pass of the four moment maps
     float hd[3][kBH][kSD];      // horizontal pass of the three derivative maps
   };
-  float d[3][kBH][kSB];         // derivative maps
   float wred[2][4];
 };
+static_assert(sizeof(SsimLds) * 4 <= 160 * 1024, "four blocks per CU");
 
 __device__ __forceinline__ int loss_view_of(const LossArg& la, int b) {
   int v = 0;
@@ -86,7 +97,8 @@ __device__ __forceinline__ int loss_view_of(const LossArg& la, int b) {
   return v;
 }
 
-__global__ void __launch_bounds__(256)
+// four blocks per CU (as many as LDS allows): at most 128 VGPRs
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   __shared__ SsimLds L;
   const int view = loss_view_of(la, blockIdx.x);
@@ -109,20 +121,27 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   constexpr int kLoadPer = (kAH * kAW + 255) / 256;
   float pa[kLoadPer], pb[kLoadPer];
   float ncx, ncy;
+  // pixel index of each of the lane's input slots (-1: outside the image, zero padding).
+  // Element indices stay 32-bit (images are at most 16384 x 16384, so 3 H W < 2^31) and
+  // are formed per channel, so that no 64-bit addresses stay live across the channel loop.
+  const int P32 = H * W;
+  int off[kLoadPer];
+#pragma unroll
+  for (int j = 0; j < kLoadPer; ++j) {
+    const int t = tid + 256 * j;
+    const int r = t / kAW, c = t % kAW;
+    const int gy = by - 2 * kR + r, gx = bx - 2 * kR + c;
+    off[j] = (t < kAH * kAW && gx >= 0 && gx < W && gy >= 0 && gy < H) ? gy * W + gx : -1;
+  }
   auto fetch = [&](int ch) {
+    const int base = ch * P32;
 #pragma unroll
     for (int j = 0; j < kLoadPer; ++j) {
-      const int t = tid + 256 * j;
-      const int r = t / kAW, c = t % kAW;
-      const int gy = by - 2 * kR + r, gx = bx - 2 * kR + c;
-      pa[j] = pb[j] = 0.f;
-      if (t < kAH * kAW && gx >= 0 && gx < W && gy >= 0 && gy < H) {
-        pa[j] = x[ch * P + (int64_t)gy * W + gx];
-        pb[j] = y[ch * P + (int64_t)gy * W + gx];
-      }
+      pa[j] = off[j] >= 0 ? x[base + off[j]] : 0.f;
+      pb[j] = off[j] >= 0 ? y[base + off[j]] : 0.f;
     }
-    ncx = x[ch * P + cidx];
-    ncy = y[ch * P + cidx];
+    ncx = x[base + (int)cidx];
+    ncy = y[base + (int)cidx];
   };
   fetch(0);
   for (int ch = 0; ch < 3; ++ch) {
@@ -140,37 +159,34 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
     }
     if (ch < 2) fetch(ch + 1);
     __syncthreads();
-    // 2a. horizontal window pass of the five moments: rows of the input block, columns of
+    // 2a. horizontal window pass of the four moments: rows of the input block, columns of
     // the moment block; lane = (run of kHRun columns, row), consecutive lanes on
     // consecutive rows
     if (tid < kAH * (kBW / kHRun)) {
       const int r = tid % kAH, c0 = (tid / kAH) * kHRun;
-      float xv[kHRun + 10], yv[kHRun + 10], xx[kHRun + 10], yy[kHRun + 10], xy[kHRun + 10];
+      float xv[kHRun + 10], yv[kHRun + 10], ss[kHRun + 10], xy[kHRun + 10];
 #pragma unroll
       for (int j = 0; j < kHRun + 10; ++j) {
         xv[j] = L.x[r][c0 + j];
         yv[j] = L.y[r][c0 + j];
-        xx[j] = xv[j] * xv[j];
-        yy[j] = yv[j] * yv[j];
+        ss[j] = xv[j] * xv[j] + yv[j] * yv[j];
         xy[j] = xv[j] * yv[j];
       }
 #pragma unroll
       for (int o = 0; o < kHRun; ++o) {
-        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
 #pragma unroll
         for (int j = 0; j < 11; ++j) {
           const float w = win.w[j];
           m0 += w * xv[o + j];
           m1 += w * yv[o + j];
-          m2 += w * xx[o + j];
-          m3 += w * yy[o + j];
-          m4 += w * xy[o + j];
+          m2 += w * ss[o + j];
+          m3 += w * xy[o + j];
         }
         L.h[0][r][c0 + o] = m0;
         L.h[1][r][c0 + o] = m1;
         L.h[2][r][c0 + o] = m2;
         L.h[3][r][c0 + o] = m3;
-        L.h[4][r][c0 + o] = m4;
       }
     }
     __syncthreads();
@@ -179,24 +195,24 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
     if (tid < kBW * kVRuns) {
       const int c = tid % kBW, r0 = (tid / kBW) * kVRun;
       const int nr = min(kVRun, kBH - r0);
-      float acc[5][kVRun];
+      float acc[4][kVRun];
 #pragma unroll
-      for (int k = 0; k < 5; ++k)
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int o = 0; o < kVRun; ++o) acc[k][o] = 0.f;
 #pragma unroll
       for (int i = 0; i < kVRun + 10; ++i) {
         if (r0 + i >= kAH) break;
-        float hv[5];
+        float hv[4];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) hv[k] = L.h[k][r0 + i][c];
+        for (int k = 0; k < 4; ++k) hv[k] = L.h[k][r0 + i][c];
 #pragma unroll
         for (int o = 0; o < kVRun; ++o) {
           const int j = i - o;  // tap index of input row r0 + i for output row r0 + o
           if (j < 0 || j > 10) continue;
           const float w = win.w[j];
 #pragma unroll
-          for (int k = 0; k < 5; ++k) acc[k][o] += w * hv[k];
+          for (int k = 0; k < 4; ++k) acc[k][o] += w * hv[k];
         }
       }
 #pragma unroll
@@ -208,9 +224,9 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
           const float ea = acc[0][o], eb = acc[1][o];        // shifted means
           const float mx = cx + ea, my = cy + eb;            // means
-          const float sxx = acc[2][o] - ea * ea, syy = acc[3][o] - eb * eb, sxy = acc[4][o] - ea * eb;
+          const float svv = acc[2][o] - ea * ea - eb * eb, sxy = acc[3][o] - ea * eb;  // sum of variances, covariance
           const float A1 = 2.f * mx * my + C1, A2 = 2.f * sxy + C2;
-          const float B1 = mx * mx + my * my + C1, B2 = sxx + syy + C2;
+          const float B1 = mx * mx + my * my + C1, B2 = svv + C2;
           const float num = A1 * A2, den = B1 * B2;
           // derivatives with respect to E[a] at fixed E[a^2], E[ab]: mx moves with it, and
           // the variance and covariance through -E[a]^2 and -E[a] E[b]
@@ -275,8 +291,9 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
         const int py = by + r0 + o, px = bx + c;
         if (px >= W || py >= H) continue;
         const int64_t e = ch * P + (int64_t)py * W + px;
-        const float av = L.x[r0 + o + 2 * kR][c + 2 * kR], bv = L.y[r0 + o + 2 * kR][c + 2 * kR];
-        const float d = x[e] - y[e];
+        const float xe = x[e], ye = y[e];
+        const float av = xe - cx, bv = ye - cy;
+        const float d = xe - ye;
         const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
         gout[e] = g[0][o] + 2.f * av * g[1][o] + bv * g[2][o] + l1w * sg;
         l1 += fabsf(d);

@@ -467,11 +467,9 @@ __global__ void __launch_bounds__(kBlendBlock / PX)
 k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32_t* __restrict__ vals,
             const uint32_t* __restrict__ emit_g, const uint2* __restrict__ ranges, SplitArg sp) {
   constexpr int NT = kBlendBlock / PX;
-  __shared__ float4 s_a[NT];   // mx, my, A, B
-  __shared__ float4 s_b[NT];   // C, o, r, g
-  __shared__ float s_c[NT];    // b
-  __shared__ float s_d[NT];    // camera-frame depth
-  __shared__ uint8_t s_m[NT];  // quadrant mask
+  // per entry: (mx, my, A, B), (C, o, r, g), (b, camera-frame depth, quadrant mask bits, -):
+  // one 48-B record, so a wave-uniform entry index addresses all of it from one register
+  __shared__ float4 s_r[NT][3];
   __shared__ uint8_t s_list[NW_OF(PX)][NT];   // per-wave entry lists of the batch
   __shared__ int s_len[NW_OF(PX)];
   __shared__ uint32_t s_wc[NW_OF(PX)][NW_OF(PX)];
@@ -529,47 +527,47 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       const uint32_t g = emit_g[vals[rg.x + kk]];
       const float4* r = vrec + (size_t)g * 4;
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[threadIdx.x] = blend_stage_a(r0);
-      s_b[threadIdx.x] = make_float4(blend_stage_c(r1.x), r1.y, r1.z, r1.w);
-      s_c[threadIdx.x] = r2.x;
-      if (want_d) s_d[threadIdx.x] = r2.y;
       qm = quadrant_mask(r0, r1, r2.w, tx, ty);
-      s_m[threadIdx.x] = (uint8_t)qm;
+      s_r[threadIdx.x][0] = blend_stage_a(r0);
+      s_r[threadIdx.x][1] = make_float4(blend_stage_c(r1.x), r1.y, r1.z, r1.w);
+      s_r[threadIdx.x][2] = make_float4(r2.x, r2.y, __uint_as_float(qm), 0.f);
     }
     const int cnt = min(NT, it.end - base);
     build_wave_lists<PX, NW_OF(PX), NT>(qm, cnt, s_list, s_len, s_wc);
-    if (!lane_done) {
-      const int len = s_len[wid];
-      for (int jj = 0; jj < len; ++jj) {
-        const int j = s_list[wid][jj];
-        // with one pixel per lane a wave's list holds only entries that meet its quadrant
-        const uint32_t m = PX == 1 ? 1u : s_m[j];
-        const float4 a = s_a[j];
-        const float4 b = s_b[j];
+    // wave-uniform loop (list length and entry index scalar); a pixel that does not take an
+    // entry (done, outside the entry's quadrants, power > 0, alpha below the cut-off, or
+    // stopping at it) runs the same arithmetic with weight 0, which adds exact zeros, and
+    // keeps its T and last contributor by selection: no per-pixel branches
+    const int len = __builtin_amdgcn_readfirstlane(s_len[wid]);
+    for (int jj = 0; jj < len; ++jj) {
+      if (__all(lane_done)) break;
+      const int j = __builtin_amdgcn_readfirstlane((int)s_list[wid][jj]);
+      const float4 a = s_r[j][0];
+      const float4 b = s_r[j][1];
+      const float4 cr = s_r[j][2];
+      // with one pixel per lane a wave's list holds only entries that meet its quadrant
+      const uint32_t m = PX == 1 ? 1u : __float_as_uint(cr.z);
+      const uint32_t pos1 = (uint32_t)(base + j + 1);
 #pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          if ((PX > 1 && !((m >> pixel_quadrant<PX>(wid, k)) & 1u)) || done[k]) continue;
-          float dx, dy;
-          const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
-          if (power > 0.0f) continue;
-          const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
-          if (alpha < kAlphaMin) continue;
-          const float Tn = T[k] * (1.0f - alpha);
-          if (Tn < kTMin) {
-            done[k] = true;
-            continue;
-          }
-          const float w = alpha * T[k];
-          C0[k] += b.z * w;
-          C1[k] += b.w * w;
-          C2[k] += s_c[j] * w;
-          if (want_d) Dm[k] += s_d[j] * w;
-          T[k] = Tn;
-          last[k] = (uint32_t)(base + j + 1);
-        }
-        lane_done = all_done();
-        if (lane_done) break;
+      for (int k = 0; k < PX; ++k) {
+        float dx, dy;
+        const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
+        const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
+        const bool ok = (PX == 1 || ((m >> pixel_quadrant<PX>(wid, k)) & 1u)) && !done[k] && !(power > 0.0f) &&
+                        alpha >= kAlphaMin;
+        const float Tn = T[k] * (1.0f - alpha);
+        const bool stop = ok && Tn < kTMin;
+        const bool take = ok && !stop;
+        done[k] = done[k] || stop;
+        const float w = take ? alpha * T[k] : 0.0f;
+        C0[k] += b.z * w;
+        C1[k] += b.w * w;
+        C2[k] += cr.x * w;
+        if (want_d) Dm[k] += cr.y * w;
+        T[k] = take ? Tn : T[k];
+        last[k] = take ? pos1 : last[k];
       }
+      lane_done = all_done();
     }
   }
   if (!split) {

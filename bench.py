@@ -703,13 +703,21 @@ def bench_step(torch, gslic, args, dev, workload, steps, warmup, with_plain=Fals
                 m.render_backward([Bp.grads[k]], [Bp.expo[k][12:24]])
             m.adam_step(Bp.expo)
 
-        for _ in range(warmup):
-            plain()
-        restore()
-        ms_plain = timed(torch, plain, steps)
-        if m.check_overflow():
-            raise RuntimeError("instance buffer overflow in the plain path")
+        # the plain path at the batched step's long-list split and with no split (single
+        # views of uniform scenes blend faster whole); the faster one is the baseline
+        plain_by_split = {}
+        for sp in (split_config(args), (0, 256, 1.25)):
+            m.set_tile_split(*sp)
+            for _ in range(warmup):
+                plain()
+            restore()
+            plain_by_split[",".join(str(x) for x in sp)] = timed(torch, plain, steps)
+            if m.check_overflow():
+                raise RuntimeError("instance buffer overflow in the plain path")
+        m.set_tile_split(*split_config(args))
+        ms_plain = min(plain_by_split.values())
         result["plain_ms_per_step"] = ms_plain
+        result["plain_ms_per_step_by_split"] = plain_by_split
         result["batched_over_plain"] = ms_plain / ms
         result["batched_eager_over_plain"] = ms_plain / ms_eager
         result["metric"] = "mapping iters/s, 8 uneven keyframes per step (batched vs one view per launch)"
@@ -806,7 +814,8 @@ def main():
         b8 = bench_step(torch, gslic, args, dev, "batch8", args.extra_steps, args.warmup, with_plain=True)
         result["batched_over_plain"] = b8["batched_over_plain"]
         result["batch8"] = {"workload": b8["config"]["workload"], "batched_ms_per_step": b8["ms_per_step"],
-                            "plain_ms_per_step": b8["plain_ms_per_step"], "steps": b8["steps"],
+                            "plain_ms_per_step": b8["plain_ms_per_step"],
+                            "plain_ms_per_step_by_split": b8["plain_ms_per_step_by_split"], "steps": b8["steps"],
                             "batched_iters_per_s": b8["value"], "stages_ms": b8["stages_ms"]}
         log("street-drive latency")
         sargs = argparse.Namespace(**vars(args))

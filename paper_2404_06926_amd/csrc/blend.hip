@@ -50,37 +50,49 @@ namespace gs {
 constexpr int kBlendBlock = 256;
 #define NW_OF(PX) (kBlendBlock / (PX) / 64)
 
-// Minimum of q = A dx^2 + 2B dx dy + C dy^2 over [x0, x1] x [y0, y1] (offsets from the
-// mean) compared with thr: 0 inside; else the smaller of the 1-D minima, clamped to the
-// rectangle, on the edges nearest the mean (the segment from any point of the rectangle to
-// the mean, along which the convex q falls, crosses one of them inside the rectangle).
-// iA = 1/A, iC = 1/C: the hardware reciprocal, whose rounding moves a clamped minimum's
-// position by an ulp and so q only at second order, well inside the caller's margin.
-// Branch-free: both edges are evaluated and the ones the mean does not lie beyond dropped.
-__device__ __forceinline__ bool footprint_hits_rect(float A, float B, float C, float iA, float iC, float thr,
-                                                    float x0, float x1, float y0, float y1) {
-  const bool in_x = x0 <= 0.f && x1 >= 0.f, in_y = y0 <= 0.f && y1 >= 0.f;
-  const float ex = x0 > 0.f ? x0 : x1;
-  const float ey = y0 > 0.f ? y0 : y1;
-  const float dy = fminf(fmaxf(-(B * ex) * iC, y0), y1);
-  const float dx = fminf(fmaxf(-(B * ey) * iA, x0), x1);
-  const float qx = A * ex * ex + 2.f * B * ex * dy + C * dy * dy;
-  const float qy = A * dx * dx + 2.f * B * dx * ey + C * ey * ey;
-  const float inf = __builtin_huge_valf();
-  return (in_x && in_y) || fminf(in_x ? inf : qx, in_y ? inf : qy) <= thr;
-}
-
 // 4-bit mask of the tile's 8x8 quadrants (bit q: x half q & 1, y half q >> 1) that the
-// footprint {q <= thr (1 + 1e-4) + 1e-4} reaches at some pixel centre.
+// footprint {q <= thr (1 + 1e-4) + 1e-4} reaches at some pixel centre, with
+// q = A dx^2 + 2B dx dy + C dy^2 (offsets from the mean). A quadrant is reached when it
+// holds the mean, else when the smaller of the 1-D minima of q, clamped to the quadrant, on
+// its edges nearest the mean passes (the segment from any point of the quadrant to the mean,
+// along which the convex q falls, crosses one of them inside the quadrant). The two x
+// halves share their nearest x edge and its unclamped minimiser, the two y halves likewise,
+// so each quadrant adds only its clamps and two quadratics. iA = 1/A, iC = 1/C: the
+// hardware reciprocal, whose rounding moves a clamped minimum's position by an ulp and so q
+// only at second order, well inside the margin. A projected conic is positive definite
+// (A, C > 0), so the minimisers are finite and each clamp is one median of three.
 __device__ __forceinline__ uint32_t quadrant_mask(float4 r0, float4 r1, float thr, int tx, int ty) {
   const float t = thr * 1.0001f + 1e-4f;
-  const float iA = __builtin_amdgcn_rcpf(r0.z), iC = __builtin_amdgcn_rcpf(r1.x);
+  const float A = r0.z, B = r0.w, C = r1.x;
+  const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+  float xl[2], xh[2], ex[2], dyu[2], ax[2], bx[2], yl[2], yh[2], ey[2], dxu[2], cy[2], by[2];
+  bool inx[2], iny[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    xl[h] = (float)(tx * kTile + 8 * h) + 0.5f - r0.x;  // pixel-centre offsets of the half
+    xh[h] = xl[h] + 7.f;
+    inx[h] = xl[h] <= 0.f && xh[h] >= 0.f;
+    ex[h] = xl[h] > 0.f ? xl[h] : xh[h];
+    dyu[h] = -(B * ex[h]) * iC;  // minimiser of q along the edge x = ex
+    ax[h] = A * ex[h] * ex[h];   // q(ex, dy) = ax + bx dy + C dy^2
+    bx[h] = 2.f * B * ex[h];
+    yl[h] = (float)(ty * kTile + 8 * h) + 0.5f - r0.y;
+    yh[h] = yl[h] + 7.f;
+    iny[h] = yl[h] <= 0.f && yh[h] >= 0.f;
+    ey[h] = yl[h] > 0.f ? yl[h] : yh[h];
+    dxu[h] = -(B * ey[h]) * iA;  // minimiser of q along the edge y = ey
+    cy[h] = C * ey[h] * ey[h];   // q(dx, ey) = cy + by dx + A dx^2
+    by[h] = 2.f * B * ey[h];
+  }
   uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float x0 = (float)(tx * kTile + 8 * (q & 1)) + 0.5f - r0.x;
-    const float y0 = (float)(ty * kTile + 8 * (q >> 1)) + 0.5f - r0.y;
-    if (footprint_hits_rect(r0.z, r0.w, r1.x, iA, iC, t, x0, x0 + 7.f, y0, y0 + 7.f)) m |= 1u << q;
+    const int h = q & 1, v = q >> 1;
+    const float dy = __builtin_amdgcn_fmed3f(dyu[h], yl[v], yh[v]);
+    const float dx = __builtin_amdgcn_fmed3f(dxu[v], xl[h], xh[h]);
+    const float qx = fmaf(C * dy, dy, fmaf(bx[h], dy, ax[h]));
+    const float qy = fmaf(A * dx, dx, fmaf(by[v], dx, cy[v]));
+    if ((inx[h] && iny[v]) || (!inx[h] && qx <= t) || (!iny[v] && qy <= t)) m |= 1u << q;
   }
   return m;
 }

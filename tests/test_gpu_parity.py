@@ -102,6 +102,13 @@ def _check_render(name, px, split):
     params, deg, cams = case(name)
     print(f"case {name} px {px} split {split}", flush=True)
     m, frames = _run_gpu(params, deg, cams, px=px, split=split)
+    if split == SPLITS[2]:
+        # the forced split must cut some list here (the dense case has lists of hundreds)
+        r = m.debug_last_render()["ranges"].cpu().numpy().astype(np.int64)
+        n_cut = int(((r[:, 1] - r[:, 0]) > 64).sum())
+        print(f"tiles cut into chunks: {n_cut}", flush=True)
+        if name == "dense":
+            assert n_cut > 0
     views, projs, bins, rend = _oracle(name)
     for f, r in zip(frames, rend):
         ok = r["tie"] == 0

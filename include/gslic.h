@@ -204,7 +204,13 @@ gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t height, int
  * (window <= GS_MAX_VIEWS), then run `iters` steps, each = one batched gs_render over
  * the window, Eq. 9 loss per keyframe, gs_render_backward, gs_adam_step (Gaussians and
  * window exposures). image: device float[3][H][W]; xyz, rgb: device n_points x 3.
- * done_event (a hipEvent_t, may be NULL) is recorded on `stream` after the last step. */
+ * The steps run without host waits (fused steps): the instance buffers are sized from the
+ * map's previous job, scaled to this window with a quarter to spare (a map's first job
+ * plans its first render with a wait); a step whose render needs more is skipped on the
+ * device and run again after the others with planning, so a job always applies `iters`
+ * steps. The call waits once, at the job's end, for the overflow counters (it clears the
+ * map's overflow flag). done_event (a hipEvent_t, may be NULL) is recorded on `stream`
+ * after the last step. */
 gs_status gs_submit_keyframe(gs_map* map, const gs_view* view, const float* image,
                              int64_t n_points, const float* xyz, const float* rgb,
                              int32_t iters, int32_t window, float lambda, float o_init,
@@ -328,12 +334,18 @@ gs_status gs_debug_last_render(gs_map* map, void* stream, const uint32_t** tiles
 
 /* Instance-buffer policy. sync_plan = 1 (default): gs_render reads the instance count back
  * after binning and grows the buffers to fit (one host wait per render). sync_plan = 0:
- * no host wait inside gs_render (a graph-capturable sequence); instances beyond
- * `capacity` are dropped and flagged, to be checked with gs_check_overflow. */
+ * no host wait inside gs_render (a graph-capturable sequence); a render that needs more
+ * than `capacity` instances drops them all (its images hold only the background, and its
+ * gs_render_backward adds no gradient) and is flagged, to be checked with
+ * gs_check_overflow. A fused step (gs_step, gs_launch_step)
+ * whose render dropped instances is skipped: the parameters, their Adam moments, the
+ * exposures and the Adam step count are left as they were (its loss value is not
+ * meaningful). */
 gs_status gs_set_instance_policy(gs_map* map, int32_t sync_plan, int64_t capacity);
 
 /* Synchronise `stream` and report whether any render since the last check dropped
- * instances (1) or not (0); clears the flag. */
+ * instances (1) or not (0); clears the flag. After skipped fused steps the map's step
+ * count (gs_map_step_count) follows the device's again. */
 gs_status gs_check_overflow(gs_map* map, void* stream, int32_t* overflow);
 
 /* Per-stage GPU timing. With timing enabled, every stage of the calls below records a

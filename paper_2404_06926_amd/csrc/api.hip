@@ -96,6 +96,9 @@ struct gs_map {
   bool grads_dirty = false;    // gradient planes may hold non-zero values (a backward without Adam,
                                // or their pointer was handed out)
   bool step_assumed_clean = false;  // the last fused gs_step skipped reading the gradient planes
+  bool dirty_step_since_check = false;  // a fused step read gradient planes since the last overflow check
+  int64_t serve_peak = 0;   // largest instance count of the last keyframe job (gs_submit_keyframe)
+  int serve_views = 0;      // its window size
   int fwd_px = 1, bwd_px = 1;  // pixels per lane of the blend kernels (fastest measured at 1280x720)
   int32_t split_par = 4096, split_min = 128;  // long-list split (SplitArg)
   float split_balance = 1.25f;
@@ -671,6 +674,9 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     return fail(GS_ERR_STATE, "sync_plan = 0 needs an instance capacity (gs_set_instance_policy)");
   }
   GS_TRY(ensure_instances(m, m->inst_cap, vn, s));
+  // the backward of this render checks these: a render that dropped its instances has none
+  va.n_inst = m->d_ninst;
+  va.inst_cap = m->inst_cap;
   uint32_t* keys[2] = {(uint32_t*)m->keys[0].ptr, (uint32_t*)m->keys[1].ptr};
   uint32_t* vals[2] = {(uint32_t*)m->vals[0].ptr, (uint32_t*)m->vals[1].ptr};
   {
@@ -860,6 +866,8 @@ gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t H, int32_t 
   return GS_OK;
 }
 
+static gs_status read_overflow(gs_map* m, hipStream_t s, uint32_t* flag, uint32_t* skipped, uint32_t* peak);
+
 gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image, int64_t n_points, const float* xyz,
                              const float* rgb, int32_t iters, int32_t window, float lambda, float o_init,
                              void* done_event, void* stream) {
@@ -953,8 +961,67 @@ gs_status gs_submit_keyframe(gs_map* m, const gs_view* view, const float* image,
     dl[j] = q.dl;
     es[j] = q.state;
   }
-  for (int it = 0; it < iters; ++it)
-    GS_TRY(gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream));
+  // The iterations run without host waits: the instance buffers are sized from the map's
+  // previous job (its largest render, scaled to this window, with a quarter to spare; a
+  // map's first job plans its first render with a wait). A fused step whose render needs
+  // more is skipped on the device (nothing applied) and counted; the job's end reads the
+  // counters once, grows the buffers to the largest need and runs the skipped iterations
+  // again with planning, so every job applies `iters` steps.
+  if (iters > 0) {
+    const bool plan_before = m->sync_plan;
+    const int64_t vn = (int64_t)nk * m->n;
+    int it = 0;
+    auto restore = [&](gs_status st) {
+      m->sync_plan = plan_before;
+      return st;
+    };
+    if (m->serve_peak == 0 || !m->fused_step) {
+      m->sync_plan = true;
+      gs_status st = gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream);
+      if (st != GS_OK) return restore(st);
+      it = 1;
+    }
+    if (it < iters) {
+      if (!m->fused_step) {
+        // the separate update has no skip: plan every render
+        for (; it < iters; ++it) {
+          gs_status st =
+              gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream);
+          if (st != GS_OK) return restore(st);
+        }
+      } else {
+        int64_t est = m->inst_cap;
+        if (m->serve_peak > 0 && m->serve_views > 0) {
+          const int64_t scaled = m->serve_peak * nk / m->serve_views;
+          est = std::max<int64_t>(est, scaled + scaled / 4 + (1 << 16));
+        }
+        gs_status st = ensure_instances(m, est, vn, s);
+        if (st != GS_OK) return restore(st);
+        m->sync_plan = false;
+        for (; it < iters; ++it) {
+          st = gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream);
+          if (st != GS_OK) return restore(st);
+        }
+      }
+    }
+    uint32_t flag = 0, skipped = 0, peak = 0;
+    gs_status st = read_overflow(m, s, &flag, &skipped, &peak);
+    if (st != GS_OK) return restore(st);
+    if (skipped > 0) {
+      m->sync_plan = true;  // plans (and grows) each render
+      for (uint32_t k = 0; k < skipped; ++k) {
+        st = gs_step(m, nk, vv.data(), ff.data(), tg.data(), lambda, es.data(), dl.data(), m->d_loss, stream);
+        if (st != GS_OK) return restore(st);
+      }
+      uint32_t f2, s2, p2;
+      st = read_overflow(m, s, &f2, &s2, &p2);
+      if (st != GS_OK) return restore(st);
+      peak = std::max(peak, p2);
+    }
+    m->serve_peak = std::max<int64_t>(peak, 1);
+    m->serve_views = nk;
+    m->sync_plan = plan_before;
+  }
   if (done_event) GS_HIP(hipEventRecord((hipEvent_t)done_event, s));
   return GS_OK;
 }
@@ -1102,8 +1169,8 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   hipStream_t s = (hipStream_t)stream;
   const gs_map_desc& d = m->desc;
   // one loss launch over all views; in a fused step its last block also advances the Adam
-  // step counter
-  const StepPrep prep{m->d_step, m->d_bc, d.beta1, d.beta2};
+  // step counter, or counts the step as skipped when its render dropped instances
+  const StepPrep prep{m->d_step, m->d_bc, d.beta1, d.beta2, m->d_ninst, m->inst_cap, m->d_overflow + 1};
   LossArg la{};
   la.n = nv;
   la.lambda = lambda;
@@ -1130,6 +1197,7 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   ad.n_exp = nv;
   ad.lr_exp = d.lr_exposure;
   m->step_assumed_clean = ad.grads_clean != 0;
+  if (!ad.grads_clean) m->dirty_step_since_check = true;
   GS_TRY(backward_impl(m, nv, dl, nullptr, nullptr, eg, &ad, s));
   m->grads_dirty = false;  // the fused update cleared every accumulated gradient it read
   m->h_step += 1;
@@ -1203,6 +1271,7 @@ gs_status gs_launch_step(gs_step_graph* g, void* stream) {
                 "run gs_adam_step first, or capture again");
   GS_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   g->map->h_step += 1;
+  if (!g->assumes_clean) g->map->dirty_step_since_check = true;
   g->map->grads_dirty = false;
   g->map->render_gen += 1;
   return GS_OK;
@@ -1304,13 +1373,31 @@ gs_status gs_set_instance_policy(gs_map* m, int32_t sync_plan, int64_t capacity)
   return GS_OK;
 }
 
+// Reads and clears the overflow words: [0] a render dropped instances, [1] fused steps
+// skipped for it, [2] the largest instance count needed. After skipped steps the host's
+// step count follows the device's, and gradient planes a skipped step would have consumed
+// are marked as holding values again.
+static gs_status read_overflow(gs_map* m, hipStream_t s, uint32_t* flag, uint32_t* skipped, uint32_t* peak) {
+  GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_overflow, 12, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipMemcpyAsync(m->h_pinned + 4, m->d_step, 8, hipMemcpyDeviceToHost, s));
+  GS_HIP(hipStreamSynchronize(s));
+  *flag = m->h_pinned[0];
+  *skipped = m->h_pinned[1];
+  *peak = m->h_pinned[2];
+  if (*skipped) {
+    m->h_step = (int64_t)((uint64_t)m->h_pinned[4] | ((uint64_t)m->h_pinned[5] << 32));
+    if (m->dirty_step_since_check) m->grads_dirty = true;
+  }
+  m->dirty_step_since_check = false;
+  GS_HIP(fill_u32(m->d_overflow, 0u, 3, s));
+  return GS_OK;
+}
+
 gs_status gs_check_overflow(gs_map* m, void* stream, int32_t* overflow) {
   if (!m || !overflow) return fail(GS_ERR_INVALID, "NULL argument");
-  hipStream_t s = (hipStream_t)stream;
-  GS_HIP(hipMemcpyAsync(m->h_pinned, m->d_overflow, 4, hipMemcpyDeviceToHost, s));
-  GS_HIP(hipStreamSynchronize(s));
-  *overflow = m->h_pinned[0] ? 1 : 0;
-  GS_HIP(fill_u32(m->d_overflow, 0u, 1, s));
+  uint32_t flag, skipped, peak;
+  GS_TRY(read_overflow(m, (hipStream_t)stream, &flag, &skipped, &peak));
+  *overflow = flag ? 1 : 0;
   return GS_OK;
 }
 

@@ -639,7 +639,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   __shared__ float s_red[NW][12];
   __shared__ uint32_t s_wmax[NW];
   BlendItem it;
-  if (!blend_item(sp, ranges, it)) return;
+  if (render_dropped(va) || !blend_item(sp, ranges, it)) return;
   if (!DET)
     for (int k = (int)threadIdx.x; k < NT * NG; k += NT) (&s_acc[0][0])[k] = 0.0f;
   const int tile = it.tile;
@@ -919,7 +919,7 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
 // Deterministic exposure gradient: per view and entry, the tiles' partial sums in tile order.
 __global__ void k_exposure_reduce(ViewsArg va, const float* __restrict__ exp_part) {
   const int v = blockIdx.x, f = threadIdx.x;
-  if (v >= va.n || f >= 12) return;
+  if (v >= va.n || f >= 12 || render_dropped(va)) return;
   const ViewDev& V = va.v[v];
   if (!V.dl_dexp) return;
   const int T = V.tiles_x * V.tiles_y;

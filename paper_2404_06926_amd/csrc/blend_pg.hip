@@ -67,6 +67,7 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
   __shared__ float s_S[3][256];       // colour behind the current chunk (incl. background)
   __shared__ float s_G[3][256];       // dL/d(pre-exposure colour)
   __shared__ uint32_t s_nc[256];      // list position after the pixel's last contributor
+  if (render_dropped(va)) return;
   const int tile = blockIdx.x;
   const int v = view_of_tile(va, tile);
   const ViewDev& V = va.v[v];

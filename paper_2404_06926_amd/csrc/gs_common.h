@@ -49,7 +49,14 @@ struct ViewsArg {
   int32_t n;
   int32_t total_tiles;
   ViewDev v[kMaxViews];
+  // the render's instance count (device) and the instance capacity: a render that needed
+  // more dropped its instances, and its backward adds no gradient at all
+  const uint32_t* n_inst;
+  int64_t inst_cap;
 };
+__device__ __forceinline__ bool render_dropped(const ViewsArg& va) {
+  return va.n_inst && (int64_t)va.n_inst[0] > va.inst_cap;
+}
 // passed by value to kernels: stays inside the 4 KiB kernel-argument space with room for
 // the other arguments
 static_assert(sizeof(ViewsArg) <= 3584, "ViewsArg too large for a kernel argument");

@@ -58,6 +58,8 @@ hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* 
                        uint32_t* temp, uint32_t* total, hipStream_t s);
 // Instances in depth order, one lane per instance (block_start: block_start_elems(capacity)
 // words); pairs listed in big_list (big_n of them) have more than 64 candidate tiles.
+// overflow[0] |= 1 when the instances exceed the capacity; overflow[2] = max(overflow[2],
+// instance count).
 // inst_off receives each pair's first emission index for the listed pairs, and for every
 // pair with all_off (the deterministic backward reads it).
 int64_t block_start_elems(int64_t capacity);
@@ -132,10 +134,15 @@ struct LossArg {
   float lambda;
   LossView v[kMaxViews];
 };
+// The Adam step counter advance of a fused step; a step whose render needed more than
+// inst_cap instances is skipped instead and counted in *skipped.
 struct StepPrep {
   int64_t* step;
   float* bc;
   float beta1, beta2;
+  const uint32_t* n_inst;
+  int64_t inst_cap;
+  uint32_t* skipped;
 };
 int64_t loss_temp_floats(int H, int W);
 int64_t loss_temp_floats_multi(const LossArg& la);

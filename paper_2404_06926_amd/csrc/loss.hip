@@ -318,16 +318,20 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
 
 // Block v: the loss of image v from its tiles' partial sums, in a fixed order. With
 // prep.step, block 0 also advances the Adam step counter and its bias corrections (as
-// adam_prepare), saving that launch in a fused step.
+// adam_prepare), saving that launch in a fused step, or counts the step as skipped.
 __global__ void __launch_bounds__(256)
 k_loss_reduce(LossArg la, const float* __restrict__ part, int32_t nb, StepPrep prep) {
   __shared__ double s[2][256];
   const int v = blockIdx.x, tid = threadIdx.x;
   if (prep.step && v == 0 && tid == 0) {
-    const int64_t t = prep.step[0] + 1;
-    prep.step[0] = t;
-    prep.bc[0] = (float)(1.0 - pow((double)prep.beta1, (double)t));
-    prep.bc[1] = (float)(1.0 - pow((double)prep.beta2, (double)t));
+    if (prep.n_inst && (int64_t)prep.n_inst[0] > prep.inst_cap) {
+      prep.skipped[0] += 1u;  // the step's render dropped instances: the step is skipped
+    } else {
+      const int64_t t = prep.step[0] + 1;
+      prep.step[0] = t;
+      prep.bc[0] = (float)(1.0 - pow((double)prep.beta1, (double)t));
+      prep.bc[1] = (float)(1.0 - pow((double)prep.beta2, (double)t));
+    }
   }
   const int b0 = la.v[v].tile_base;
   const int b1 = v + 1 < la.n ? la.v[v + 1].tile_base : nb;
@@ -375,7 +379,7 @@ hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t 
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ssim_tile, dim3((unsigned)nb), dim3(256), 0, s, win, la, temp + kPartOffset);
   hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)la.n), dim3(256), 0, s, la, temp + kPartOffset, (int32_t)nb,
-                     prep ? *prep : StepPrep{nullptr, nullptr, 0.f, 0.f});
+                     prep ? *prep : StepPrep{nullptr, nullptr, 0.f, 0.f, nullptr, 0, nullptr});
   return hipGetLastError();
 }
 

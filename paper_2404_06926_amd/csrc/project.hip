@@ -239,6 +239,10 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float s_gsh[MULTI ? 3 * K : 1][MULTI ? 256 : 1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // a render that dropped its instances (it needed more than the buffers hold) has no
+  // gradient: nothing is added, and a fused step is skipped, leaving the map, its moments
+  // and the exposures as they are (the same decision for every thread)
+  if (render_dropped(va)) return;
   if (FUSED && blockIdx.x == 0 && (int)threadIdx.x < 12 * ad.n_exp) {
     // the views' exposures (their gradients are complete once the blend backward is done),
     // as the separate exposure update does, in place of a launch of its own

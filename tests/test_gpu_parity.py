@@ -641,6 +641,39 @@ def test_captured_step_refuses_a_grown_map():
         g.close()
 
 
+def test_fused_step_whose_render_overflows_is_skipped():
+    # No-wait planning with an instance capacity far below the views' need: the render drops
+    # its instances and the fused step is skipped on the device, leaving the parameters,
+    # their Adam moments, the exposure states and the step count as they were; the overflow
+    # is reported. With planning the same step then applies.
+    torch = torch_mod()
+    params, deg, cams = case("c3a")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        m = gpu_map(params, deg)
+        tg = [torch.tensor(scenes.smooth_image(6, c.height, c.width), device="cuda") for c in cams]
+        fr = [gslic.Frame(torch.empty(3, c.height, c.width, device="cuda"), torch.empty(c.height, c.width, device="cuda"),
+                          torch.empty(c.height, c.width, dtype=torch.int32, device="cuda")) for c in cams]
+        es = [gslic.identity_exposure_state() for _ in cams]
+        gr = [torch.empty(3, c.height, c.width, device="cuda") for c in cams]
+        lo = torch.empty(len(cams), device="cuda")
+        m.set_instance_policy(False, 1024)
+        torch.cuda.synchronize()
+        before = [m.params().clone(), *(t.clone() for t in m.adam_moments()), *(e.clone() for e in es)]
+        m.step(cams, fr, tg, es, gr, lo)
+        torch.cuda.synchronize()
+        assert m.check_overflow()
+        assert m.step_count == 0
+        for a, b in zip(before, [m.params(), *m.adam_moments(), *es]):
+            assert torch.equal(a, b)
+        m.set_instance_policy(True, 0)
+        m.step(cams, fr, tg, es, gr, lo)
+        torch.cuda.synchronize()
+        assert not m.check_overflow()
+        assert m.step_count == 1
+        assert not torch.equal(m.params(), before[0])
+
+
 def test_autograd_backward_after_a_second_render_raises():
     # The backward pairs with the map's most recent render: a render between the forward
     # and its backward is detected instead of silently using the newer render's state.

@@ -47,3 +47,32 @@ def test_alone_and_in_the_mix_give_identical_maps():
     # and again alone: the deterministic path is reproducible run to run
     again, _ = _run(mk()[:1], slots=1)
     assert torch.equal(alone[0], again[0])
+
+
+def test_keyframe_job_reruns_the_steps_whose_render_overflowed():
+    # A job's steps run without host waits, their instance buffers sized from the map's
+    # previous job. Here the second job appends 60k points (every point kept), far beyond
+    # that estimate: its renders drop their instances, the fused steps are skipped on the
+    # device and run again with planning, so every job still applies all its steps.
+    import torch
+    from paper_2404_06926_amd import gslic
+    W, H, iters = 160, 120, 3
+    base = scenes.pinhole(W, H, 100.0 * W / 128)
+    init = scenes.frustum_gaussians(2000, 1, base, seed=21)
+    m = gslic.GaussianMap(sh_degree=1, capacity=4096, expand_tau=0.0)
+    m.add_gaussians(torch.from_numpy(init).cuda())
+    img = torch.tensor(scenes.smooth_image(5, H, W), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(21)
+    for k, npts in enumerate([100, 60000]):
+        cam = scenes.pinhole(W, H, base.fx)
+        cam.t = np.array([0.02 * k, 0.0, 0.0], np.float32)
+        pts = scenes.frustum_gaussians(npts, 0, cam, seed=40 + k)[:, 0:3].astype(np.float32)
+        col = rng.random((npts, 3)).astype(np.float32)
+        print(f"job {k}: {npts} points", flush=True)
+        m.submit_keyframe(cam, img, torch.from_numpy(pts).cuda(), torch.from_numpy(col).cuda(), iters=iters,
+                          window=2)
+        torch.cuda.synchronize()
+        assert m.step_count == (k + 1) * iters
+        assert not m.check_overflow()
+    assert m.n == 2000 + 100 + 60000
+    assert torch.isfinite(m.params()[:, : m.n]).all()

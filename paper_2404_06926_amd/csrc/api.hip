@@ -293,6 +293,9 @@ void fill_viewdev(ViewDev& d, const gs_view& v) {
   d.fy = v.fy;
   d.cx = v.cx;
   d.cy = v.cy;
+  // the projection's clamp of the view-space slope (FP32, as the kernels formed it)
+  d.limx = 1.3f * ((0.5f * (float)v.width) / v.fx);
+  d.limy = 1.3f * ((0.5f * (float)v.height) / v.fy);
   for (int k = 0; k < 3; ++k) {
     double c = 0.0;
     for (int r = 0; r < 3; ++r) c -= (double)v.R_cw[3 * r + k] * (double)v.t_cw[r];

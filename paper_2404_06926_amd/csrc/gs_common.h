@@ -27,6 +27,7 @@ struct ViewDev {
   float R[9];
   float t[3];
   float fx, fy, cx, cy;
+  float limx, limy;         // 1.3 (W / 2) / fx and 1.3 (H / 2) / fy (FP32, IEEE division)
   float campos[3];          // camera centre in world coordinates (colour direction)
   float bg[3];
   int32_t W, H, tiles_x, tiles_y;
@@ -124,9 +125,21 @@ struct KeyProj {
   float a, c;            // diagonal of Sigma' (for the tile rectangle)
 };
 
+// Opacity o = sigmoid(logit) and thr = 2 ln(255 o) (for o >= 1/255; 0 otherwise), FP64
+// then rounded: the same for every view, so computed once per Gaussian.
+struct KeyOpacity {
+  float o, thr;
+};
+__device__ __forceinline__ KeyOpacity key_opacity(float logit) {
+  KeyOpacity k;
+  k.o = (float)(1.0 / (1.0 + exp(-(double)logit)));
+  k.thr = k.o < 1.0f / 255.0f ? 0.0f : (float)(2.0 * log(255.0 * (double)k.o));
+  return k;
+}
+
 // Eq. 2-3 for one view; culls depth <= near_z, det <= 0 and opacity < 1/255.
 __device__ __forceinline__ KeyProj key_project(const ViewDev& V, const KeyGeo& G, float m0, float m1,
-                                               float m2, float logit, float near_z) {
+                                               float m2, const KeyOpacity& op, float near_z) {
 #pragma clang fp contract(off)
   KeyProj P;
   P.visible = false;
@@ -136,8 +149,7 @@ __device__ __forceinline__ KeyProj key_project(const ViewDev& V, const KeyGeo& G
   const float zh = ((W[6] * m0 + W[7] * m1) + W[8] * m2) + V.t[2];
   P.zh = zh;
   if (!(zh > near_z) || !G.ok) return P;
-  const float limx = 1.3f * __fdiv_rn(0.5f * (float)V.W, V.fx);
-  const float limy = 1.3f * __fdiv_rn(0.5f * (float)V.H, V.fy);
+  const float limx = V.limx, limy = V.limy;
   float tx = __fdiv_rn(xh, zh), ty = __fdiv_rn(yh, zh);
   if (tx < -limx) tx = -limx;
   if (tx > limx) tx = limx;
@@ -172,9 +184,9 @@ __device__ __forceinline__ KeyProj key_project(const ViewDev& V, const KeyGeo& G
   P.c = c;
   P.mx = V.fx * __fdiv_rn(xh, zh) + V.cx;
   P.my = V.fy * __fdiv_rn(yh, zh) + V.cy;
-  P.o = (float)(1.0 / (1.0 + exp(-(double)logit)));
+  P.o = op.o;
   if (P.o < 1.0f / 255.0f) return P;
-  P.thr = (float)(2.0 * log(255.0 * (double)P.o));
+  P.thr = op.thr;
   P.visible = true;
   return P;
 }

@@ -35,7 +35,7 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
   const float m0 = P[i], m1 = P[cap + i], m2 = P[2 * cap + i];
   const KeyGeo G = key_geometry(P[3 * cap + i], P[4 * cap + i], P[5 * cap + i], P[6 * cap + i],
                                 P[7 * cap + i], P[8 * cap + i], P[9 * cap + i]);
-  const float logit = P[10 * cap + i];
+  const KeyOpacity op = key_opacity(P[10 * cap + i]);
   float sh[3 * K];
 #pragma unroll
   for (int f = 0; f < 3 * K; ++f) sh[f] = P[(11 + f) * cap + i];
@@ -43,7 +43,7 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
   for (int v = 0; v < va.n; ++v) {
     const ViewDev& V = va.v[v];
     const size_t vi = (size_t)v * N + i;
-    const KeyProj kp = key_project(V, G, m0, m1, m2, logit, near_z);
+    const KeyProj kp = key_project(V, G, m0, m1, m2, op, near_z);
     int r[4] = {0, 0, -1, -1};
     uint32_t cnt = 0;
     uint64_t hits = 0;  // passing tiles in row-major rectangle order (rectangles of <= 64 tiles)
@@ -401,7 +401,7 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
     const float yh = W[3] * mu0 + W[4] * mu1 + W[5] * mu2 + V.t[1];
     const float zh = W[6] * mu0 + W[7] * mu1 + W[8] * mu2 + V.t[2];
     const float iz = 1.0f / zh, iz2 = iz * iz;
-    const float limx = 1.3f * (0.5f * (float)V.W / V.fx), limy = 1.3f * (0.5f * (float)V.H / V.fy);
+    const float limx = V.limx, limy = V.limy;
     const float rx = xh * iz, ry = yh * iz;
     const bool clx = rx < -limx || rx > limx, cly = ry < -limy || ry > limy;
     const float tx = fminf(limx, fmaxf(-limx, rx)), ty = fminf(limy, fmaxf(-limy, ry));

@@ -756,7 +756,7 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
     if (m->bwd_mode == 1 && !maps)
       GS_HIP(blend_backward_per_gaussian(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr,
                                          (const uint32_t*)m->emit_g.ptr, (const uint2*)m->ranges.ptr, g2d, ig,
-                                         (float*)m->exp_part.ptr, s));
+                                         (float*)m->exp_part.ptr, m->last_sp, s));
     else
       GS_HIP(blend_backward(va, rec, N, (const uint32_t*)m->vals[m->sorted].ptr, (const uint32_t*)m->emit_g.ptr,
                             (const uint2*)m->ranges.ptr, g2d, ig, (float*)m->exp_part.ptr, m->last_sp,

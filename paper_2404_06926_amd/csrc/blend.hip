@@ -42,6 +42,7 @@
 // T_back), so the split changes results only by FP32 rounding order; a stop decision
 // within rounding of the threshold may fall one entry differently, as between any two
 // orders of evaluation.
+#include "blend_split.h"
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -246,68 +247,6 @@ __device__ __forceinline__ void build_wave_lists(uint32_t m_own, int cnt, uint8_
     if (t == 0) s_len[w2] = (int)tot;
   }
   __syncthreads();
-}
-
-// ---- split lists -------------------------------------------------------------------
-// State of one chunk of a split tile, per pixel of the tile (field-major, 256 floats):
-//   0    the chunk's own transmittance factor (product of its entries' 1 - alpha)
-//   1-3  colour the chunk adds (sum of c a T, T the transmittance in front of the entry)
-//   4    depth the chunk adds
-//   5    transmittance after the chunk (where the pixel stopped, if it stopped in it)
-//   6    bits: list position after the chunk's last contributor | kStopped | kDead
-constexpr uint32_t kStopped = 1u << 31;   // the pixel's transmittance fell below kTMin here
-constexpr uint32_t kDead = 1u << 30;      // ... before the chunk: the chunk adds nothing
-constexpr uint32_t kPosMask = kDead - 1u;
-
-__device__ __forceinline__ float* split_field(const SplitArg& sp, uint32_t slot, int f) {
-  return sp.state + ((size_t)slot * kSplitFields + f) * (kTile * kTile);
-}
-
-// Chunk length for a render with n_inst instances (par > 0).
-__device__ __forceinline__ uint32_t chunk_len(uint32_t n_inst, int32_t par, int32_t min_len) {
-  const uint32_t L = max((n_inst + (uint32_t)par - 1u) / (uint32_t)par, (uint32_t)min_len);
-  return (L + 63u) & ~63u;
-}
-
-// Chunk c of a list of n entries cut into nch near-equal chunks: [begin, end).
-__device__ __forceinline__ void chunk_range(int n, int nch, int c, int& begin, int& end) {
-  begin = (int)((int64_t)c * n / nch);
-  end = (int)((int64_t)(c + 1) * n / nch);
-}
-
-struct BlendItem {
-  int tile, c, nch, begin, end;  // chunk c of nch covers list positions [begin, end)
-  uint32_t slot0;                // first state slot of the tile, kNoSlot if not split
-};
-
-// Work of block b: blocks [0, par) take the chunks >= 1 of split tiles (the long lists
-// start first), blocks [par, par + tiles) take tile b - par, whole or its chunk 0.
-// Returns false (uniformly over the block) for a block without work.
-__device__ __forceinline__ bool blend_item(const SplitArg& sp, const uint2* __restrict__ ranges, BlendItem& it) {
-  const int b = (int)blockIdx.x;
-  int tile = b - sp.par, c = 0;
-  if (b < sp.par) {
-    if ((uint32_t)b >= min(sp.counts[0], (uint32_t)sp.par)) return false;
-    const uint2 e = sp.extra[b];
-    if (e.x == kNoSlot) return false;
-    tile = (int)e.x;
-    c = (int)e.y;
-  }
-  const uint2 rg = ranges[tile];
-  const int n = (int)(rg.y - rg.x);
-  it.tile = tile;
-  it.c = c;
-  it.slot0 = sp.par > 0 ? sp.tile_slot[tile] : kNoSlot;
-  if (it.slot0 == kNoSlot) {
-    it.nch = 1;
-    it.begin = 0;
-    it.end = n;
-  } else {
-    const int L = (int)chunk_len(*sp.n_inst, sp.par, sp.min_len);
-    it.nch = (n + L - 1) / L;
-    chunk_range(n, it.nch, c, it.begin, it.end);
-  }
-  return true;
 }
 
 // One pixel's outputs from its pre-exposure colour (blended colour without background),
@@ -928,10 +867,6 @@ __global__ void k_exposure_reduce(ViewsArg va, const float* __restrict__ exp_par
   V.dl_dexp[f] += s;
 }
 
-// blocks [0, par) for the chunks >= 1 of split tiles, then one per tile
-static dim3 item_grid(const ViewsArg& va, const SplitArg& sp) {
-  return dim3((unsigned)(va.total_tiles + (sp.par > 0 ? sp.par : 0)));
-}
 
 template <int PX>
 static void launch_fwd(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,

@@ -112,10 +112,11 @@ hipError_t blend_backward(const ViewsArg& va, const float4* rec, int32_t N, cons
                           float* exp_part, const SplitArg& sp, int px, hipStream_t s);
 
 // Per-Gaussian form of blend_backward (blend_pg.hip): colour and exposure gradients only
-// (no depth / opacity maps).
+// (no depth / opacity maps); the chunks of split tiles (sp, as in blend_backward) are
+// separate work items.
 hipError_t blend_backward_per_gaussian(const ViewsArg& va, const float4* rec, int32_t N, const uint32_t* vals,
                                        const uint32_t* emit_g, const uint2* ranges, float* g2d, float* inst_grad,
-                                       float* exp_part, hipStream_t s);
+                                       float* exp_part, const SplitArg& sp, hipStream_t s);
 // fixed-order reduction of the per-tile exposure partials of the deterministic backward
 hipError_t exposure_reduce(const ViewsArg& va, const float* exp_part, hipStream_t s);
 

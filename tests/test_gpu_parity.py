@@ -141,8 +141,15 @@ def test_per_gaussian_backward_matches_oracle_adjoint(name, det):
 
 
 def test_per_gaussian_backward_after_a_split_render():
-    # the per-Gaussian backward reads only the pixel outputs, which the split blend writes
+    # the chunks of a split tile are work items of the per-Gaussian backward too, each
+    # starting from the state the split forward left after it
     _check_backward("dense", 1, False, mode=1, split=(65536, 64, 0.0))
+
+
+@pytest.mark.parametrize("split", SPLITS[1:])
+@pytest.mark.parametrize("name,det", [("dense", False), ("dense", True), ("multi", False), ("c3a", True)])
+def test_split_per_gaussian_backward_matches_oracle_adjoint(name, det, split):
+    _check_backward(name, 1, det, mode=1, split=split)
 
 
 def _check_backward(name, px, det, mode, split=None):

@@ -800,10 +800,17 @@ def main():
 
     result = bench_step(torch, gslic, args, dev, "headline", args.steps, args.warmup, with_cpu=True)
     if not args.no_extras:
-        # The rest of BASELINE's metric and the context numbers, each a short leg of its own:
-        # the outdoor single view, the 8-view batch against one view per launch, the
-        # street-drive keyframe latency, the achievable HBM bandwidth and the oracle's
-        # config-1 step on one and on all host threads.
+        # The rest of the metric (the keyframe latency) and the context numbers, each a short
+        # leg of its own: the headline map at SH0, the outdoor single view, the 8-view batch
+        # against one view per launch, the street-drive keyframe latency, the achievable HBM
+        # bandwidth and the oracle's 10k-Gaussian step on one and on all host threads.
+        log("headline workload at SH0")
+        a0 = argparse.Namespace(**vars(args))
+        a0.sh = 0
+        h0 = bench_step(torch, gslic, a0, dev, "headline", args.extra_steps, args.warmup)
+        result["headline_sh0"] = {"workload": h0["config"]["workload"], "iters_per_s": h0["value"],
+                                  "ms_per_step": h0["ms_per_step"], "steps": h0["steps"],
+                                  "stages_ms": h0["stages_ms"]}
         log("outdoor workload")
         od = bench_step(torch, gslic, args, dev, "outdoor", args.extra_steps, args.warmup)
         result["outdoor_single_view"] = {"workload": od["config"]["workload"], "iters_per_s": od["value"],

@@ -188,7 +188,7 @@ gs_status gs_loss(gs_map* map, const float* out, const float* gt, int32_t height
  * results as gs_loss, with no map and no allocation. Its per-tile partial sums live in a
  * fixed device array of GS_LOSS_NOALLOC_SCRATCH_FLOATS floats (about 128 KiB, one copy per
  * GPU, held until the process ends), enough for images of up to 16384 output tiles of
- * 32x16 pixels (e.g. 4096 x 2048); larger images return GS_ERR_CAPACITY and enqueue
+ * 32x32 pixels (e.g. 4096 x 4096); larger images return GS_ERR_CAPACITY and enqueue
  * nothing. Arguments, layout and results are those of gs_loss. Every call on one GPU
  * shares that GPU's array: calls that overlap on one GPU (different streams, or threads
  * without ordering) race and may return wrong values; calls ordered on one stream are

@@ -3,7 +3,7 @@
 // Gaussian window (sigma 1.5, separable), C1 = 0.01^2, C2 = 0.03^2, zero padding outside
 // the image.
 //
-// One fused pass per 32x16 output tile (k_ssim_tile), channel by channel:
+// One fused pass per 32x32 output tile (k_ssim_tile, 512 threads), channel by channel:
 //   1. out and gt over the tile with a 10-pixel margin go to LDS as differences from the
 //      tile's centre pixel (a = x - cx, b = y - cy; zero padding outside the image means
 //      a = -cx there). The window sums are shift-covariant, so the local moments of a and b
@@ -22,10 +22,12 @@
 //      dL/dout = blur(d_mu) + 2 a blur(d_aa) + b blur(d_ab) + the L1 term on the tile
 //      (the L1 term from the unshifted values, so that sign(0) = 0 is exact).
 // The moments of the 5-pixel margin are recomputed by the neighbouring tiles instead of
-// going through HBM. Every block writes its sums of SSIM and |out - gt|; a second launch
-// (one block per image) adds each image's sums in a fixed order and writes its loss. (A
-// last-block ticket in the tile kernel would save that launch, but the device-scope release
-// each block would then need writes back its XCD's L2 and cost more than the launch.)
+// going through HBM; a 32x32 tile recomputes 1.7x its pixels' moments (42 x 42 for 32 x 32)
+// where a 32x16 tile recomputed 2.1x. Every block writes its sums of SSIM and |out - gt|; a
+// second launch (one block per image) adds each image's sums in a fixed order and writes its
+// loss. (A last-block ticket in the tile kernel would save that launch, but the
+// device-scope release each block would then need writes back its XCD's L2 and cost more
+// than the launch.)
 #include <cmath>
 
 #include "gs_common.h"
@@ -34,26 +36,86 @@
 namespace gs {
 
 constexpr int kR = 5;                  // window radius
-constexpr int kTW = 32, kTH = 16;      // output tile
+constexpr int kTW = 32, kTH = 32;      // output tile
 constexpr int kBW = kTW + 2 * kR;      // 42: moments / derivative maps
-constexpr int kBH = kTH + 2 * kR;      // 26
+constexpr int kBH = kTH + 2 * kR;      // 42
 constexpr int kAW = kTW + 4 * kR;      // 52: inputs
-constexpr int kAH = kTH + 4 * kR;      // 36
-constexpr int kHRun = 6;               // horizontal moment pass: outputs per lane (42 = 7 x 6)
-constexpr int kVRun = 5;               // vertical moment pass: rows per lane (26 = 5 x 5 + 1)
-constexpr int kDRun = 4;               // horizontal derivative pass: outputs per lane (32 = 8 x 4)
-constexpr int kGRun = 2;               // vertical derivative pass: rows per lane (16 = 8 x 2)
-// LDS row strides: odd, so that lanes walking down a column (consecutive rows) hit
-// different banks
-constexpr int kSA = kAW + 1;           // 53
-constexpr int kSB = kBW + 1;           // 43
-constexpr int kSD = kTW + 1;           // 33
+constexpr int kAH = kTH + 4 * kR;      // 52
+constexpr int kThreads = 512;
+// Runs of outputs per lane. Each pass keeps the SIMDs' shares of the block's work even (a
+// block's waves take the four SIMDs in turn): 8 waves for the horizontal passes and the
+// last one, 4 for the vertical moment pass (its 8-wave form, runs of 4 rows, issues more
+// instructions and measured slower). Where the run does not divide the width, the last run
+// computes a few outputs more (from padding words) that nothing reads.
+constexpr int kHRun = 5, kHRuns = 9;   // horizontal moment pass: 45 >= 42 columns
+constexpr int kVRun = 7, kVRuns = 6;   // vertical moment pass: 42 rows
+constexpr int kDRun = 3, kDRuns = 11;  // horizontal derivative pass: 33 >= 32 columns
+constexpr int kGRun = 2;               // vertical derivative pass: 32 rows = 16 x 2
+// LDS row strides in words: inputs, moments' horizontal pass, derivative maps and their
+// horizontal pass (see the lane tables below)
+constexpr int kSA = 61;
+constexpr int kSB = 61;
+constexpr int kSD = 43;
+constexpr int kSE = 43;
+constexpr int kHRows = kVRun * kVRuns + 10;  // rows of the moments' horizontal pass read
+constexpr int kDRows = kVRun * kVRuns;       // rows of the derivative maps written
 constexpr int kPartOffset = 64;        // temp: [64 ...) per-block partial sums
-// every pass's lanes fit the 256-thread block
-static_assert(kBW % kHRun == 0 && kAH * (kBW / kHRun) <= 256, "horizontal moment pass");
-static_assert(kBW * ((kBH + kVRun - 1) / kVRun) <= 256, "vertical moment pass");
-static_assert(kTW % kDRun == 0 && kBH * (kTW / kDRun) <= 256, "horizontal derivative pass");
-static_assert(kTH % kGRun == 0 && kTW * (kTH / kGRun) == 256, "vertical derivative pass");
+static_assert(kHRun * kHRuns >= kBW && kHRun * kHRuns <= kSB && kHRun * kHRuns + 10 <= kSA, "horizontal moment runs");
+static_assert(kVRun * kVRuns >= kBH && kHRows >= kAH, "vertical moment runs");
+static_assert(kDRun * kDRuns >= kTW && kDRun * kDRuns <= kSE && kDRun * kDRuns + 10 <= kSD, "horizontal derivative runs");
+static_assert(kTW * (kTH / kGRun) == kThreads && kTH % kGRun == 0, "vertical derivative pass");
+
+// Lane tables. LDS has 32 banks of 4 bytes and serves a wave's access as two halves of 32
+// lanes; a half whose lanes touch 32 distinct banks takes one pass, a half with k words in
+// one bank k passes. In the three passes below every lane reads a run of words at
+// base(lane) + j for the same j, so a half is conflict-free exactly when its lanes' bases
+// fall in distinct banks. Each pass's work items (row or column, run) are grouped by the
+// bank of their base, and lane 32 h + u takes the h-th item whose base lies in bank u; the
+// strides above make those groups small enough that the items fill 16, 8 and 16 halves (8,
+// 4 and 8 waves), and make the horizontal passes' writes conflict-free as well (the
+// vertical moment pass's writes are two-way). Entry: first index | run << 8; kNoItem for an
+// idle lane.
+constexpr uint16_t kNoItem = 0xFFFF;
+struct LaneTable {
+  uint16_t item[kThreads];
+  int used;  // lanes up to the last busy one
+};
+// items (a, b), a < na, b < nb, enumerated with a outer; base bank = (a sa + b sb) mod 32
+constexpr LaneTable pack_lanes(int na, int nb, int sa, int sb) {
+  LaneTable t{};
+  for (int i = 0; i < kThreads; ++i) t.item[i] = kNoItem;
+  int cnt[32] = {};
+  t.used = 0;
+  for (int a = 0; a < na; ++a)
+    for (int b = 0; b < nb; ++b) {
+      const int u = (a * sa + b * sb) & 31;
+      const int lane = 32 * cnt[u] + u;
+      cnt[u] += 1;
+      if (lane < kThreads) t.item[lane] = (uint16_t)(a | b << 8);
+      if (lane + 1 > t.used) t.used = lane + 1;
+    }
+  return t;
+}
+// horizontal moment pass: (input row r, run k), base r kSA + k kHRun
+constexpr LaneTable kLanesH = pack_lanes(kAH, kHRuns, kSA, kHRun);
+// vertical moment pass: (column c, run q), base (q kVRun) kSB + c
+constexpr LaneTable kLanesV = pack_lanes(kBW, kVRuns, 1, kVRun * kSB);
+// horizontal derivative pass: (row r, run k), base r kSD + k kDRun
+constexpr LaneTable kLanesD = pack_lanes(kBH, kDRuns, kSD, kDRun);
+static_assert(kLanesH.used <= kThreads && kLanesV.used <= kThreads && kLanesD.used <= kThreads, "lane tables overflow");
+struct LaneTables {
+  uint16_t h[kThreads], v[kThreads], d[kThreads];
+};
+constexpr LaneTables make_lane_tables() {
+  LaneTables t{};
+  for (int i = 0; i < kThreads; ++i) {
+    t.h[i] = kLanesH.item[i];
+    t.v[i] = kLanesV.item[i];
+    t.d[i] = kLanesD.item[i];
+  }
+  return t;
+}
+__constant__ LaneTables c_lanes = make_lane_tables();
 
 // Normalised 1-D Gaussian window (sigma 1.5), passed by value to the kernel.
 struct Win {
@@ -71,7 +133,7 @@ static Win make_window() {
   return W;
 }
 
-// 40,064 bytes: four blocks fit a CU's 160 KiB of LDS. The inputs are dead once the
+// 76,192 bytes: two blocks fit a CU's 160 KiB of LDS. The inputs are dead once the
 // horizontal moment pass has read them (the last pass takes a and b at its own pixels from
 // the values it loads for the L1 term), so the derivative maps reuse their space; the
 // moments' horizontal pass is dead once the vertical pass has read it.
@@ -81,15 +143,15 @@ struct SsimLds {
       float x[kAH][kSA];        // a = x - cx (inputs with a 10-pixel margin)
       float y[kAH][kSA];        // b = y - cy
     };
-    float d[3][kBH][kSB];       // derivative maps
+    float d[3][kDRows][kSD];    // derivative maps
   };
   union {
-    float h[4][kAH][kSB];       // horizontal pass of the four moment maps
-    float hd[3][kBH][kSD];      // horizontal pass of the three derivative maps
+    float h[4][kHRows][kSB];    // horizontal pass of the four moment maps
+    float hd[3][kBH][kSE];      // horizontal pass of the three derivative maps
   };
-  float wred[2][4];
+  float wred[2][kThreads / 64];
 };
-static_assert(sizeof(SsimLds) * 4 <= 160 * 1024, "four blocks per CU");
+static_assert(sizeof(SsimLds) == 76192 && sizeof(SsimLds) * 2 <= 160 * 1024, "two blocks per CU");
 
 __device__ __forceinline__ int loss_view_of(const LossArg& la, int b) {
   int v = 0;
@@ -97,8 +159,8 @@ __device__ __forceinline__ int loss_view_of(const LossArg& la, int b) {
   return v;
 }
 
-// four blocks per CU (as many as LDS allows): at most 128 VGPRs
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+// two blocks per CU (as many as LDS allows): at most 128 VGPRs
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   __shared__ SsimLds L;
   const int view = loss_view_of(la, blockIdx.x);
@@ -115,10 +177,12 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
   const float s_ssim = -la.lambda / n;                 // dL/dSSIM per pixel and channel
   const float l1w = (1.0f - la.lambda) / n;
+  // this lane's work items in the table-driven passes
+  const uint32_t item_h = c_lanes.h[tid], item_v = c_lanes.v[tid], item_d = c_lanes.d[tid];
   // centre pixel of the tile (inside the image)
   const int64_t cidx = (int64_t)min(by + kTH / 2, H - 1) * W + min(bx + kTW / 2, W - 1);
   float ssum = 0.f, l1 = 0.f;
-  constexpr int kLoadPer = (kAH * kAW + 255) / 256;
+  constexpr int kLoadPer = (kAH * kAW + kThreads - 1) / kThreads;
   float pa[kLoadPer], pb[kLoadPer];
   float ncx, ncy;
   // pixel index of each of the lane's input slots (-1: outside the image, zero padding).
@@ -128,7 +192,7 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   int off[kLoadPer];
 #pragma unroll
   for (int j = 0; j < kLoadPer; ++j) {
-    const int t = tid + 256 * j;
+    const int t = tid + kThreads * j;
     const int r = t / kAW, c = t % kAW;
     const int gy = by - 2 * kR + r, gx = bx - 2 * kR + c;
     off[j] = (t < kAH * kAW && gx >= 0 && gx < W && gy >= 0 && gy < H) ? gy * W + gx : -1;
@@ -151,7 +215,7 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
     // are loaded into registers while this one is processed
 #pragma unroll
     for (int j = 0; j < kLoadPer; ++j) {
-      const int t = tid + 256 * j;
+      const int t = tid + kThreads * j;
       if (t < kAH * kAW) {
         L.x[t / kAW][t % kAW] = pa[j] - cx;
         L.y[t / kAW][t % kAW] = pb[j] - cy;
@@ -160,10 +224,9 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
     if (ch < 2) fetch(ch + 1);
     __syncthreads();
     // 2a. horizontal window pass of the four moments: rows of the input block, columns of
-    // the moment block; lane = (run of kHRun columns, row), consecutive lanes on
-    // consecutive rows
-    if (tid < kAH * (kBW / kHRun)) {
-      const int r = tid % kAH, c0 = (tid / kAH) * kHRun;
+    // the moment block; a lane takes kHRun outputs of one row
+    if (item_h != kNoItem) {
+      const int r = item_h & 0xFF, c0 = (item_h >> 8) * kHRun;
       float xv[kHRun + 10], yv[kHRun + 10], ss[kHRun + 10], xy[kHRun + 10];
 #pragma unroll
       for (int j = 0; j < kHRun + 10; ++j) {
@@ -190,11 +253,9 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
       }
     }
     __syncthreads();
-    // 2b. vertical pass and 3. the derivative maps; lane = (column, run of kVRun rows)
-    constexpr int kVRuns = (kBH + kVRun - 1) / kVRun;
-    if (tid < kBW * kVRuns) {
-      const int c = tid % kBW, r0 = (tid / kBW) * kVRun;
-      const int nr = min(kVRun, kBH - r0);
+    // 2b. vertical pass and 3. the derivative maps; a lane takes kVRun rows of one column
+    if (item_v != kNoItem) {
+      const int c = item_v & 0xFF, r0 = (item_v >> 8) * kVRun;
       float acc[4][kVRun];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -202,7 +263,6 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
         for (int o = 0; o < kVRun; ++o) acc[k][o] = 0.f;
 #pragma unroll
       for (int i = 0; i < kVRun + 10; ++i) {
-        if (r0 + i >= kAH) break;
         float hv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) hv[k] = L.h[k][r0 + i][c];
@@ -217,7 +277,6 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
       }
 #pragma unroll
       for (int o = 0; o < kVRun; ++o) {
-        if (o >= nr) break;
         const int rb = r0 + o;
         const int gy = by - kR + rb, gx = bx - kR + c;
         float dmu = 0.f, dxx = 0.f, dxy = 0.f;
@@ -232,8 +291,9 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
           // the variance and covariance through -E[a]^2 and -E[a] E[b]
           const float dnum = 2.f * my * A2 - 2.f * eb * A1;
           const float dden = 2.f * mx * B2 - 2.f * ea * B1;
-          // one division: with q = num / den (the SSIM value), d(q)/d. = (dnum - q dden) / den
-          const float inv = 1.0f / den, q = num * inv, si = s_ssim * inv;
+          // one reciprocal (den >= C1 C2 - rounding, far from the denormal range): with
+          // q = num / den (the SSIM value), d(q)/d. = (dnum - q dden) / den
+          const float inv = __builtin_amdgcn_rcpf(den), q = num * inv, si = s_ssim * inv;
           dmu = si * (dnum - q * dden);
           dxx = -si * q * B1;
           dxy = 2.f * si * A1;
@@ -246,10 +306,10 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
       }
     }
     __syncthreads();
-    // 4a. horizontal window pass of the derivative maps; lane = (run of kDRun columns,
-    // row), consecutive lanes on consecutive rows
-    if (tid < kBH * (kTW / kDRun)) {
-      const int r = tid % kBH, c0 = (tid / kBH) * kDRun;
+    // 4a. horizontal window pass of the derivative maps; a lane takes kDRun outputs of one
+    // row
+    if (item_d != kNoItem) {
+      const int r = item_d & 0xFF, c0 = (item_d >> 8) * kDRun;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         float dv[kDRun + 10];
@@ -265,7 +325,8 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
       }
     }
     __syncthreads();
-    // 4b. vertical pass and dL/dout on the tile; lane = (column, run of kGRun rows)
+    // 4b. vertical pass and dL/dout on the tile; lane = (column, run of kGRun rows), a half
+    // wave on 32 consecutive columns of one run
     {
       const int c = tid % kTW, r0 = (tid / kTW) * kGRun;
       float g[3][kGRun];
@@ -311,8 +372,14 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   __syncthreads();
   if (tid == 0) {
     const int64_t b = blockIdx.x;
-    part[2 * b] = L.wred[0][0] + L.wred[0][1] + L.wred[0][2] + L.wred[0][3];
-    part[2 * b + 1] = L.wred[1][0] + L.wred[1][1] + L.wred[1][2] + L.wred[1][3];
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      s0 += L.wred[0][w];
+      s1 += L.wred[1][w];
+    }
+    part[2 * b] = s0;
+    part[2 * b + 1] = s1;
   }
 }
 
@@ -377,7 +444,7 @@ hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t 
     nb += loss_tiles(la.v[v].H, la.v[v].W);
   }
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ssim_tile, dim3((unsigned)nb), dim3(256), 0, s, win, la, temp + kPartOffset);
+  hipLaunchKernelGGL(k_ssim_tile, dim3((unsigned)nb), dim3(kThreads), 0, s, win, la, temp + kPartOffset);
   hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)la.n), dim3(256), 0, s, la, temp + kPartOffset, (int32_t)nb,
                      prep ? *prep : StepPrep{nullptr, nullptr, 0.f, 0.f, nullptr, 0, nullptr});
   return hipGetLastError();

@@ -60,7 +60,7 @@ def test_defaults_and_validation_without_gpu(L):
     # refused on the host before any device work: an image with more tiles than the fixed
     # scratch holds, and a lambda outside [0, 1] (the pointers are never dereferenced)
     fake = ctypes.c_void_p(256)
-    assert L.gs_loss_noalloc(fake, fake, 4096, 4096, 0.2, fake, fake, None) == gslic.GS_ERR_CAPACITY
+    assert L.gs_loss_noalloc(fake, fake, 4096, 8192, 0.2, fake, fake, None) == gslic.GS_ERR_CAPACITY
     assert L.gs_loss_noalloc(fake, fake, 4, 4, 1.5, fake, fake, None) == gslic.GS_ERR_INVALID
     assert L.gs_set_tile_split(None, 4096, 128, 2.0) == gslic.GS_ERR_INVALID
     assert L.gs_map_set_step_count(None, 0, None) == gslic.GS_ERR_INVALID

@@ -258,7 +258,7 @@ def test_backward_with_map_gradients_matches_oracle(name, px, det, split):
 def test_loss_matches_oracle():
     torch = torch_mod()
     rng = np.random.default_rng(3)
-    # sizes below one 32x16 tile, ragged, several tiles, and the full 1280x720 view
+    # sizes below one 32x32 tile, ragged, several tiles, and the full 1280x720 view
     for (H, W) in [(5, 7), (48, 64), (75, 100), (192, 256), (720, 1280)]:
         gt = scenes.smooth_image(5, H, W)
         out = np.clip(gt + rng.normal(0, 0.05, gt.shape), 0, 1).astype(np.float32)

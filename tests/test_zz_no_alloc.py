@@ -40,8 +40,8 @@ def test_loss_noalloc_refuses_images_beyond_its_scratch():
     out = torch.zeros(3, 1, 1, device="cuda")
     lo = torch.zeros(1, device="cuda")
     L = gslic.lib()
-    # 4096 x 4096 needs 32768 tiles of 32x16: twice the fixed array
-    code = L.gs_loss_noalloc(gslic._ptr(out), gslic._ptr(out), 4096, 4096, 0.2, gslic._ptr(lo), gslic._ptr(out),
+    # 8192 x 4096 needs 32768 tiles of 32x32: twice the fixed array
+    code = L.gs_loss_noalloc(gslic._ptr(out), gslic._ptr(out), 4096, 8192, 0.2, gslic._ptr(lo), gslic._ptr(out),
                              gslic._stream())
     assert code == gslic.GS_ERR_CAPACITY
     assert b"too large" in L.gs_last_error()

@@ -77,6 +77,7 @@ struct gs_map {
   int64_t* d_step = nullptr;   // Adam step t
   float* d_bc = nullptr;       // bias corrections
   uint32_t* d_ninst = nullptr; // instance count of the last render
+  bool big_n_dirty = false;     // the large-rectangle count (d_ninst[8]) may be nonzero
   uint32_t* d_overflow = nullptr;
   float* d_loss = nullptr;     // loss values of keyframe jobs (64 floats)
   uint32_t* h_pinned = nullptr;
@@ -647,7 +648,10 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint32_t* big_n = m->d_ninst + 8;  // count of large-rectangle pairs (word 8 of the counter block)
   {
     StageTimer t(m, s, GS_STAGE_PROJECT);
-    GS_HIP(fill_u32(big_n, 0u, 1, s));
+    // the tile ranges of every completed render clear the large-rectangle count for the
+    // next one; a render that stopped before them leaves it to be cleared here
+    if (m->big_n_dirty) GS_HIP(fill_u32(big_n, 0u, 1, s));
+    m->big_n_dirty = true;
     // on the side: the pair count the depth sort reads, and the tile ranges (with the split
     // counters after them) zeroed for this render
     const ProjSide side{m->d_nvn, (uint32_t)vn, (uint32_t*)m->ranges.ptr, 2 * tiles + 2};
@@ -660,10 +664,15 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     GS_HIP(radix_sort_u32(dkey, dval, m->d_nvn, vn, 32, (uint32_t*)m->sort_tmp.ptr, &dwhich, s, true));
   }
   const uint32_t* order = dval[dwhich];
+  // the instance buffers of the current capacity exist before the scan of the counts, which
+  // marks the emission blocks' first pairs for that capacity
+  if (m->inst_cap > 0) GS_TRY(ensure_instances(m, m->inst_cap, vn, s));
+  const int64_t marked_cap = m->inst_cap;
   {
     StageTimer t(m, s, GS_STAGE_SCAN);
     if (vn > 0)
-      GS_HIP(scan_counts(counts, order, offsets, vn, (uint32_t*)m->scan_tmp.ptr, m->d_ninst, s));
+      GS_HIP(scan_counts(counts, order, offsets, vn, (uint32_t*)m->scan_tmp.ptr, m->d_ninst,
+                         (uint32_t*)m->block_start.ptr, marked_cap, s));
     else
       GS_HIP(fill_u32(m->d_ninst, 0u, 1, s));
   }
@@ -686,7 +695,8 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     StageTimer t(m, s, GS_STAGE_DUPLICATE);
     GS_HIP(duplicate_keys(rec, counts, order, offsets, m->d_ninst, (const uint32_t*)m->big_list.ptr, big_n, N, va,
                           keys[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr, m->deterministic,
-                          (uint32_t*)m->block_start.ptr, m->inst_cap, m->d_overflow, s));
+                          (uint32_t*)m->block_start.ptr, marked_cap > 0 && marked_cap == m->inst_cap, m->inst_cap,
+                          m->d_overflow, s));
   }
   int which = 0;
   {
@@ -698,7 +708,8 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint2* ranges = (uint2*)m->ranges.ptr;
   {
     StageTimer t(m, s, GS_STAGE_RANGES);
-    GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, s));
+    GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, big_n, s));
+    m->big_n_dirty = false;
     m->last_sp = split_arg(m, tiles);
     GS_HIP(split_items(ranges, (int32_t)tiles, m->last_sp, s));
   }

@@ -440,9 +440,12 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   const uint2 rg = ranges[tile];
   const float4* vrec = rec + (size_t)v * N * 4;
 
+  // T carries the pixel's state in its sign: a pixel that is done (outside the image,
+  // stopped in an earlier chunk or at an entry of this one) keeps -T, so one comparison
+  // gives both its transmittance and whether it still blends
   float pxc[PX], pyc[PX], T[PX], C0[PX], C1[PX], C2[PX], Dm[PX];
   uint32_t last[PX];
-  bool done[PX], inside[PX], dead[PX];
+  bool inside[PX], dead[PX];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     int lx, ly;
@@ -451,27 +454,26 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     pxc[k] = (float)px + 0.5f;
     pyc[k] = (float)py + 0.5f;
     inside[k] = px < V.W && py < V.H;
-    done[k] = !inside[k];
     dead[k] = false;
     T[k] = 1.0f;
     if (split && it.c > 0 && inside[k]) {
       // transmittance in front of the chunk: the earlier chunks' factors
       const int q = ly * kTile + lx;
       for (int c = 0; c < it.c; ++c) T[k] *= split_field(sp, it.slot0 + c, 0)[q];
-      if (T[k] < kTMin) done[k] = dead[k] = true;  // stopped in an earlier chunk
+      dead[k] = T[k] < kTMin;  // stopped in an earlier chunk
     }
+    if (!inside[k] || dead[k]) T[k] = -T[k];
     C0[k] = C1[k] = C2[k] = Dm[k] = 0.0f;
     last[k] = 0;
   }
   auto all_done = [&]() {
     bool d = true;
 #pragma unroll
-    for (int k = 0; k < PX; ++k) d = d && done[k];
+    for (int k = 0; k < PX; ++k) d = d && T[k] < 0.0f;
     return d;
   };
-  bool lane_done = all_done();
   for (int base = it.begin; base < it.end; base += NT) {
-    if (__syncthreads_count(lane_done) == NT) break;
+    if (__syncthreads_count(all_done()) == NT) break;
     const int kk = base + (int)threadIdx.x;
     uint32_t qm = 0;
     if (kk < it.end) {
@@ -491,7 +493,7 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     // keeps its T and last contributor by selection: no per-pixel branches
     const int len = __builtin_amdgcn_readfirstlane(s_len[wid]);
     for (int jj = 0; jj < len; ++jj) {
-      if (__all(lane_done)) break;
+      if (__all(all_done())) break;
       const int j = __builtin_amdgcn_readfirstlane((int)s_list[wid][jj]);
       const float4 a = s_r[j][0];
       const float4 b = s_r[j][1];
@@ -504,21 +506,20 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         float dx, dy;
         const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
         const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
-        const bool ok = (PX == 1 || ((m >> pixel_quadrant<PX>(wid, k)) & 1u)) && !done[k] && !(power > 0.0f) &&
-                        alpha >= kAlphaMin;
+        const bool ok = (PX == 1 || ((m >> pixel_quadrant<PX>(wid, k)) & 1u)) && !(T[k] < 0.0f) &&
+                        !(power > 0.0f) && alpha >= kAlphaMin;
         const float Tn = T[k] * (1.0f - alpha);
-        const bool stop = ok && Tn < kTMin;
-        const bool take = ok && !stop;
-        done[k] = done[k] || stop;
+        const bool above = !(Tn < kTMin);
+        const bool take = ok && above;
+        const bool stop = ok && !above;
         const float w = take ? alpha * T[k] : 0.0f;
         C0[k] += b.z * w;
         C1[k] += b.w * w;
         C2[k] += cr.x * w;
-        if (want_d) Dm[k] += cr.y * w;
-        T[k] = take ? Tn : T[k];
+        Dm[k] += cr.y * w;  // (kept only where the depth is wanted: one FMA, no select)
+        T[k] = take ? Tn : (stop ? -T[k] : T[k]);
         last[k] = take ? pos1 : last[k];
       }
-      lane_done = all_done();
     }
   }
   if (!split) {
@@ -526,7 +527,7 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     for (int k = 0; k < PX; ++k) {
       if (!inside[k]) continue;
       const int64_t p = (int64_t)(int)pyc[k] * V.W + (int)pxc[k];
-      write_pixel<DEPTH>(V, p, C0[k], C1[k], C2[k], T[k], last[k], Dm[k]);
+      write_pixel<DEPTH>(V, p, C0[k], C1[k], C2[k], fabsf(T[k]), last[k], Dm[k]);
     }
     return;
   }
@@ -535,7 +536,9 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     int lx, ly;
     lane_pixel<PX>(wid, lane, k, lx, ly);
     const int q = ly * kTile + lx;
-    const uint32_t bits = last[k] | (dead[k] ? kDead : (inside[k] && done[k] ? kStopped : 0u));
+    const bool done = T[k] < 0.0f;
+    T[k] = fabsf(T[k]);
+    const uint32_t bits = last[k] | (dead[k] ? kDead : (inside[k] && done ? kStopped : 0u));
     split_field(sp, slot, 1)[q] = C0[k];
     split_field(sp, slot, 2)[q] = C1[k];
     split_field(sp, slot, 3)[q] = C2[k];
@@ -733,9 +736,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
                         power <= 0.0f && alpha >= kAlphaMin;
         any = any || on;
         const float al = on ? alpha : 0.0f;
-        const float oma = 1.0f - al;
-        // transmittance in front of this Gaussian
-        T[k] = on ? T[k] * __builtin_amdgcn_rcpf(oma) : T[k];
+        // transmittance in front of this Gaussian (al = 0 leaves it as it is: the
+        // reciprocal of 1 is exactly 1)
+        T[k] = T[k] * __builtin_amdgcn_rcpf(1.0f - al);
         const float w = al * T[k];
         add(k, 6, w * G0[k]);
         add(k, 7, w * G1[k]);
@@ -744,21 +747,23 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         // step of the colour behind to the one in front of this Gaussian,
         // B <- alpha c + (1 - alpha) B = B + alpha (c - B)
         const float d0 = b.z - B0[k], d1 = b.w - B1[k], d2 = c2 - B2[k];
-        float dalpha = T[k] * (d0 * G0[k] + d1 * G1[k] + d2 * G2[k]);
+        // dL/dalpha = T (c - B) . G (+ the maps' terms)
+        float dot = d0 * G0[k] + d1 * G1[k] + d2 * G2[k];
         B0[k] = fmaf(al, d0, B0[k]);
         B1[k] = fmaf(al, d1, B1[k]);
         B2[k] = fmaf(al, d2, B2[k]);
         if (MAPS) {
           const float dd = dep - BD[k], dO = 1.0f - BO[k];
-          dalpha += T[k] * (dd * gD[k] + dO * gO[k]);
+          dot += dd * gD[k] + dO * gO[k];
           BD[k] = fmaf(al, dd, BD[k]);
           BO[k] = fmaf(al, dO, BO[k]);
           add(k, 9, w * gD[k]);
         }
-        // dL/dpower = dL/dalpha * alpha (no gradient through the clamp at kAlphaMax); its
-        // moments over the pixels, which the projection backward turns into the 2D mean,
-        // conic and opacity gradients
-        const float dpow = (on && araw <= kAlphaMax) ? dalpha * al : 0.0f;
+        // dL/dpower = dL/dalpha * alpha = (alpha T) dot (no gradient through the clamp at
+        // kAlphaMax; selected to zero where the pixel does not take the entry, whose colour
+        // behind may not be finite there); its moments over the pixels, which the projection
+        // backward turns into the 2D mean, conic and opacity gradients
+        const float dpow = (on && araw <= kAlphaMax) ? w * dot : 0.0f;
         const float px_ = dpow * dx, py_ = dpow * dy;
         add(k, 0, px_);
         add(k, 1, py_);

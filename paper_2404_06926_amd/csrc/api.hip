@@ -729,18 +729,20 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
 
 static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
                                const float* const* dL_dopacity, float* const* dL_dexposure, const AdamArg* fused,
-                               hipStream_t s);
+                               const LossFinish& lf, hipStream_t s);
+static const LossFinish kNoLossFinish{nullptr, nullptr, 0.f, 0};
 
 gs_status gs_render_backward(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
                              const float* const* dL_dopacity, float* const* dL_dexposure, void* stream) {
   g_err.clear();
   if (m) m->grads_dirty = true;
-  return backward_impl(m, nv, dL_drgb, dL_ddepth, dL_dopacity, dL_dexposure, nullptr, (hipStream_t)stream);
+  return backward_impl(m, nv, dL_drgb, dL_ddepth, dL_dopacity, dL_dexposure, nullptr, kNoLossFinish,
+                       (hipStream_t)stream);
 }
 
 static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drgb, const float* const* dL_ddepth,
                                const float* const* dL_dopacity, float* const* dL_dexposure, const AdamArg* fused,
-                               hipStream_t stream) {
+                               const LossFinish& lf, hipStream_t stream) {
   if (!m || !dL_drgb) return fail(GS_ERR_INVALID, "map and dL_drgb must not be NULL");
   if (!m->have_render) return fail(GS_ERR_STATE, "render_backward needs a preceding render of the same map");
   if (nv != m->last_va.n) return fail(GS_ERR_STATE, "n_views differs from the preceding render");
@@ -778,7 +780,7 @@ static gs_status backward_impl(gs_map* m, int32_t nv, const float* const* dL_drg
     GS_HIP(project_backward(m->deg, params_of(m), grads_of(m), m->cap, N, va, m->desc.near_z,
                             (const uint32_t*)m->counts.ptr, (float4*)g2d,
                             m->last_det ? (const float*)m->inst_grad.ptr : nullptr,
-                            (const uint32_t*)m->inst_off.ptr, m->vis, fused, s));
+                            (const uint32_t*)m->inst_off.ptr, m->vis, fused, lf, s));
   }
   return GS_OK;
 }
@@ -815,11 +817,12 @@ static gs_status check_loss_view(const float* out, const float* gt, int32_t H, i
 
 // One loss launch over la.n images (their sizes and pointers already checked), the
 // partial sums in the map's workspace.
-static gs_status loss_impl(gs_map* m, const LossArg& la, const StepPrep* prep, hipStream_t s) {
+// defer_finish: the losses are left to a later launch (LossFinish on loss_tmp).
+static gs_status loss_impl(gs_map* m, const LossArg& la, const StepPrep* prep, bool defer_finish, hipStream_t s) {
   if (!(la.lambda >= 0.f && la.lambda <= 1.f)) return fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
   GS_TRY(ensure(m, m->loss_tmp, (size_t)loss_temp_floats_multi(la) * 4, s));
   StageTimer t(m, s, GS_STAGE_LOSS);
-  GS_HIP(ssim_loss(la, (float*)m->loss_tmp.ptr, prep, s));
+  GS_HIP(ssim_loss(la, (float*)m->loss_tmp.ptr, prep, defer_finish, s));
   return GS_OK;
 }
 
@@ -837,7 +840,7 @@ gs_status gs_loss(gs_map* m, const float* out, const float* gt, int32_t H, int32
   g_err.clear();
   if (!m) return fail(GS_ERR_INVALID, "NULL argument");
   GS_TRY(check_loss_view(out, gt, H, W, loss_dev, dL_dout));
-  return loss_impl(m, one_loss_view(out, gt, H, W, lambda, loss_dev, dL_dout), nullptr, (hipStream_t)stream);
+  return loss_impl(m, one_loss_view(out, gt, H, W, lambda, loss_dev, dL_dout), nullptr, false, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------- loss without allocation
@@ -876,7 +879,7 @@ gs_status gs_loss_noalloc(const float* out, const float* gt, int32_t H, int32_t 
     part = g_scratch_ptr[dev];
   }
   // every partial sum the reduction reads is written by the tile kernel first: nothing to clear
-  GS_HIP(ssim_loss(one_loss_view(out, gt, H, W, lambda, loss_dev, dL_dout), part, nullptr, (hipStream_t)stream));
+  GS_HIP(ssim_loss(one_loss_view(out, gt, H, W, lambda, loss_dev, dL_dout), part, nullptr, false, (hipStream_t)stream));
   return GS_OK;
 }
 
@@ -1182,15 +1185,16 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   GS_TRY(gs_render(m, nv, vv, frames, stream));
   hipStream_t s = (hipStream_t)stream;
   const gs_map_desc& d = m->desc;
-  // one loss launch over all views; in a fused step its last block also advances the Adam
-  // step counter, or counts the step as skipped when its render dropped instances
+  // one loss launch over all views; in a fused step its first block also advances the Adam
+  // step counter (or counts the step as skipped when its render dropped instances), and the
+  // losses are finished by the projection backward's first block
   const StepPrep prep{m->d_step, m->d_bc, d.beta1, d.beta2, m->d_ninst, m->inst_cap, m->d_overflow + 1};
   LossArg la{};
   la.n = nv;
   la.lambda = lambda;
   for (int v = 0; v < nv; ++v)
     la.v[v] = LossView{frames[v].rgb, targets[v], dl_drgb[v], loss_dev + v, vv[v].height, vv[v].width, 0, 0};
-  GS_TRY(loss_impl(m, la, m->fused_step ? &prep : nullptr, s));
+  GS_TRY(loss_impl(m, la, m->fused_step ? &prep : nullptr, m->fused_step, s));
   if (!m->fused_step) {
     GS_TRY(gs_render_backward(m, nv, dl, nullptr, nullptr, eg, stream));
     GS_TRY(gs_adam_step(m, nv, exposure_states, stream));
@@ -1212,7 +1216,8 @@ gs_status gs_step(gs_map* m, int32_t nv, const gs_view* views, const gs_frame* f
   ad.lr_exp = d.lr_exposure;
   m->step_assumed_clean = ad.grads_clean != 0;
   if (!ad.grads_clean) m->dirty_step_since_check = true;
-  GS_TRY(backward_impl(m, nv, dl, nullptr, nullptr, eg, &ad, s));
+  const LossFinish lf{(const float*)m->loss_tmp.ptr + loss_part_offset(), loss_dev, lambda, 0};
+  GS_TRY(backward_impl(m, nv, dl, nullptr, nullptr, eg, &ad, lf, s));
   m->grads_dirty = false;  // the fused update cleared every accumulated gradient it read
   m->h_step += 1;
   return GS_OK;

@@ -62,6 +62,46 @@ __device__ __forceinline__ bool render_dropped(const ViewsArg& va) {
 // the other arguments
 static_assert(sizeof(ViewsArg) <= 3584, "ViewsArg too large for a kernel argument");
 
+// Eq. 9 loss of an image from the loss kernel's per-tile partial sums (SSIM and |out - gt|
+// of each 32 x 32 output tile, two floats per tile): the sums in a fixed order (thread t of
+// a 256-thread block adds tiles b0 + t, b0 + t + 256, ... in FP64, then a tree in LDS), so
+// every launch that finishes a loss gives the same value.
+constexpr int kLossTile = 32;
+__device__ __forceinline__ int loss_tiles_of(int H, int W) {
+  return ((W + kLossTile - 1) / kLossTile) * ((H + kLossTile - 1) / kLossTile);
+}
+__device__ inline float loss_from_partials(const float* __restrict__ part, int b0, int b1, int H, int W,
+                                           float lambda, double (&s)[2][256]) {
+  const int tid = threadIdx.x;
+  double a = 0.0, c = 0.0;
+  for (int k = b0 + tid; k < b1; k += 256) {
+    a += part[2 * k];
+    c += part[2 * k + 1];
+  }
+  s[0][tid] = a;
+  s[1][tid] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      s[0][tid] += s[0][tid + o];
+      s[1][tid] += s[1][tid + o];
+    }
+    __syncthreads();
+  }
+  const double nn = 3.0 * (double)H * (double)W;
+  const float L = (float)((1.0 - lambda) * s[1][0] / nn + lambda * (1.0 - s[0][0] / nn));
+  __syncthreads();  // s is reused by the next call
+  return L;
+}
+// The losses of a fused step's views, left to the projection backward's first block (one
+// launch fewer): part == nullptr for none; loss[v] for view v of the step's ViewsArg.
+struct LossFinish {
+  const float* part;
+  float* loss;
+  float lambda;
+  int32_t pad;
+};
+
 // Projection record layout (floats), one per (view, Gaussian), view-major:
 //   [0] mean2d x  [1] mean2d y  [2] conic A  [3] conic B
 //   [4] conic C   [5] opacity   [6] red      [7] green

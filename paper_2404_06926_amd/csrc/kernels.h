@@ -47,9 +47,10 @@ hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, cons
 // With inst_grad != nullptr the 2D gradients are the sums, in emission order, of the
 // instance records [inst_off[vi], inst_off[vi] + counts[vi]); otherwise they come from g2d.
 // With adam != nullptr the Adam update of each row is applied in the same kernel (one step).
+// lf.part (fused steps only): the first block also writes the views' losses.
 hipError_t project_backward(int deg, float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                             const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
-                            uint8_t* vis, const AdamArg* adam, hipStream_t s);
+                            uint8_t* vis, const AdamArg* adam, const LossFinish& lf, hipStream_t s);
 
 // binning (binning.hip)
 int64_t scan_temp_elems(int64_t n);
@@ -141,8 +142,8 @@ struct LossArg {
   float lambda;
   LossView v[kMaxViews];
 };
-// The Adam step counter advance of a fused step; a step whose render needed more than
-// inst_cap instances is skipped instead and counted in *skipped.
+// The Adam step counter advance of a fused step (by the loss kernel); a step whose render
+// needed more than inst_cap instances is skipped instead and counted in *skipped.
 struct StepPrep {
   int64_t* step;
   float* bc;
@@ -153,7 +154,12 @@ struct StepPrep {
 };
 int64_t loss_temp_floats(int H, int W);
 int64_t loss_temp_floats_multi(const LossArg& la);
-hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t s);
+// defer_finish: the tile kernel only; the losses are left to the projection backward
+// (LossFinish with part = temp + loss_part_offset()), or to loss_finish_launch.
+hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, bool defer_finish, hipStream_t s);
+int64_t loss_part_offset();
+// the losses of va's views from the partial sums of a deferred loss launch
+hipError_t loss_finish_launch(const ViewsArg& va, const LossFinish& lf, hipStream_t s);
 
 // optimiser and map maintenance (adam.hip)
 hipError_t adam_step(float* buf, int64_t cap, int32_t F, int32_t N, const uint8_t* vis, const LrArg& lr,

@@ -36,7 +36,7 @@
 namespace gs {
 
 constexpr int kR = 5;                  // window radius
-constexpr int kTW = 32, kTH = 32;      // output tile
+constexpr int kTW = kLossTile, kTH = kLossTile;  // output tile (32 x 32)
 constexpr int kBW = kTW + 2 * kR;      // 42: moments / derivative maps
 constexpr int kBH = kTH + 2 * kR;      // 42
 constexpr int kAW = kTW + 4 * kR;      // 52: inputs
@@ -159,10 +159,22 @@ __device__ __forceinline__ int loss_view_of(const LossArg& la, int b) {
   return v;
 }
 
-// two blocks per CU (as many as LDS allows): at most 128 VGPRs
+// two blocks per CU (as many as LDS allows): at most 128 VGPRs. With prep.step, block 0
+// also advances the Adam step counter and its bias corrections (as adam_prepare), saving
+// that launch in a fused step, or counts the step as skipped.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
+k_ssim_tile(Win win, LossArg la, float* __restrict__ part, StepPrep prep) {
   __shared__ SsimLds L;
+  if (prep.step && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (prep.n_inst && (int64_t)prep.n_inst[0] > prep.inst_cap) {
+      prep.skipped[0] += 1u;  // the step's render dropped instances: the step is skipped
+    } else {
+      const int64_t t = prep.step[0] + 1;
+      prep.step[0] = t;
+      prep.bc[0] = (float)(1.0 - pow((double)prep.beta1, (double)t));
+      prep.bc[1] = (float)(1.0 - pow((double)prep.beta2, (double)t));
+    }
+  }
   const int view = loss_view_of(la, blockIdx.x);
   const LossView& V = la.v[view];
   const float* __restrict__ x = V.x;
@@ -383,49 +395,39 @@ k_ssim_tile(Win win, LossArg la, float* __restrict__ part) {
   }
 }
 
-// Block v: the loss of image v from its tiles' partial sums, in a fixed order. With
-// prep.step, block 0 also advances the Adam step counter and its bias corrections (as
-// adam_prepare), saving that launch in a fused step, or counts the step as skipped.
+// Block v: the loss of image v from its tiles' partial sums, in a fixed order.
 __global__ void __launch_bounds__(256)
-k_loss_reduce(LossArg la, const float* __restrict__ part, int32_t nb, StepPrep prep) {
+k_loss_reduce(LossArg la, const float* __restrict__ part, int32_t nb) {
   __shared__ double s[2][256];
-  const int v = blockIdx.x, tid = threadIdx.x;
-  if (prep.step && v == 0 && tid == 0) {
-    if (prep.n_inst && (int64_t)prep.n_inst[0] > prep.inst_cap) {
-      prep.skipped[0] += 1u;  // the step's render dropped instances: the step is skipped
-    } else {
-      const int64_t t = prep.step[0] + 1;
-      prep.step[0] = t;
-      prep.bc[0] = (float)(1.0 - pow((double)prep.beta1, (double)t));
-      prep.bc[1] = (float)(1.0 - pow((double)prep.beta2, (double)t));
-    }
-  }
+  const int v = blockIdx.x;
   const int b0 = la.v[v].tile_base;
   const int b1 = v + 1 < la.n ? la.v[v + 1].tile_base : nb;
-  double a = 0.0, c = 0.0;
-  for (int k = b0 + tid; k < b1; k += 256) {
-    a += part[2 * k];
-    c += part[2 * k + 1];
-  }
-  s[0][tid] = a;
-  s[1][tid] = c;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      s[0][tid] += s[0][tid + o];
-      s[1][tid] += s[1][tid + o];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double nn = 3.0 * (double)la.v[v].H * (double)la.v[v].W;
-    la.v[v].loss[0] = (float)((1.0 - la.lambda) * s[1][0] / nn + la.lambda * (1.0 - s[0][0] / nn));
-  }
+  const float L = loss_from_partials(part, b0, b1, la.v[v].H, la.v[v].W, la.lambda, s);
+  if (threadIdx.x == 0) la.v[v].loss[0] = L;
 }
 
 int64_t loss_tiles(int H, int W) { return (int64_t)((W + kTW - 1) / kTW) * ((H + kTH - 1) / kTH); }
 
+hipError_t loss_finish_launch(const ViewsArg& va, const LossFinish& lf, hipStream_t s) {
+  if (!lf.part || va.n <= 0) return hipSuccess;
+  LossArg la{};
+  la.n = va.n;
+  la.lambda = lf.lambda;
+  int64_t nb = 0;
+  for (int v = 0; v < va.n; ++v) {
+    la.v[v].H = va.v[v].H;
+    la.v[v].W = va.v[v].W;
+    la.v[v].loss = lf.loss + v;
+    la.v[v].tile_base = (int32_t)nb;
+    nb += loss_tiles(va.v[v].H, va.v[v].W);
+  }
+  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)la.n), dim3(256), 0, s, la, lf.part, (int32_t)nb);
+  return hipGetLastError();
+}
+
 int64_t loss_temp_floats(int H, int W) { return kPartOffset + 2 * loss_tiles(H, W); }
+
+int64_t loss_part_offset() { return kPartOffset; }
 
 int64_t loss_temp_floats_multi(const LossArg& la) {
   int64_t nb = 0;
@@ -435,7 +437,7 @@ int64_t loss_temp_floats_multi(const LossArg& la) {
 
 // la.v[*].tiles_x and tile_base are filled here. temp holds loss_temp_floats_multi(la)
 // floats (nothing in it needs clearing: the reduction reads only what the tiles wrote).
-hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t s) {
+hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, bool defer_finish, hipStream_t s) {
   const Win win = make_window();
   int64_t nb = 0;
   for (int v = 0; v < la.n; ++v) {
@@ -444,9 +446,10 @@ hipError_t ssim_loss(LossArg la, float* temp, const StepPrep* prep, hipStream_t 
     nb += loss_tiles(la.v[v].H, la.v[v].W);
   }
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ssim_tile, dim3((unsigned)nb), dim3(kThreads), 0, s, win, la, temp + kPartOffset);
-  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)la.n), dim3(256), 0, s, la, temp + kPartOffset, (int32_t)nb,
+  hipLaunchKernelGGL(k_ssim_tile, dim3((unsigned)nb), dim3(kThreads), 0, s, win, la, temp + kPartOffset,
                      prep ? *prep : StepPrep{nullptr, nullptr, 0.f, 0.f, nullptr, 0, nullptr});
+  if (!defer_finish)
+    hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)la.n), dim3(256), 0, s, la, temp + kPartOffset, (int32_t)nb);
   return hipGetLastError();
 }
 

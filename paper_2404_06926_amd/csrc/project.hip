@@ -235,10 +235,22 @@ template <int DEG, bool FUSED, bool MULTI>
 __global__ void __launch_bounds__(256)
 k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg va, float near_z,
               const uint32_t* __restrict__ counts, float4* __restrict__ g2d, const float4* __restrict__ inst_grad,
-              const uint32_t* __restrict__ inst_off, uint8_t* __restrict__ vis, AdamArg ad) {
+              const uint32_t* __restrict__ inst_off, uint8_t* __restrict__ vis, AdamArg ad, LossFinish lf) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float s_gsh[MULTI ? 3 * K : 1][MULTI ? 256 : 1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (FUSED && lf.part && blockIdx.x == 0) {
+    // the step's losses (Eq. 9) from the loss kernel's per-tile sums, in place of a launch
+    // of their own
+    __shared__ double s_loss[2][256];
+    int b0 = 0;
+    for (int v = 0; v < va.n; ++v) {
+      const int b1 = b0 + loss_tiles_of(va.v[v].H, va.v[v].W);
+      const float L = loss_from_partials(lf.part, b0, b1, va.v[v].H, va.v[v].W, lf.lambda, s_loss);
+      if (threadIdx.x == 0) lf.loss[v] = L;
+      b0 = b1;
+    }
+  }
   // a render that dropped its instances (it needed more than the buffers hold) has no
   // gradient: nothing is added, and a fused step is skipped, leaving the map, its moments
   // and the exposures as they are (the same decision for every thread)
@@ -524,24 +536,24 @@ static hipError_t launch_fwd(const float* P, int64_t cap, int32_t N, const Views
 template <int DEG>
 static hipError_t launch_bwd(float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                              const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
-                             uint8_t* vis, const AdamArg* ad, hipStream_t s) {
+                             uint8_t* vis, const AdamArg* ad, const LossFinish& lf, hipStream_t s) {
   const dim3 grid((N + 255) / 256), block(256);
   const float4* ig = (const float4*)inst_grad;
   const AdamArg a = ad ? *ad : AdamArg{};
   if (va.n == 1) {
     if (ad)
       hipLaunchKernelGGL((k_project_bwd<DEG, true, false>), grid, block, 0, s, P, G, cap, N, va, near_z, counts, g2d,
-                         ig, inst_off, vis, a);
+                         ig, inst_off, vis, a, lf);
     else
       hipLaunchKernelGGL((k_project_bwd<DEG, false, false>), grid, block, 0, s, P, G, cap, N, va, near_z, counts,
-                         g2d, ig, inst_off, vis, a);
+                         g2d, ig, inst_off, vis, a, lf);
   } else {
     if (ad)
       hipLaunchKernelGGL((k_project_bwd<DEG, true, true>), grid, block, 0, s, P, G, cap, N, va, near_z, counts, g2d,
-                         ig, inst_off, vis, a);
+                         ig, inst_off, vis, a, lf);
     else
       hipLaunchKernelGGL((k_project_bwd<DEG, false, true>), grid, block, 0, s, P, G, cap, N, va, near_z, counts,
-                         g2d, ig, inst_off, vis, a);
+                         g2d, ig, inst_off, vis, a, lf);
   }
   return hipGetLastError();
 }
@@ -565,19 +577,27 @@ hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, cons
 
 hipError_t project_backward(int deg, float* P, float* G, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
                             const uint32_t* counts, float4* g2d, const float* inst_grad, const uint32_t* inst_off,
-                            uint8_t* vis, const AdamArg* adam, hipStream_t s) {
-  if (N <= 0) {  // no launch: the exposures get the separate update
-    if (!adam || adam->n_exp <= 0) return hipSuccess;
+                            uint8_t* vis, const AdamArg* adam, const LossFinish& lf, hipStream_t s) {
+  if (N <= 0) {  // no projection launch: the losses and the exposures get launches of their own
+    hipError_t e = loss_finish_launch(va, lf, s);
+    if (e != hipSuccess || !adam || adam->n_exp <= 0) return e;
     ExpArg ea{};
     ea.n = adam->n_exp;
-    for (int e = 0; e < ea.n; ++e) ea.p[e] = const_cast<float*>(va.v[e].exposure);
+    for (int x = 0; x < ea.n; ++x) ea.p[x] = const_cast<float*>(va.v[x].exposure);
     return adam_exposures(ea, adam->bc, adam->lr_exp, adam->beta1, adam->beta2, adam->eps, s);
   }
+  // only the fused kernel's first block finishes losses
+  LossFinish lfk = lf;
+  if (!adam) {
+    hipError_t e = loss_finish_launch(va, lf, s);
+    if (e != hipSuccess) return e;
+    lfk = LossFinish{nullptr, nullptr, 0.f, 0};
+  }
   switch (deg) {
-    case 0: return launch_bwd<0>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
-    case 1: return launch_bwd<1>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
-    case 2: return launch_bwd<2>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
-    default: return launch_bwd<3>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, s);
+    case 0: return launch_bwd<0>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, lfk, s);
+    case 1: return launch_bwd<1>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, lfk, s);
+    case 2: return launch_bwd<2>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, lfk, s);
+    default: return launch_bwd<3>(P, G, cap, N, va, near_z, counts, g2d, inst_grad, inst_off, vis, adam, lfk, s);
   }
 }
 

@@ -77,7 +77,6 @@ struct gs_map {
   int64_t* d_step = nullptr;   // Adam step t
   float* d_bc = nullptr;       // bias corrections
   uint32_t* d_ninst = nullptr; // instance count of the last render
-  bool big_n_dirty = false;     // the large-rectangle count (d_ninst[8]) may be nonzero
   uint32_t* d_overflow = nullptr;
   float* d_loss = nullptr;     // loss values of keyframe jobs (64 floats)
   uint32_t* h_pinned = nullptr;
@@ -87,7 +86,7 @@ struct gs_map {
   DevBuf rec, counts, offsets, scan_tmp, g2d, keys[2], vals[2], sort_tmp, ranges, pixT, pixN, loss_tmp;
   DevBuf dkey[2], dval[2];     // depth-sort keys / (view, Gaussian) ids, double-buffered
   DevBuf emit_g, inst_off;     // Gaussian of each emission index; first emission index per pair
-  DevBuf block_start, big_list;  // instance-parallel binning: first pair per block; large-rectangle pairs
+  DevBuf block_start;           // instance-parallel binning: first pair per emission block
   DevBuf split_slot, split_extra, split_state;  // long lists cut into chunks (blend)
   DevBuf inst_grad, exp_part;  // deterministic backward: per-instance gradients, per-tile exposure sums
   DevBuf dbg_g;                // Gaussian index per instance in blend order (inspection only)
@@ -462,7 +461,7 @@ gs_status gs_destroy_map(gs_map* m) {
   DevBuf* bufs[] = {&m->rec, &m->counts, &m->offsets, &m->scan_tmp, &m->g2d, &m->keys[0], &m->keys[1],
                     &m->vals[0], &m->vals[1], &m->sort_tmp, &m->ranges, &m->pixT, &m->pixN, &m->loss_tmp,
                     &m->dkey[0], &m->dkey[1], &m->dval[0], &m->dval[1], &m->emit_g, &m->inst_off,
-                    &m->block_start, &m->big_list, &m->split_slot, &m->split_extra, &m->split_state,
+                    &m->block_start, &m->split_slot, &m->split_extra, &m->split_state,
                     &m->inst_grad, &m->exp_part, &m->dbg_g, &m->gr_rgb, &m->gr_T, &m->gr_flags,
                     &m->gr_off, &m->gr_tmp, &m->gr_d2, &m->ar_rgb, &m->ar_T, &m->ar_nc, &m->ar_dl,
                     &m->pend_xyz, &m->pend_rgb};
@@ -619,7 +618,6 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
     GS_TRY(ensure(m, m->dval[b], (size_t)std::max<int64_t>(vn, 1) * 4, s));
   }
   GS_TRY(ensure(m, m->inst_off, (size_t)std::max<int64_t>(vn, 1) * 4, s));
-  GS_TRY(ensure(m, m->big_list, (size_t)std::max<int64_t>(vn, 1) * 4, s));
   GS_TRY(ensure(m, m->exp_part, (size_t)std::max<int64_t>(tiles, 1) * 12 * 4, s));
   GS_TRY(ensure(m, m->sort_tmp, (size_t)sort_temp_elems(std::max<int64_t>(std::max<int64_t>(vn, m->inst_cap), 1)) * 4,
                 s));
@@ -645,18 +643,12 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint32_t* offsets = (uint32_t*)m->offsets.ptr;
   uint32_t* dkey[2] = {(uint32_t*)m->dkey[0].ptr, (uint32_t*)m->dkey[1].ptr};
   uint32_t* dval[2] = {(uint32_t*)m->dval[0].ptr, (uint32_t*)m->dval[1].ptr};
-  uint32_t* big_n = m->d_ninst + 8;  // count of large-rectangle pairs (word 8 of the counter block)
   {
     StageTimer t(m, s, GS_STAGE_PROJECT);
-    // the tile ranges of every completed render clear the large-rectangle count for the
-    // next one; a render that stopped before them leaves it to be cleared here
-    if (m->big_n_dirty) GS_HIP(fill_u32(big_n, 0u, 1, s));
-    m->big_n_dirty = true;
     // on the side: the pair count the depth sort reads, and the tile ranges (with the split
     // counters after them) zeroed for this render
     const ProjSide side{m->d_nvn, (uint32_t)vn, (uint32_t*)m->ranges.ptr, 2 * tiles + 2};
-    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0],
-                           (uint32_t*)m->big_list.ptr, big_n, side, s));
+    GS_HIP(project_forward(m->deg, params_of(m), m->cap, N, va, m->desc.near_z, rec, counts, dkey[0], side, s));
   }
   int dwhich = 0;
   {
@@ -693,8 +685,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint32_t* vals[2] = {(uint32_t*)m->vals[0].ptr, (uint32_t*)m->vals[1].ptr};
   {
     StageTimer t(m, s, GS_STAGE_DUPLICATE);
-    GS_HIP(duplicate_keys(rec, counts, order, offsets, m->d_ninst, (const uint32_t*)m->big_list.ptr, big_n, N, va,
-                          keys[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr, m->deterministic,
+    GS_HIP(duplicate_keys(rec, counts, order, offsets, m->d_ninst, N, va, keys[0], (uint32_t*)m->emit_g.ptr, (uint32_t*)m->inst_off.ptr, m->deterministic,
                           (uint32_t*)m->block_start.ptr, marked_cap > 0 && marked_cap == m->inst_cap, m->inst_cap,
                           m->d_overflow, s));
   }
@@ -708,8 +699,7 @@ gs_status gs_render(gs_map* m, int32_t nv, const gs_view* views, const gs_frame*
   uint2* ranges = (uint2*)m->ranges.ptr;
   {
     StageTimer t(m, s, GS_STAGE_RANGES);
-    GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, big_n, s));
-    m->big_n_dirty = false;
+    GS_HIP(tile_ranges(keys[which], m->d_ninst, m->inst_cap, ranges, tiles, s));
     m->last_sp = split_arg(m, tiles);
     GS_HIP(split_items(ranges, (int32_t)tiles, m->last_sp, s));
   }

@@ -40,10 +40,8 @@ struct ProjSide {
   uint32_t* zero;
   int64_t n_zero;
 };
-// big_list / big_n (zeroed before): pairs whose tile rectangle exceeds 64 tiles.
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                           float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* big_list,
-                           uint32_t* big_n, const ProjSide& side, hipStream_t s);
+                           float4* rec, uint32_t* counts, uint32_t* dkey, const ProjSide& side, hipStream_t s);
 // With inst_grad != nullptr the 2D gradients are the sums, in emission order, of the
 // instance records [inst_off[vi], inst_off[vi] + counts[vi]); otherwise they come from g2d.
 // With adam != nullptr the Adam update of each row is applied in the same kernel (one step).
@@ -61,16 +59,16 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t
 hipError_t scan_counts(const uint32_t* counts, const uint32_t* order, uint32_t* offsets, int64_t n,
                        uint32_t* temp, uint32_t* total, uint32_t* block_start, int64_t capacity, hipStream_t s);
 // Instances in depth order, one lane per instance (block_start: block_start_elems(capacity)
-// words); pairs listed in big_list (big_n of them) have more than 64 candidate tiles.
+// words); a pair with more than 64 candidate tiles is emitted by one wave.
 // overflow[0] |= 1 when the instances exceed the capacity; overflow[2] = max(overflow[2],
 // instance count).
-// inst_off receives each pair's first emission index for the listed pairs, and for every
-// pair with all_off (the deterministic backward reads it). starts_marked: scan_counts wrote
-// block_start for this capacity; otherwise a launch of its own writes it.
+// With all_off, inst_off receives every pair's first emission index (the deterministic
+// backward reads it). starts_marked: scan_counts wrote block_start for this capacity;
+// otherwise a launch of its own writes it.
 int64_t block_start_elems(int64_t capacity);
 hipError_t duplicate_keys(const float4* rec, const uint32_t* counts, const uint32_t* order, const uint32_t* offsets,
-                          const uint32_t* n_dev, const uint32_t* big_list, const uint32_t* big_n, int32_t N,
-                          const ViewsArg& va, uint32_t* tiles, uint32_t* emit_g, uint32_t* inst_off,
+                          const uint32_t* n_dev, int32_t N, const ViewsArg& va, uint32_t* tiles, uint32_t* emit_g,
+                          uint32_t* inst_off,
                           bool all_off, uint32_t* block_start, bool starts_marked, int64_t capacity,
                           uint32_t* overflow, hipStream_t s);
 hipError_t gather_gaussians(const uint32_t* vals, const uint32_t* emit_g, const uint32_t* n_dev, int64_t cap,
@@ -79,9 +77,8 @@ int64_t sort_temp_elems(int64_t cap);
 // vals_iota: the values are 0, 1, 2, ... and vals[0] is not read.
 hipError_t radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev, int64_t cap, int nbits,
                           uint32_t* temp, int* which, hipStream_t s, bool vals_iota);
-// zero_word (optional): cleared too (the large-rectangle pair count, for the next render).
 hipError_t tile_ranges(const uint32_t* tiles, const uint32_t* n_dev, int64_t cap, uint2* ranges, int64_t n_tiles,
-                       uint32_t* zero_word, hipStream_t s);
+                       hipStream_t s);
 
 // blending (blend.hip)
 // Long tile lists are split into chunks that separate workgroups blend: a tile whose list

@@ -22,8 +22,7 @@ constexpr int kSerialTiles = 16;
 template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
-              float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey,
-              uint32_t* __restrict__ big_list, uint32_t* __restrict__ big_n, ProjSide side) {
+              float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey, ProjSide side) {
   // lanes past the end stay (reading row N - 1) so that the whole wave takes part in the
   // cooperative tile counting below; they write nothing
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,8 +110,6 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     // depth-sort key of the pair: float bits of a positive depth, largest key when unused
     dkey[vi] = cnt ? __float_as_uint(kp.zh) : 0xffffffffu;
     if (cnt == 0) continue;
-    // rectangles past the 64-bit mask are binned by a wave each
-    if ((r[2] - r[0] + 1) * (r[3] - r[1] + 1) > 64) big_list[atomicAdd(big_n, 1u)] = (uint32_t)vi;
     // view-dependent colour: max(0, sum_k sh_k Y_k(dir) + 0.5)
     float dx = m0 - V.campos[0], dy = m1 - V.campos[1], dz = m2 - V.campos[2];
     const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -526,10 +523,9 @@ k_project_bwd(float* P, float* __restrict__ Gp, int64_t cap, int32_t N, ViewsArg
 
 template <int DEG>
 static hipError_t launch_fwd(const float* P, int64_t cap, int32_t N, const ViewsArg& va, float near_z,
-                             float4* rec, uint32_t* counts, uint32_t* dkey, uint32_t* big_list,
-                             uint32_t* big_n, const ProjSide& side, hipStream_t s) {
+                             float4* rec, uint32_t* counts, uint32_t* dkey, const ProjSide& side, hipStream_t s) {
   hipLaunchKernelGGL(k_project_fwd<DEG>, dim3((N + 255) / 256), dim3(256), 0, s, P, cap, N, va,
-                     near_z, rec, counts, dkey, big_list, big_n, side);
+                     near_z, rec, counts, dkey, side);
   return hipGetLastError();
 }
 
@@ -560,7 +556,7 @@ static hipError_t launch_bwd(float* P, float* G, int64_t cap, int32_t N, const V
 
 hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, const ViewsArg& va,
                            float near_z, float4* rec, uint32_t* counts, uint32_t* dkey,
-                           uint32_t* big_list, uint32_t* big_n, const ProjSide& side, hipStream_t s) {
+                           const ProjSide& side, hipStream_t s) {
   if (N <= 0) {  // no projection launch: the side writes get their own
     hipError_t e = hipSuccess;
     if (side.nvn) e = fill_u32(side.nvn, side.nvn_value, 1, s);
@@ -568,10 +564,10 @@ hipError_t project_forward(int deg, const float* P, int64_t cap, int32_t N, cons
     return e;
   }
   switch (deg) {
-    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
-    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
-    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
-    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, big_list, big_n, side, s);
+    case 0: return launch_fwd<0>(P, cap, N, va, near_z, rec, counts, dkey, side, s);
+    case 1: return launch_fwd<1>(P, cap, N, va, near_z, rec, counts, dkey, side, s);
+    case 2: return launch_fwd<2>(P, cap, N, va, near_z, rec, counts, dkey, side, s);
+    default: return launch_fwd<3>(P, cap, N, va, near_z, rec, counts, dkey, side, s);
   }
 }
 

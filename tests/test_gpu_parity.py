@@ -54,6 +54,39 @@ def test_projection_keys_and_sort_bit_exact(name):
     params, deg, cams = case(name)
     print(f"case {name}: N={params.shape[0]} deg={deg} views={len(cams)}", flush=True)
     m, frames = _run_gpu(params, deg, cams)
+    _check_keys(m, params, deg, cams)
+
+
+def test_emission_skips_culled_pairs_with_stale_large_rectangles():
+    # A pair without instances starts where the next one does, and the projection writes no
+    # record for it, so a Gaussian culled since an earlier render keeps that render's record.
+    # Large Gaussians (rectangles of more than 64 tiles, emitted by one wave each) are culled
+    # here after a first render; the second render's keys must still match the oracle's,
+    # the emission taking only the pairs that have instances.
+    torch = torch_mod()
+    params, deg, cams = case("c1")
+    params = params.copy()
+    rng = np.random.default_rng(11)
+    params[rng.choice(params.shape[0], 1000, replace=False), 3:6] += 3.0  # large Gaussians (184 over 64 tiles)
+    print("c1 with 1000 enlarged Gaussians", flush=True)
+    m, _ = _run_gpu(params, deg, cams)
+    dbg = m.debug_last_render()
+    cnt = dbg["counts"][0].cpu().numpy()
+    rect = dbg["proj"][0].cpu().numpy()[:, 12:14].view(np.uint32).astype(np.int64)
+    area = ((rect[:, 1] & 0xFFFF) - (rect[:, 0] & 0xFFFF) + 1) * ((rect[:, 1] >> 16) - (rect[:, 0] >> 16) + 1)
+    large = np.nonzero((cnt > 0) & (area > 64))[0]
+    assert large.size >= 20, large.size
+    culled = large[::2]
+    params[culled, 10] = -12.0  # opacity below 1/255: culled, their records left as they were
+    m.params()[10, torch.tensor(culled, device="cuda")] = -12.0
+    m.render(cams, exposures(cams))
+    torch.cuda.synchronize()
+    print(f"culled {culled.size} of {large.size} large Gaussians", flush=True)
+    _check_keys(m, params, deg, cams)
+    assert (m.debug_last_render()["counts"][0].cpu().numpy()[culled] == 0).all()
+
+
+def _check_keys(m, params, deg, cams):
     dbg = m.debug_last_render()
     views, projs, bins, rend = oracle_forward(params, deg, cams)
     for v, pr in enumerate(projs):

@@ -493,7 +493,14 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
     // keeps its T and last contributor by selection: no per-pixel branches
     const int len = __builtin_amdgcn_readfirstlane(s_len[wid]);
     for (int jj = 0; jj < len; ++jj) {
-      if (__all(all_done())) break;
+      // one comparison per pixel gives both the wave's exit test and the pixel's own
+      bool live[PX], any_live = false;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        live[k] = !(T[k] < 0.0f);
+        any_live = any_live || live[k];
+      }
+      if (!__any(any_live)) break;
       const int j = __builtin_amdgcn_readfirstlane((int)s_list[wid][jj]);
       const float4 a = s_r[j][0];
       const float4 b = s_r[j][1];
@@ -506,18 +513,19 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
         float dx, dy;
         const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc[k], pyc[k], dx, dy);
         const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
-        const bool ok = (PX == 1 || ((m >> pixel_quadrant<PX>(wid, k)) & 1u)) && !(T[k] < 0.0f) &&
+        const bool ok = (PX == 1 || ((m >> pixel_quadrant<PX>(wid, k)) & 1u)) && live[k] &&
                         !(power > 0.0f) && alpha >= kAlphaMin;
         const float Tn = T[k] * (1.0f - alpha);
-        const bool above = !(Tn < kTMin);
-        const bool take = ok && above;
-        const bool stop = ok && !above;
+        const bool below = Tn < kTMin;
+        const bool take = ok && !below;
         const float w = take ? alpha * T[k] : 0.0f;
         C0[k] += b.z * w;
         C1[k] += b.w * w;
         C2[k] += cr.x * w;
         Dm[k] += cr.y * w;  // (kept only where the depth is wanted: one FMA, no select)
-        T[k] = take ? Tn : (stop ? -T[k] : T[k]);
+        // taken: T after the entry; stopping here: done, T kept (as -T)
+        const float Tnext = below ? -T[k] : Tn;
+        T[k] = ok ? Tnext : T[k];
         last[k] = take ? pos1 : last[k];
       }
     }

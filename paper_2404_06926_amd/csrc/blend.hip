@@ -339,10 +339,11 @@ k_blend_trans(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint
   int lx, ly;
   lane_pixel<1>(wid, lane, 0, lx, ly);
   const float pxc = (float)(tx * kTile + lx) + 0.5f, pyc = (float)(ty * kTile + ly) + 0.5f;
-  bool done = !(tx * kTile + lx < V.W && ty * kTile + ly < V.H);
-  float T = 1.0f;
+  // T carries the pixel's state in its sign, as in the forward: a pixel outside the image or
+  // whose product fell below the stop threshold keeps -T
+  float T = (tx * kTile + lx < V.W && ty * kTile + ly < V.H) ? 1.0f : -1.0f;
   for (int base = begin; base < end; base += NT) {
-    if (__syncthreads_count(done) == NT) break;
+    if (__syncthreads_count(T < 0.0f) == NT) break;
     const int kk = base + (int)threadIdx.x;
     uint32_t qm = 0;
     if (kk < end) {
@@ -354,26 +355,26 @@ k_blend_trans(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint
       qm = quadrant_mask(r0, r1, r2.w, tx, ty);
     }
     build_wave_lists<1, NW, NT>(qm, min(NT, end - base), s_list, s_len, s_wc);
-    if (!done) {
-      const int len = s_len[wid];
-      for (int jj = 0; jj < len; ++jj) {
-        const int j = s_list[wid][jj];
-        const float4 a = s_a[j];
-        const float2 b = s_b[j];
-        float dx, dy;
-        const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
-        if (power > 0.0f) continue;
-        const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
-        if (alpha < kAlphaMin) continue;
-        T = T * (1.0f - alpha);
-        if (T < kTMin) {  // every later chunk is dead for this pixel whatever lies in front
-          done = true;
-          break;
-        }
-      }
+    // wave-uniform and branch-free, as the forward's loop: a pixel that does not take an
+    // entry keeps its T by selection
+    const int len = __builtin_amdgcn_readfirstlane(s_len[wid]);
+    for (int jj = 0; jj < len; ++jj) {
+      const bool live = !(T < 0.0f);
+      if (!__any(live)) break;
+      const int j = __builtin_amdgcn_readfirstlane((int)s_list[wid][jj]);
+      const float4 a = s_a[j];
+      const float2 b = s_b[j];
+      float dx, dy;
+      const float power = blend_power2(a.x, a.y, a.z, a.w, b.x, pxc, pyc, dx, dy);
+      const float alpha = fminf(kAlphaMax, b.y * blend_exp2(power));
+      const bool ok = live && !(power > 0.0f) && alpha >= kAlphaMin;
+      const float Tn = T * (1.0f - alpha);
+      // below the threshold every later chunk is dead for this pixel whatever lies in
+      // front: the product so far is kept, marked done
+      T = ok ? (Tn < kTMin ? -Tn : Tn) : T;
     }
   }
-  split_field(sp, slot0 + c, 0)[ly * kTile + lx] = T;
+  split_field(sp, slot0 + c, 0)[ly * kTile + lx] = fabsf(T);
 }
 
 // Items of a render: every tile longer than the chunk length and than `balance` times the

@@ -293,20 +293,8 @@ k_split_merge(ViewsArg va, const uint2* __restrict__ ranges, SplitArg sp) {
   const int q = (int)threadIdx.x;
   const int px = tx * kTile + (q & 15), py = ty * kTile + (q >> 4);
   if (px >= V.W || py >= V.H) return;
-  float c0 = 0.f, c1 = 0.f, c2 = 0.f, d = 0.f, T = 1.0f;
-  uint32_t last = 0;
-  for (int c = 0; c < nch; ++c) {
-    const uint32_t bits = __float_as_uint(split_field(sp, slot0 + c, 6)[q]);
-    if (bits & kDead) break;
-    c0 += split_field(sp, slot0 + c, 1)[q];
-    c1 += split_field(sp, slot0 + c, 2)[q];
-    c2 += split_field(sp, slot0 + c, 3)[q];
-    d += split_field(sp, slot0 + c, 4)[q];
-    T = split_field(sp, slot0 + c, 5)[q];
-    last = max(last, bits & kPosMask);
-    if (bits & kStopped) break;
-  }
-  write_pixel<DEPTH>(V, (int64_t)py * V.W + px, c0, c1, c2, T, last, d);
+  const ChunkSums r = sum_chunks(sp, slot0, 0, nch, q, ChunkSums{0.f, 0.f, 0.f, 0.f, 1.0f, 0u});
+  write_pixel<DEPTH>(V, (int64_t)py * V.W + px, r.c0, r.c1, r.c2, r.T, r.last, r.d);
 }
 
 // Pass 1 of a split tile: block b takes chunk extra[b].y - 1 of tile extra[b].x (every
@@ -655,16 +643,9 @@ k_blend_bwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
       // one the pixel stopped in, then the background, add behind it (normalised)
       const int q = ly * kTile + lx;
       const float Tf = T[k];
-      float r0 = Tf * B0[k], r1 = Tf * B1[k], r2 = Tf * B2[k], rd = 0.f;
-      for (int c = it.c + 1; c < it.nch; ++c) {
-        const uint32_t bits = __float_as_uint(split_field(sp, it.slot0 + c, 6)[q]);
-        if (bits & kDead) break;
-        r0 += split_field(sp, it.slot0 + c, 1)[q];
-        r1 += split_field(sp, it.slot0 + c, 2)[q];
-        r2 += split_field(sp, it.slot0 + c, 3)[q];
-        rd += split_field(sp, it.slot0 + c, 4)[q];
-        if (bits & kStopped) break;
-      }
+      const ChunkSums cs = sum_chunks(sp, it.slot0, it.c + 1, it.nch, q,
+                                      ChunkSums{Tf * B0[k], Tf * B1[k], Tf * B2[k], 0.f, 0.f, 0u});
+      const float r0 = cs.c0, r1 = cs.c1, r2 = cs.c2, rd = cs.d;
       T[k] = split_field(sp, slot, 5)[q];
       // a chunk past the pixel's stop has no contributor there; keep its state finite
       const float inv = T[k] > 0.0f ? 1.0f / T[k] : 0.0f;

@@ -129,14 +129,10 @@ k_blend_bwd_pg(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uin
     float S0 = T * V.bg[0], S1 = T * V.bg[1], S2 = T * V.bg[2];
     if (split && px < V.W && py < V.H) {
       const int q = (py - ty * kTile) * kTile + (px - tx * kTile);
-      for (int c = it.c + 1; c < it.nch; ++c) {
-        const uint32_t bits = __float_as_uint(split_field(sp, it.slot0 + c, 6)[q]);
-        if (bits & kDead) break;
-        S0 += split_field(sp, it.slot0 + c, 1)[q];
-        S1 += split_field(sp, it.slot0 + c, 2)[q];
-        S2 += split_field(sp, it.slot0 + c, 3)[q];
-        if (bits & kStopped) break;
-      }
+      const ChunkSums cs = sum_chunks(sp, it.slot0, it.c + 1, it.nch, q, ChunkSums{S0, S1, S2, 0.f, 0.f, 0u});
+      S0 = cs.c0;
+      S1 = cs.c1;
+      S2 = cs.c2;
       T = split_field(sp, it.slot0 + it.c, 5)[q];
     }
     s_T[ps] = T;

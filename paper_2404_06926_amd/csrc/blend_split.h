@@ -23,6 +23,50 @@ __device__ __forceinline__ float* split_field(const SplitArg& sp, uint32_t slot,
   return sp.state + ((size_t)slot * kSplitFields + f) * (kTile * kTile);
 }
 
+// What the chunks c0, c0 + 1, ... of a split tile add at pixel q onto `acc`, in chunk order,
+// up to the chunk the pixel stopped in and before a chunk it was dead for: the colour and
+// depth sums, the transmittance after the last chunk taken and the largest
+// last-contributor position.
+// The state is read four chunks at a time, all loads issued before the first is used
+// (a chunk-by-chunk walk waits one memory round trip per chunk); the sums still add chunk
+// by chunk, so the result is the walk's.
+struct ChunkSums {
+  float c0, c1, c2, d, T;
+  uint32_t last;
+};
+__device__ inline ChunkSums sum_chunks(const SplitArg& sp, uint32_t slot0, int c0, int nch, int q, ChunkSums acc) {
+  ChunkSums r = acc;
+  bool go = true;
+  for (int cb = c0; cb < nch && go; cb += 4) {
+    uint32_t bits[4];
+    float f[4][5];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      bits[u] = kDead;
+      if (cb + u < nch) {
+        const uint32_t s = slot0 + (uint32_t)(cb + u);
+        bits[u] = __float_as_uint(split_field(sp, s, 6)[q]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) f[u][k] = split_field(sp, s, 1 + k)[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (go && (bits[u] & kDead)) go = false;
+      if (go) {
+        r.c0 += f[u][0];
+        r.c1 += f[u][1];
+        r.c2 += f[u][2];
+        r.d += f[u][3];
+        r.T = f[u][4];
+        r.last = max(r.last, bits[u] & kPosMask);
+        if (bits[u] & kStopped) go = false;
+      }
+    }
+  }
+  return r;
+}
+
 // Chunk length for a render with n_inst instances (par > 0).
 __device__ __forceinline__ uint32_t chunk_len(uint32_t n_inst, int32_t par, int32_t min_len) {
   const uint32_t L = max((n_inst + (uint32_t)par - 1u) / (uint32_t)par, (uint32_t)min_len);

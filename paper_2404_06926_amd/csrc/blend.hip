@@ -418,9 +418,9 @@ k_blend_fwd(ViewsArg va, const float4* __restrict__ rec, int32_t N, const uint32
   const int tile = it.tile;
   const bool split = it.slot0 != kNoSlot;
   const uint32_t slot = it.slot0 + (uint32_t)it.c;
-  // a split tile always carries depth: a backward through the depth map needs the depth
-  // seen behind each chunk, whether or not this render outputs the map
-  const bool want_d = DEPTH || split;
+  // the depth sum is always accumulated (one FMA): a split tile carries it in its chunk
+  // state whether or not this render outputs the map, since a backward through the depth
+  // map needs the depth seen behind each chunk
   const int v = view_of_tile(va, tile);
   const ViewDev& V = va.v[v];
   const int lt = tile - V.tile_base;

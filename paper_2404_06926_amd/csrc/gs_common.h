@@ -285,59 +285,6 @@ __device__ __forceinline__ bool key_tile_hit(float mx, float my, float A, float 
   return qmin <= thr;
 }
 
-// The tile predicate split into the parts a column and a row of tiles share: a column's
-// x-side edge offset and division by C are the same for all its tiles, a row's y-side edge
-// offset and division by A likewise, so a rectangle of w x h tiles needs w + h divisions
-// instead of up to 2 w h. The operations and their order are key_tile_hit's, so the result
-// is the same bit for bit.
-struct TileSide {
-  float lo, hi;  // pixel-centre extent of the tile along this axis, relative to the mean
-  float d;       // offset from the mean to the nearer edge (used when out)
-  float q;       // the other coordinate's unclamped minimiser on that edge (when out)
-  bool out;      // the mean lies outside the extent
-};
-
-__device__ __forceinline__ TileSide tile_side(float m, float B, float div, int t) {
-#pragma clang fp contract(off)
-  const float e0 = (float)(16 * t) + 0.5f, e1 = (float)(16 * t) + 15.5f;
-  TileSide sd;
-  sd.lo = e0 - m;
-  sd.hi = e1 - m;
-  sd.out = !(m >= e0 && m <= e1);
-  sd.d = ((m < e0) ? e0 : e1) - m;
-  sd.q = (m < e0 || m > e1) ? __fdiv_rn(-(B * sd.d), div) : 0.0f;
-  return sd;
-}
-
-// column tx (divides by C) and row ty (divides by A)
-__device__ __forceinline__ TileSide tile_col(float mx, float B, float C, int tx) { return tile_side(mx, B, C, tx); }
-__device__ __forceinline__ TileSide tile_row(float my, float A, float B, int ty) { return tile_side(my, B, A, ty); }
-
-__device__ __forceinline__ bool tile_hit_sides(float A, float B, float C, float thr, const TileSide& c,
-                                               const TileSide& r) {
-#pragma clang fp contract(off)
-  if (!c.out && !r.out) return true;
-  const float B2 = B + B;
-  float qmin = __builtin_huge_valf();
-  if (c.out) {  // on the x-side edge
-    const float dx = c.d;
-    float dy = c.q;
-    dy = (dy < r.lo) ? r.lo : dy;
-    dy = (r.hi < dy) ? r.hi : dy;
-    const float q = ((A * (dx * dx)) + (B2 * (dx * dy))) + (C * (dy * dy));
-    qmin = (q < qmin) ? q : qmin;
-  }
-  if (r.out) {  // on the y-side edge
-    const float dy = r.d;
-    float dx = r.q;
-    dx = (dx < c.lo) ? c.lo : dx;
-    dx = (c.hi < dx) ? c.hi : dx;
-    const float q = ((A * (dx * dx)) + (B2 * (dx * dy))) + (C * (dy * dy));
-    qmin = (q < qmin) ? q : qmin;
-  }
-  return qmin <= thr;
-}
-
 // ---------------------------------------------------------------------------------
 // Blend arithmetic shared by the forward and the backward passes. Every blend kernel must
 // take the same skip decisions, so the exponent is formed in one fixed sequence of

@@ -16,9 +16,10 @@
 
 namespace gs {
 
-// Rectangles of up to this many candidate tiles are tested by their own lane.
-constexpr int kSerialTiles = 16;
-
+// Tile tests of a wave: the tests of all its rectangles of up to 64 tiles (the hit mask's
+// width) are laid end to end, 64 (pair, tile) tests per step, so that the work per step
+// does not depend on how unevenly the rectangle sizes fall over the lanes; larger
+// rectangles are walked by the whole wave one at a time.
 template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
@@ -48,42 +49,47 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     uint64_t hits = 0;  // passing tiles in row-major rectangle order (rectangles of <= 64 tiles)
     int area = 0;
     if (valid && kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) area = (r[2] - r[0] + 1) * (r[3] - r[1] + 1);
-    if (area > 0 && area <= kSerialTiles) {
-      // the shorter side of the rectangle (at most 4 tiles, as w h <= 16) is prepared once,
-      // the longer one walked: w + h divisions in all
-      const int w = r[2] - r[0] + 1, h = r[3] - r[1] + 1;
-      TileSide sd[4];
-      if (h <= 4) {
+    // rectangles of up to 64 tiles: the tests of all of them in one list (lane order, each
+    // rectangle row-major), 64 per step; the lane that owns a test is found by a binary
+    // search of the list's running ends
+    {
+      const int lane = (int)(threadIdx.x & 63);
+      const int a = area <= 64 ? area : 0;
+      int end = a;  // inclusive running sum: this lane's tests end before `end`
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (j < h) sd[j] = tile_row(kp.my, kp.A, kp.B, r[1] + j);
-        for (int i = 0; i < w; ++i) {
-          const TileSide c = tile_col(kp.mx, kp.B, kp.C, r[0] + i);
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(end, o, 64);
+        if (lane >= o) end += t;
+      }
+      const int beg = end - a;
+      const int total = __shfl(end, 63, 64);
+      for (int base = 0; base < total; base += 64) {  // wave-uniform
+        const int j = base + lane;
+        int own = 0;  // lanes whose tests all come before test j
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (j < h && tile_hit_sides(kp.A, kp.B, kp.C, kp.thr, c, sd[j])) {
-              ++cnt;
-              hits |= 1ull << (j * w + i);
-            }
-        }
-      } else {  // w <= 4
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < w) sd[i] = tile_col(kp.mx, kp.B, kp.C, r[0] + i);
-        for (int j = 0; j < h; ++j) {
-          const TileSide row = tile_row(kp.my, kp.A, kp.B, r[1] + j);
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (i < w && tile_hit_sides(kp.A, kp.B, kp.C, kp.thr, sd[i], row)) {
-              ++cnt;
-              hits |= 1ull << (j * w + i);
-            }
+        for (int step = 32; step >= 1; step >>= 1)
+          if (__shfl(end, own + step - 1, 64) <= j) own += step;
+        const int t = j - __shfl(beg, own, 64);
+        const float mx = __shfl(kp.mx, own, 64), my = __shfl(kp.my, own, 64), A = __shfl(kp.A, own, 64);
+        const float B = __shfl(kp.B, own, 64), C = __shfl(kp.C, own, 64), thr = __shfl(kp.thr, own, 64);
+        const int x0 = __shfl(r[0], own, 64), y0 = __shfl(r[1], own, 64), rw = __shfl(r[2], own, 64) - x0 + 1;
+        // t < 64 and rw <= 64: the quotient t / rw exactly (as in the emission)
+        const int qy = (int)fmaf((float)t, __builtin_amdgcn_rcpf((float)rw), 1.0f / 128.0f);
+        const bool hit = j < total && key_tile_hit(mx, my, A, B, C, thr, x0 + (t - qy * rw), y0 + qy);
+        const uint64_t m = __ballot(hit);
+        // this lane's tests in the step: list positions [lo, hi), mask bits lo - beg on
+        const int lo = max(beg, base), hi = min(end, base + 64);
+        if (lo < hi) {
+          const int n = hi - lo;
+          const uint64_t seg = (m >> (lo - base)) & (n == 64 ? ~0ull : ((1ull << n) - 1ull));
+          hits |= seg << (lo - beg);
         }
       }
+      if (a > 0) cnt = (uint32_t)__popcll(hits);
     }
     // larger rectangles: the whole wave evaluates one lane's rectangle, 64 tiles per step,
     // so no lane loops over hundreds of tiles while the others wait
-    uint64_t todo = __ballot(area > kSerialTiles);
+    uint64_t todo = __ballot(area > 64);
     while (todo) {
       const int src = __ffsll((long long)todo) - 1;
       todo &= todo - 1;

@@ -16,6 +16,15 @@
 
 namespace gs {
 
+// Orders a wave's LDS accesses on either side (a wave executes its LDS instructions in
+// order; the fences keep the compiler from moving accesses across and make it wait for
+// the earlier ones).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Tile tests of a wave: the tests of all its rectangles of up to 64 tiles (the hit mask's
 // width) are laid end to end, 64 (pair, tile) tests per step, so that the work per step
 // does not depend on how unevenly the rectangle sizes fall over the lanes; larger
@@ -24,6 +33,7 @@ template <int DEG>
 __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
               float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey, ProjSide side) {
+  __shared__ uint8_t s_own[4][64];  // per wave: the lane whose tile tests start at each position
   // lanes past the end stay (reading row N - 1) so that the whole wave takes part in the
   // cooperative tile counting below; they write nothing
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,10 +60,12 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
     int area = 0;
     if (valid && kp.visible && key_rect(kp, V.tiles_x, V.tiles_y, r)) area = (r[2] - r[0] + 1) * (r[3] - r[1] + 1);
     // rectangles of up to 64 tiles: the tests of all of them in one list (lane order, each
-    // rectangle row-major), 64 per step; the lane that owns a test is found by a binary
-    // search of the list's running ends
+    // rectangle row-major), 64 per step. In each step the lanes whose tests start in it
+    // mark their start position in the wave's LDS row; a test's owner is the mark at or
+    // before it, else the owner carried over from the step before.
     {
       const int lane = (int)(threadIdx.x & 63);
+      uint8_t* const own_row = s_own[threadIdx.x >> 6];
       const int a = area <= 64 ? area : 0;
       int end = a;  // inclusive running sum: this lane's tests end before `end`
 #pragma unroll
@@ -62,13 +74,20 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
         if (lane >= o) end += t;
       }
       const int beg = end - a;
-      const int total = __shfl(end, 63, 64);
+      const int total = __builtin_amdgcn_readfirstlane(__shfl(end, 63, 64));
+      const uint64_t upto = ~0ull >> (63 - lane);  // lanes 0 .. lane
+      int carry = 0;
       for (int base = 0; base < total; base += 64) {  // wave-uniform
         const int j = base + lane;
-        int own = 0;  // lanes whose tests all come before test j
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-          if (__shfl(end, own + step - 1, 64) <= j) own += step;
+        own_row[lane] = 0xff;
+        wave_lds_sync();
+        if (a > 0 && beg >= base && beg < base + 64) own_row[beg - base] = (uint8_t)lane;
+        wave_lds_sync();
+        const int mark = own_row[lane];
+        const uint64_t before = __ballot(mark != 0xff) & upto;
+        const int own = before ? __shfl(mark, 63 - __clzll((long long)before), 64) : carry;
+        carry = __builtin_amdgcn_readlane(own, 63);
+        wave_lds_sync();  // the row is rewritten in the next step
         const int t = j - __shfl(beg, own, 64);
         const float mx = __shfl(kp.mx, own, 64), my = __shfl(kp.my, own, 64), A = __shfl(kp.A, own, 64);
         const float B = __shfl(kp.B, own, 64), C = __shfl(kp.C, own, 64), thr = __shfl(kp.thr, own, 64);

@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(256)
 k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, float near_z,
               float4* __restrict__ rec, uint32_t* __restrict__ counts, uint32_t* __restrict__ dkey, ProjSide side) {
   __shared__ uint8_t s_own[4][64];  // per wave: the lane whose tile tests start at each position
+  __shared__ float4 s_pair[4][64][2];  // per wave and lane: conic, mean, threshold, rectangle
   // lanes past the end stay (reading row N - 1) so that the whole wave takes part in the
   // cooperative tile counting below; they write nothing
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,6 +77,11 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
       const int beg = end - a;
       const int total = __builtin_amdgcn_readfirstlane(__shfl(end, 63, 64));
       const uint64_t upto = ~0ull >> (63 - lane);  // lanes 0 .. lane
+      // the lane's pair as its tests need it, read by the lanes that test it
+      s_pair[threadIdx.x >> 6][lane][0] = make_float4(kp.mx, kp.my, kp.A, kp.B);
+      s_pair[threadIdx.x >> 6][lane][1] =
+          make_float4(kp.C, kp.thr, __uint_as_float((uint32_t)r[0] | ((uint32_t)r[1] << 16)),
+                      __uint_as_float((uint32_t)beg | ((uint32_t)(r[2] - r[0] + 1) << 16)));
       int carry = 0;
       for (int base = 0; base < total; base += 64) {  // wave-uniform
         const int j = base + lane;
@@ -88,10 +94,11 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
         const int own = before ? __shfl(mark, 63 - __clzll((long long)before), 64) : carry;
         carry = __builtin_amdgcn_readlane(own, 63);
         wave_lds_sync();  // the row is rewritten in the next step
-        const int t = j - __shfl(beg, own, 64);
-        const float mx = __shfl(kp.mx, own, 64), my = __shfl(kp.my, own, 64), A = __shfl(kp.A, own, 64);
-        const float B = __shfl(kp.B, own, 64), C = __shfl(kp.C, own, 64), thr = __shfl(kp.thr, own, 64);
-        const int x0 = __shfl(r[0], own, 64), y0 = __shfl(r[1], own, 64), rw = __shfl(r[2], own, 64) - x0 + 1;
+        const float4 p0 = s_pair[threadIdx.x >> 6][own][0], p1 = s_pair[threadIdx.x >> 6][own][1];
+        const float mx = p0.x, my = p0.y, A = p0.z, B = p0.w, C = p1.x, thr = p1.y;
+        const uint32_t xy = __float_as_uint(p1.z), bw = __float_as_uint(p1.w);
+        const int x0 = (int)(xy & 0xffffu), y0 = (int)(xy >> 16), rw = (int)(bw >> 16);
+        const int t = j - (int)(bw & 0xffffu);
         // t < 64 and rw <= 64: the quotient t / rw exactly (as in the emission)
         const int qy = (int)fmaf((float)t, __builtin_amdgcn_rcpf((float)rw), 1.0f / 128.0f);
         const bool hit = j < total && key_tile_hit(mx, my, A, B, C, thr, x0 + (t - qy * rw), y0 + qy);
@@ -105,6 +112,7 @@ k_project_fwd(const float* __restrict__ P, int64_t cap, int32_t N, ViewsArg va, 
         }
       }
       if (a > 0) cnt = (uint32_t)__popcll(hits);
+      wave_lds_sync();  // the pair row is rewritten for the next view
     }
     // larger rectangles: the whole wave evaluates one lane's rectangle, 64 tiles per step,
     // so no lane loops over hundreds of tiles while the others wait

@@ -57,6 +57,30 @@ def test_projection_keys_and_sort_bit_exact(name):
     _check_keys(m, params, deg, cams)
 
 
+def test_tile_counts_over_every_rectangle_size():
+    # The projection lays the tile tests of all of a wave's rectangles of up to 64 tiles end
+    # to end, 64 per step, and walks larger ones with the whole wave. Log-scales spread over
+    # four units put rectangles of 1 tile up to the whole 16 x 12-tile image side by side in
+    # each wave (on the CPU: 2285 of one tile, 6360 of 2-16, 1199 of 17-64, 156 over 64), so
+    # waves' lists span many steps and rectangles' tests cross step boundaries; counts,
+    # records and keys must still equal the oracle's bit for bit.
+    params, deg, cams = case("c1")
+    params = params.copy()
+    rng = np.random.default_rng(12)
+    params[:, 3:6] += rng.uniform(-1.0, 3.0, size=(params.shape[0], 1))
+    print("c1 with log-scales spread over [-1, 3]", flush=True)
+    m, _ = _run_gpu(params, deg, cams)
+    dbg = m.debug_last_render()
+    cnt = dbg["counts"][0].cpu().numpy()
+    rect = dbg["proj"][0].cpu().numpy()[:, 12:14].view(np.uint32).astype(np.int64)
+    area = ((rect[:, 1] & 0xFFFF) - (rect[:, 0] & 0xFFFF) + 1) * ((rect[:, 1] >> 16) - (rect[:, 0] >> 16) + 1)
+    area = area[cnt > 0]
+    print(f"rectangles: {area.size}, of 1: {(area == 1).sum()}, 2-16: {((area > 1) & (area <= 16)).sum()}, "
+          f"17-64: {((area > 16) & (area <= 64)).sum()}, over 64: {(area > 64).sum()}", flush=True)
+    assert (area == 1).sum() > 100 and ((area > 16) & (area <= 64)).sum() > 100 and (area > 64).sum() > 100
+    _check_keys(m, params, deg, cams)
+
+
 def test_emission_skips_culled_pairs_with_stale_large_rectangles():
     # A pair without instances starts where the next one does, and the projection writes no
     # record for it, so a Gaussian culled since an earlier render keeps that render's record.
